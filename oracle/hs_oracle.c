@@ -1,0 +1,1225 @@
+/*
+ * hs_oracle.c -- plain FP64 CPU oracle of the per-time-step particle update of the hybrid
+ * SP-Shakhov / DSMC method (Jin, Liu, Yang, Cao, Zhuo, Zhong; arXiv 2506.23917).
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the GPU path is checked against.  It is written
+ * straight from the paper (Sec. 2.1 DSMC, Sec. 2.2 SP-Shakhov, Sec. 3.1 coupling,
+ * Sec. 3.2 Steps 1-6) and from the readings of the paper recorded next to it; it shares
+ * no code with the GPU path.  Slow and simple on purpose: one case at a time, one cell at
+ * a time, one particle at a time, in array order, all in IEEE double.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC'11), keyed by the case seed, counter = (entity low 32 bits,
+ * entity high 28 bits | stream << 28, step, draw).  Streams: 0 particle (entity = id),
+ * 1 cell, 2 inflow face, 3 initialisation (entity = cell).
+ */
+#include "hs_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KB 1.380649e-23               /* Boltzmann constant, J/K                        */
+#define PI 3.14159265358979323846
+#define MAX_BOUNCE 8                  /* body reflections per particle per step          */
+#define MAX_AR 64                     /* Shakhov acceptance-rejection attempts           */
+#define MAX_INJ_AR 64                 /* inflow normal-speed attempts                    */
+#define MAX_POS_TRY 64                /* initial-position attempts in a cut cell         */
+#define SUB 16                        /* sub-cells per axis for cut-cell volumes         */
+
+enum { ST_PARTICLE = 0, ST_CELL = 1, ST_FACE = 2, ST_INIT = 3 };
+enum { DRAW_RELAX = 0, DRAW_AR = 1, DRAW_BOUNCE = 200, DRAW_INJ_TIME = 300 };
+
+typedef struct {
+    int32_t cell;      /* boundary cell, case-local */
+    int32_t side;      /* 0..5 = -x,+x,-y,+y,-z,+z */
+    double lambda;     /* expected number of entering particles per step */
+} face_t;
+
+typedef struct {
+    hso_case p;
+    double *region_box;
+    hso_state *region_state;
+    double *dt_over_tau;
+    int64_t ncells;
+    double *vol, *sigc_max, *acc, *dt_cell;
+    int64_t n_samples;
+    int64_t np, cap;
+    double *x, *v;
+    int32_t *cell;
+    int64_t *id;
+    int64_t next_id, step;
+    int64_t nfaces;
+    face_t *faces;
+    hso_trace *trace;
+    hso_counters cnt;
+    /* sort scratch */
+    double *x2, *v2;
+    int32_t *cell2;
+    int64_t *id2;
+    int64_t *count;
+} ocase;
+
+struct hso_sim {
+    hso_gas gas;
+    int n_cases;
+    ocase *cases;
+    int trace_on;
+    int failed;
+};
+
+/* ------------------------------------------------------------------------------------ */
+/* Random numbers                                                                        */
+/* ------------------------------------------------------------------------------------ */
+
+/* Philox4x32 with 10 rounds, as defined in Salmon et al. (SC'11): each round multiplies
+ * counter words 0 and 2 by two fixed odd constants, and the high halves are mixed with
+ * the other two words and the round key; the key is bumped by the golden-ratio and
+ * sqrt(3)-1 Weyl constants between rounds. */
+void hso_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void hso_draw(uint64_t seed, uint32_t stream, uint64_t entity, uint32_t step,
+              uint32_t draw, uint32_t out[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = (uint32_t)(entity & 0xffffffffu);
+    ctr[1] = (uint32_t)((entity >> 32) & 0x0fffffffu) | (stream << 28);
+    ctr[2] = step;
+    ctr[3] = draw;
+    key[0] = (uint32_t)(seed & 0xffffffffu);
+    key[1] = (uint32_t)(seed >> 32);
+    hso_philox4x32_10(ctr, key, out);
+}
+
+/* A 32-bit word as a uniform number in the open interval (0,1): (w + 1/2) / 2^32. */
+double hso_uniform(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+/* A 32-bit word as a uniform integer in [0, n): floor(w * n / 2^32). */
+uint32_t hso_index(uint32_t w, uint32_t n) { return (uint32_t)(((uint64_t)w * n) >> 32); }
+
+/* ------------------------------------------------------------------------------------ */
+/* Gas model (Sec. 4 opening paragraph, Eq. 33; Sec. 2.2 for tau = mu / p)                */
+/* ------------------------------------------------------------------------------------ */
+
+/* VHS total cross-section times relative speed (Bird's VHS model, the paper's gas model
+ * of Sec. 4): sigma_T = pi d_ref^2 (2 k T_ref / (m_r c_r^2))^(omega-1/2) / Gamma(5/2-omega)
+ * with reduced mass m_r = m/2, so sigma_T c_r = K c_r^(2-2 omega). */
+static double vhs_K(const hso_gas *g)
+{
+    return PI * g->d_ref * g->d_ref * pow(4.0 * KB * g->T_ref / g->m, g->omega - 0.5)
+           / tgamma(2.5 - g->omega);
+}
+
+double hso_sigma_c(const hso_gas *g, double cr)
+{
+    return vhs_K(g) * pow(cr, 2.0 - 2.0 * g->omega);
+}
+
+/* Power-law viscosity with the VHS exponent omega (Sec. 4). */
+double hso_viscosity(const hso_gas *g, double T)
+{
+    return g->mu_ref * pow(T / g->T_ref, g->omega);
+}
+
+/* VHS mean free path, Eq. 33. */
+double hso_mean_free_path(const hso_gas *g, double n, double T)
+{
+    return 1.0 / (sqrt(2.0) * PI * g->d_ref * g->d_ref * n * pow(g->T_ref / T, g->omega - 0.5));
+}
+
+/* One-way number flux of a drifting Maxwellian through a face with inward unit normal
+ * nrm: n (exp(-s^2) + sqrt(pi) s (1 + erf s)) / (2 beta sqrt(pi)), beta = 1/sqrt(2RT),
+ * s = beta U.nrm.  (Inflow boundaries are not described in the paper; this is the
+ * standard kinetic-theory flux used to feed freestream boundaries.) */
+double hso_inflow_number_flux(const hso_gas *g, const hso_state *st, const double nrm[3])
+{
+    double R = KB / g->m;
+    double beta = 1.0 / sqrt(2.0 * R * st->T);
+    double s = beta * (st->u[0] * nrm[0] + st->u[1] * nrm[1] + st->u[2] * nrm[2]);
+    return st->n * (exp(-s * s) + sqrt(PI) * s * (1.0 + erf(s))) / (2.0 * beta * sqrt(PI));
+}
+
+/* Flux-weighted normal speed z = beta c_n > 0, density proportional to
+ * z exp(-(z - s)^2), with s = beta U.n the inward drift in thermal units.  Exact
+ * acceptance-rejection; each attempt consumes 4 words.
+ *  s >= 0: envelope |y| exp(-y^2) [y > -s] + s exp(-y^2), y = z - s, which dominates
+ *     (y + s) exp(-y^2) [y > -s].  The first part (mass 1 - exp(-s^2)/2) is sampled
+ *     exactly (Rayleigh for y > 0, truncated Rayleigh on (-s, 0)); the second is the
+ *     full Gaussian of mass s sqrt(pi), whose draws below -s are rejected.  Keep with
+ *     probability (y + s) / (|y| + s).
+ *  -3/4 < s < 0: envelope z exp(-z^2) exp(-s^2) (since 2 z s <= 0); z = sqrt(-ln u),
+ *     keep with probability exp(2 z s).
+ *  s <= -3/4: envelope z exp(-2 |s| z - s^2) (dropping z^2), a Gamma(2, 2|s|) draw,
+ *     keep with probability exp(-z^2). */
+double hso_sample_normal_speed(double s, const uint32_t *w, int n_attempts, int *used)
+{
+    double z = 0.0;
+    if (s >= 0.0) {
+        double e = exp(-s * s);
+        double Ma = 1.0 - 0.5 * e;
+        double Mb = s * sqrt(PI);
+        double pa = Ma / (Ma + Mb);
+        z = s > 0.0 ? s : 1.0;
+        for (int a = 0; a < n_attempts; ++a) {
+            double u0 = hso_uniform(w[4 * a + 0]);
+            double u1 = hso_uniform(w[4 * a + 1]);
+            double u2 = hso_uniform(w[4 * a + 2]);
+            double u3 = hso_uniform(w[4 * a + 3]);
+            double y;
+            if (u0 < pa) {
+                if (u1 * Ma < 0.5)
+                    y = sqrt(-log(u2));
+                else
+                    y = -sqrt(-log(1.0 - u2 * (1.0 - e)));
+            } else {
+                y = sqrt(-log(u1)) * cos(2.0 * PI * u2);
+                if (y <= -s) continue;
+            }
+            double zz = y + s;
+            if (zz <= 0.0) continue;
+            z = zz;
+            if (u3 * (fabs(y) + s) < zz) {
+                *used = a + 1;
+                return zz;
+            }
+        }
+    } else if (s > -0.75) {
+        for (int a = 0; a < n_attempts; ++a) {
+            double zz = sqrt(-log(hso_uniform(w[4 * a + 0])));
+            z = zz;
+            if (hso_uniform(w[4 * a + 3]) < exp(2.0 * zz * s)) {
+                *used = a + 1;
+                return zz;
+            }
+        }
+    } else {
+        for (int a = 0; a < n_attempts; ++a) {
+            double zz = -(log(hso_uniform(w[4 * a + 0])) + log(hso_uniform(w[4 * a + 1]))) / (-2.0 * s);
+            z = zz;
+            if (hso_uniform(w[4 * a + 3]) < exp(-zz * zz)) {
+                *used = a + 1;
+                return zz;
+            }
+        }
+    }
+    *used = -n_attempts;
+    return z;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Geometry                                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+static int64_t ncells_of(const hso_case *c)
+{
+    if (c->dim == 0) return c->nx;
+    int64_t n = c->nx;
+    if (c->dim >= 2) n *= c->ny;
+    if (c->dim >= 3) n *= c->nz;
+    return n;
+}
+
+static void cell_ijk(const hso_case *c, int64_t k, int64_t ijk[3])
+{
+    ijk[0] = ijk[1] = ijk[2] = 0;
+    if (c->dim == 0) { ijk[0] = k; return; }
+    ijk[0] = k % c->nx;
+    if (c->dim >= 2) ijk[1] = (k / c->nx) % c->ny;
+    if (c->dim >= 3) ijk[2] = k / ((int64_t)c->nx * c->ny);
+}
+
+static int body_axes(const hso_case *c)
+{
+    return c->body == HSO_BODY_SPHERE ? 3 : 2;
+}
+
+/* Is an absolute point strictly inside the body?  (distance^2 < R^2, summed x, y, z) */
+static int inside_body(const hso_case *c, const double x[3])
+{
+    if (c->body == HSO_BODY_NONE) return 0;
+    int na = body_axes(c);
+    double d2 = 0.0;
+    for (int a = 0; a < na; ++a) {
+        double d = x[a] - c->body_c[a];
+        d2 = d2 + d * d;
+    }
+    return d2 < c->body_r * c->body_r;
+}
+
+/* Cut-cell volume rule: count the 16^dim sub-cell centres
+ * lo + (i + (s + 1/2)/16) h that lie outside the body.  Cells whose nearest point is
+ * clearly outside (or farthest corner clearly inside) are classified without sampling;
+ * the margin makes that exact-equivalent to sampling. */
+int64_t hso_cut_count(const hso_case *c, int i, int j, int k)
+{
+    int dim = c->dim;
+    int64_t full = 1;
+    for (int a = 0; a < dim; ++a) full *= SUB;
+    if (c->body == HSO_BODY_NONE || dim == 0) return full;
+    int64_t ijk[3] = { i, j, k };
+    int na = body_axes(c);
+    double near2 = 0.0, far2 = 0.0;
+    for (int a = 0; a < na; ++a) {
+        double blo = c->lo[a] + (double)ijk[a] * c->h[a];
+        double bhi = c->lo[a] + (double)(ijk[a] + 1) * c->h[a];
+        double dn = 0.0;
+        if (c->body_c[a] < blo) dn = blo - c->body_c[a];
+        else if (c->body_c[a] > bhi) dn = c->body_c[a] - bhi;
+        double df = fabs(blo - c->body_c[a]);
+        if (fabs(bhi - c->body_c[a]) > df) df = fabs(bhi - c->body_c[a]);
+        near2 = near2 + dn * dn;
+        far2 = far2 + df * df;
+    }
+    double R2 = c->body_r * c->body_r;
+    if (near2 > R2 * (1.0 + 1e-9)) return full;
+    if (far2 < R2 * (1.0 - 1e-9)) return 0;
+    int64_t out = 0;
+    int s2max = dim >= 3 ? SUB : 1;
+    int s1max = dim >= 2 ? SUB : 1;
+    for (int s2 = 0; s2 < s2max; ++s2)
+        for (int s1 = 0; s1 < s1max; ++s1)
+            for (int s0 = 0; s0 < SUB; ++s0) {
+                int sub[3] = { s0, s1, s2 };
+                double p[3] = { 0.0, 0.0, 0.0 };
+                for (int a = 0; a < dim; ++a)
+                    p[a] = c->lo[a] + ((double)ijk[a] + ((double)sub[a] + 0.5) / SUB) * c->h[a];
+                if (!inside_body(c, p)) ++out;
+            }
+    return out;
+}
+
+static double cell_volume(const hso_case *c, int64_t k)
+{
+    double full = c->h[0] * c->h[1] * c->h[2];
+    if (c->dim == 0 || c->body == HSO_BODY_NONE) return full;
+    int64_t ijk[3];
+    cell_ijk(c, k, ijk);
+    int64_t tot = 1;
+    for (int a = 0; a < c->dim; ++a) tot *= SUB;
+    int64_t out = hso_cut_count(c, (int)ijk[0], (int)ijk[1], (int)ijk[2]);
+    return (double)out / (double)tot * full;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Maxwellian sampling, Eq. 17                                                           */
+/* ------------------------------------------------------------------------------------ */
+
+/* Thermal velocity from four uniforms R1..R4 exactly as Eq. 17 writes it. */
+static void maxwell_eq17(double T, double R, const uint32_t w[4], double C[3])
+{
+    double a = sqrt(2.0 * R * T);
+    double r1 = hso_uniform(w[0]), r2 = hso_uniform(w[1]);
+    double r3 = hso_uniform(w[2]), r4 = hso_uniform(w[3]);
+    C[0] = a * cos(2.0 * PI * r1) * sqrt(-log(r2));
+    C[1] = a * cos(2.0 * PI * r3) * sqrt(-log(r4));
+    C[2] = a * sin(2.0 * PI * r3) * sqrt(-log(r4));
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Creation / destruction                                                                */
+/* ------------------------------------------------------------------------------------ */
+
+static int validate_case(const hso_case *c)
+{
+    if (c->dim < 0 || c->dim > 3) return HSO_EARG;
+    if (c->nx <= 0 || (c->dim >= 2 && c->ny <= 0) || (c->dim >= 3 && c->nz <= 0)) return HSO_EARG;
+    for (int a = 0; a < 3; ++a) if (!(c->h[a] > 0.0)) return HSO_EARG;
+    if (!(c->F_N > 0.0) || !(c->T_sigma > 0.0)) return HSO_EARG;
+    if (c->capacity < 0) return HSO_EARG;
+    if (c->dim == 0) {
+        if (!c->dt_over_tau || c->n_regions < 1 || !c->region_state) return HSO_EARG;
+    } else if (!(c->dt_G > 0.0)) return HSO_EARG;
+    if (c->body != HSO_BODY_NONE) {
+        if (c->body == HSO_BODY_CYLINDER && c->dim < 2) return HSO_EARG;
+        if (c->body == HSO_BODY_SPHERE && c->dim < 3) return HSO_EARG;
+        if (!(c->body_r > 0.0) || !(c->body_T > 0.0)) return HSO_EARG;
+        for (int s = 0; s < 2 * c->dim; ++s) if (c->bc[s] == HSO_BC_SPECULAR) return HSO_EARG;
+        for (int a = 0; a < body_axes(c); ++a) {
+            double n_a = a == 0 ? c->nx : a == 1 ? c->ny : c->nz;
+            if (c->body_c[a] - c->body_r <= c->lo[a]) return HSO_EARG;
+            if (c->body_c[a] + c->body_r >= c->lo[a] + n_a * c->h[a]) return HSO_EARG;
+        }
+    }
+    return HSO_OK;
+}
+
+static void free_case(ocase *c)
+{
+    free(c->region_box); free(c->region_state); free(c->dt_over_tau);
+    free(c->vol); free(c->sigc_max); free(c->acc); free(c->dt_cell);
+    free(c->x); free(c->v); free(c->cell); free(c->id);
+    free(c->x2); free(c->v2); free(c->cell2); free(c->id2); free(c->count);
+    free(c->faces); free(c->trace);
+}
+
+static int alloc_particles(ocase *c, int64_t cap)
+{
+    size_t n = (size_t)(cap > 0 ? cap : 1);
+    c->x = calloc(3 * n, sizeof(double));  c->v = calloc(3 * n, sizeof(double));
+    c->cell = calloc(n, sizeof(int32_t));  c->id = calloc(n, sizeof(int64_t));
+    c->x2 = calloc(3 * n, sizeof(double)); c->v2 = calloc(3 * n, sizeof(double));
+    c->cell2 = calloc(n, sizeof(int32_t)); c->id2 = calloc(n, sizeof(int64_t));
+    if (!c->x || !c->v || !c->cell || !c->id || !c->x2 || !c->v2 || !c->cell2 || !c->id2)
+        return HSO_ECAP;
+    return HSO_OK;
+}
+
+/* Inflow faces, in the order: side -x,+x,-y,+y,-z,+z; within a side the boundary cells in
+ * x-fastest order.  A face is an inflow face if its side is HSO_BC_INFLOW and its centre
+ * lies inside the slot box on every tangential axis where slot_hi > slot_lo. */
+static int build_faces(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    oc->nfaces = 0;
+    if (c->dim == 0) return HSO_OK;
+    int64_t n[3] = { c->nx, c->dim >= 2 ? c->ny : 1, c->dim >= 3 ? c->nz : 1 };
+    int64_t maxf = 0;
+    for (int s = 0; s < 2 * c->dim; ++s) {
+        int a = s / 2;
+        maxf += ncells_of(c) / n[a];
+    }
+    oc->faces = calloc((size_t)(maxf > 0 ? maxf : 1), sizeof(face_t));
+    if (!oc->faces) return HSO_ECAP;
+    for (int s = 0; s < 2 * c->dim; ++s) {
+        if (c->bc[s] != HSO_BC_INFLOW) continue;
+        int a = s / 2;
+        double nrm[3] = { 0.0, 0.0, 0.0 };
+        nrm[a] = (s % 2 == 0) ? 1.0 : -1.0;
+        double flux = hso_inflow_number_flux(g, &c->inflow, nrm);
+        double area = 1.0;
+        for (int t = 0; t < 3; ++t) if (t != a) area *= c->h[t];
+        double lam = flux * area * c->dt_G / c->F_N;
+        for (int64_t k = 0; k < ncells_of(c); ++k) {
+            int64_t ijk[3];
+            cell_ijk(c, k, ijk);
+            if (ijk[a] != ((s % 2 == 0) ? 0 : n[a] - 1)) continue;
+            int ok = 1;
+            for (int t = 0; t < c->dim; ++t) {
+                if (t == a || !(c->slot_hi[t] > c->slot_lo[t])) continue;
+                double ctr = c->lo[t] + ((double)ijk[t] + 0.5) * c->h[t];
+                if (!(ctr >= c->slot_lo[t] && ctr < c->slot_hi[t])) ok = 0;
+            }
+            if (!ok) continue;
+            face_t *f = &oc->faces[oc->nfaces++];
+            f->cell = (int32_t)k;
+            f->side = s;
+            f->lambda = lam;
+        }
+    }
+    return HSO_OK;
+}
+
+int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace,
+               hso_sim **out)
+{
+    if (!gas || !cases || n_cases <= 0 || !out) return HSO_EARG;
+    if (!(gas->m > 0.0) || !(gas->d_ref > 0.0) || !(gas->T_ref > 0.0) || !(gas->mu_ref > 0.0))
+        return HSO_EARG;
+    for (int i = 0; i < n_cases; ++i) {
+        int e = validate_case(&cases[i]);
+        if (e) return e;
+        for (int j = 0; j < i; ++j)
+            if (cases[j].seed == cases[i].seed) return HSO_EARG;
+    }
+    hso_sim *s = calloc(1, sizeof(hso_sim));
+    if (!s) return HSO_ECAP;
+    s->gas = *gas;
+    s->n_cases = n_cases;
+    s->trace_on = trace;
+    s->cases = calloc((size_t)n_cases, sizeof(ocase));
+    if (!s->cases) { free(s); return HSO_ECAP; }
+    for (int ci = 0; ci < n_cases; ++ci) {
+        ocase *oc = &s->cases[ci];
+        oc->p = cases[ci];
+        const hso_case *c = &cases[ci];
+        int e = HSO_OK;
+        if (c->n_regions > 0) {
+            oc->region_box = malloc(sizeof(double) * 6 * (size_t)c->n_regions);
+            oc->region_state = malloc(sizeof(hso_state) * (size_t)c->n_regions);
+            if (c->region_box) memcpy(oc->region_box, c->region_box, sizeof(double) * 6 * (size_t)c->n_regions);
+            else memset(oc->region_box, 0, sizeof(double) * 6 * (size_t)c->n_regions);
+            memcpy(oc->region_state, c->region_state, sizeof(hso_state) * (size_t)c->n_regions);
+        }
+        oc->p.region_box = oc->region_box;
+        oc->p.region_state = oc->region_state;
+        oc->ncells = ncells_of(c);
+        int64_t nc = oc->ncells;
+        if (c->dim == 0) {
+            oc->dt_over_tau = malloc(sizeof(double) * (size_t)nc);
+            memcpy(oc->dt_over_tau, c->dt_over_tau, sizeof(double) * (size_t)nc);
+        }
+        oc->p.dt_over_tau = oc->dt_over_tau;
+        oc->vol = calloc((size_t)nc, sizeof(double));
+        oc->sigc_max = calloc((size_t)nc, sizeof(double));
+        oc->acc = calloc((size_t)nc * 13, sizeof(double));
+        oc->dt_cell = calloc((size_t)nc, sizeof(double));
+        oc->count = calloc((size_t)nc + 1, sizeof(int64_t));
+        oc->trace = calloc((size_t)nc, sizeof(hso_trace));
+        if (!oc->vol || !oc->sigc_max || !oc->acc || !oc->dt_cell || !oc->count || !oc->trace)
+            e = HSO_ECAP;
+        if (!e) e = alloc_particles(oc, c->capacity);
+        if (!e) e = build_faces(gas, oc);
+        if (e) { hso_destroy(s); return e; }
+        oc->cap = c->capacity;
+        /* initial (sigma_T c_r)_max: the VHS value at c* = 10 sqrt(k T_sigma / m) */
+        double sc0 = hso_sigma_c(gas, 10.0 * sqrt(KB * c->T_sigma / gas->m));
+        for (int64_t k = 0; k < nc; ++k) {
+            oc->vol[k] = cell_volume(c, k);
+            oc->sigc_max[k] = sc0;
+            if (c->dim == 0) {
+                /* 0-D: the observation step equals the cell's own step r_k tau_0, with
+                 * tau_0 = mu(T_0) / (n_0 k T_0) of the nominal state (Eq. 10's tau) */
+                const hso_state *st = &c->region_state[0];
+                double tau0 = hso_viscosity(gas, st->T) / (st->n * KB * st->T);
+                oc->dt_cell[k] = c->dt_over_tau[k] * tau0;
+            } else {
+                oc->dt_cell[k] = c->dt_G;
+            }
+        }
+    }
+    *out = s;
+    return HSO_OK;
+}
+
+void hso_destroy(hso_sim *s)
+{
+    if (!s) return;
+    for (int i = 0; i < s->n_cases; ++i) free_case(&s->cases[i]);
+    free(s->cases);
+    free(s);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Step (1): initialisation                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+static const hso_state *region_of(const hso_case *c, int64_t k)
+{
+    if (c->n_regions <= 0) return NULL;
+    if (c->dim == 0) return &c->region_state[0];
+    int64_t ijk[3];
+    cell_ijk(c, k, ijk);
+    for (int r = 0; r < c->n_regions; ++r) {
+        const double *b = &c->region_box[6 * r];
+        int in = 1;
+        for (int a = 0; a < c->dim; ++a) {
+            double ctr = c->lo[a] + ((double)ijk[a] + 0.5) * c->h[a];
+            if (!(ctr >= b[a] && ctr < b[3 + a])) in = 0;
+        }
+        if (in) return &c->region_state[r];
+    }
+    return NULL;
+}
+
+/* Step (1): particles uniformly at random inside each cell's fluid part, velocities
+ * U + C with C from Eq. 17.  N_k = floor(n V_k / F_N + u). Ids run in cell order. */
+static int init_case(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    double R = KB / g->m;
+    oc->np = 0;
+    oc->next_id = 0;
+    oc->step = 0;
+    oc->n_samples = 0;
+    memset(&oc->cnt, 0, sizeof(oc->cnt));
+    memset(oc->acc, 0, sizeof(double) * 13 * (size_t)oc->ncells);
+    for (int64_t k = 0; k < oc->ncells; ++k) {
+        const hso_state *st = region_of(c, k);
+        if (!st || oc->vol[k] <= 0.0 || st->n <= 0.0) continue;
+        uint32_t w[4];
+        hso_draw(c->seed, ST_INIT, (uint64_t)k, 0, 0, w);
+        int64_t N = (int64_t)floor(st->n * oc->vol[k] / c->F_N + hso_uniform(w[0]));
+        if (oc->np + N > oc->cap) return HSO_ECAP;
+        int64_t ijk[3];
+        cell_ijk(c, k, ijk);
+        for (int64_t q = 0; q < N; ++q) {
+            int64_t i = oc->np++;
+            double *x = &oc->x[3 * i];
+            x[0] = x[1] = x[2] = 0.0;
+            if (c->dim > 0) {
+                int placed = 0;
+                for (int t = 0; t < MAX_POS_TRY && !placed; ++t) {
+                    hso_draw(c->seed, ST_INIT, (uint64_t)k, 0, (uint32_t)(1 + 128 * q + t), w);
+                    for (int a = 0; a < c->dim; ++a)
+                        x[a] = c->lo[a] + ((double)ijk[a] + hso_uniform(w[a])) * c->h[a];
+                    placed = !inside_body(c, x);
+                }
+                if (!placed) {
+                    /* centre of the first sub-cell (x-fastest) that lies outside the body */
+                    int s2max = c->dim >= 3 ? SUB : 1, s1max = c->dim >= 2 ? SUB : 1;
+                    for (int s2 = 0; s2 < s2max && !placed; ++s2)
+                        for (int s1 = 0; s1 < s1max && !placed; ++s1)
+                            for (int s0 = 0; s0 < SUB && !placed; ++s0) {
+                                int sub[3] = { s0, s1, s2 };
+                                for (int a = 0; a < c->dim; ++a)
+                                    x[a] = c->lo[a] + ((double)ijk[a] + ((double)sub[a] + 0.5) / SUB) * c->h[a];
+                                placed = !inside_body(c, x);
+                            }
+                }
+            }
+            hso_draw(c->seed, ST_INIT, (uint64_t)k, 0, (uint32_t)(1 + 128 * q + 64), w);
+            double C[3];
+            maxwell_eq17(st->T, R, w, C);
+            for (int a = 0; a < 3; ++a) oc->v[3 * i + a] = st->u[a] + C[a];
+            oc->cell[i] = (int32_t)k;
+            oc->id[i] = oc->next_id++;
+        }
+    }
+    double sc0 = hso_sigma_c(g, 10.0 * sqrt(KB * c->T_sigma / g->m));
+    for (int64_t k = 0; k < oc->ncells; ++k) oc->sigc_max[k] = sc0;
+    return HSO_OK;
+}
+
+int hso_init_particles(hso_sim *s)
+{
+    if (!s) return HSO_EARG;
+    for (int i = 0; i < s->n_cases; ++i) {
+        int e = init_case(&s->gas, &s->cases[i]);
+        if (e) { s->failed = e; return e; }
+    }
+    return HSO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Step (2): inflow injection and free transport with walls                              */
+/* ------------------------------------------------------------------------------------ */
+
+/* Enter new particles through every inflow face (reading: freestream boundaries are fed
+ * by the one-way Maxwellian flux; the paper only states that particles leaving the
+ * domain are removed).  Count floor(lambda_f + u); each entering particle is placed
+ * uniformly on the face, with a flux-weighted normal speed, Gaussian tangential speeds
+ * (Eq. 17 form) and a fresh id; it then moves for a uniform fraction of the step. */
+static int inject(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    int64_t n[3] = { c->nx, c->dim >= 2 ? c->ny : 1, c->dim >= 3 ? c->nz : 1 };
+    double beta = 1.0 / sqrt(2.0 * R * c->inflow.T);
+    for (int64_t f = 0; f < oc->nfaces; ++f) {
+        const face_t *fc = &oc->faces[f];
+        uint32_t w[4];
+        hso_draw(c->seed, ST_FACE, (uint64_t)f, st, 0, w);
+        int64_t nf = (int64_t)floor(fc->lambda + hso_uniform(w[0]));
+        int a = fc->side / 2;
+        double sg = (fc->side % 2 == 0) ? 1.0 : -1.0;
+        int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        int64_t ijk[3];
+        cell_ijk(c, fc->cell, ijk);
+        double sn = sg * c->inflow.u[a] * beta;
+        for (int64_t q = 0; q < nf; ++q) {
+            if (oc->np >= oc->cap) return HSO_ECAP;
+            int64_t i = oc->np++;
+            double *x = &oc->x[3 * i], *v = &oc->v[3 * i];
+            uint32_t base = (uint32_t)(1 + 128 * q);
+            hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base, w);
+            x[0] = x[1] = x[2] = 0.0;
+            for (int t = 0; t < c->dim; ++t) {
+                if (t == a) continue;
+                double frac = hso_uniform(t == t1 ? w[0] : w[1]);
+                x[t] = c->lo[t] + ((double)ijk[t] + frac) * c->h[t];
+            }
+            x[a] = (fc->side % 2 == 0) ? c->lo[a] : c->lo[a] + (double)n[a] * c->h[a];
+            hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 1, w);
+            double at = sqrt(2.0 * R * c->inflow.T);
+            double rr = sqrt(-log(hso_uniform(w[1])));
+            v[t1] = c->inflow.u[t1] + at * cos(2.0 * PI * hso_uniform(w[0])) * rr;
+            v[t2] = c->inflow.u[t2] + at * sin(2.0 * PI * hso_uniform(w[0])) * rr;
+            uint32_t ws[4 * MAX_INJ_AR];
+            for (int att = 0; att < MAX_INJ_AR; ++att)
+                hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 2 + (uint32_t)att, &ws[4 * att]);
+            int used;
+            double z = hso_sample_normal_speed(sn, ws, MAX_INJ_AR, &used);
+            if (used < 0) oc->cnt.inject_cap++;
+            v[a] = sg * z / beta;
+            oc->cell[i] = fc->cell;
+            oc->id[i] = oc->next_id++;
+            oc->cnt.injected++;
+        }
+    }
+    return HSO_OK;
+}
+
+/* Time at which the straight path x + c t first meets the body surface, or -1.
+ * Cylinder (axis z): x, y components; sphere: x, y, z.  Hit when the start is not
+ * inside (q >= 0), the path approaches (b < 0) and the root q / (-b + sqrt(b^2 - a q))
+ * does not exceed t. */
+static double body_hit(const hso_case *c, const double x[3], const double v[3], double t)
+{
+    int na = body_axes(c);
+    double a = 0.0, b = 0.0, q = 0.0;
+    for (int k = 0; k < na; ++k) {
+        double d = x[k] - c->body_c[k];
+        a = a + v[k] * v[k];
+        b = b + d * v[k];
+        q = q + d * d;
+    }
+    q = q - c->body_r * c->body_r;
+    if (!(a > 0.0) || q < 0.0 || b >= 0.0) return -1.0;
+    double disc = b * b - a * q;
+    if (disc < 0.0) return -1.0;
+    double th = q / (-b + sqrt(disc));
+    return th <= t ? th : -1.0;
+}
+
+/* Diffuse reflection with full accommodation at T_w (Step (2), Eq. 30, read with
+ * c_n = sqrt(2 R T_w) sqrt(-ln R1): the printed "cos" is spurious); tangential speeds in
+ * the Eq. 17 (y, z) form.  Tangent frame: cylinder t1 = (-n_y, n_x, 0), t2 = z; sphere
+ * t1 = normalise(e x n) with e the axis of smallest |n_e| (first on ties), t2 = n x t1. */
+static void diffuse_reflect(const hso_case *c, double R, const double xh[3], const uint32_t w[4],
+                            double v[3])
+{
+    double nrm[3] = { 0.0, 0.0, 0.0 }, t1[3] = { 0.0, 0.0, 0.0 }, t2[3] = { 0.0, 0.0, 0.0 };
+    int na = body_axes(c);
+    double len = 0.0;
+    for (int k = 0; k < na; ++k) { nrm[k] = xh[k] - c->body_c[k]; len = len + nrm[k] * nrm[k]; }
+    len = sqrt(len);
+    for (int k = 0; k < na; ++k) nrm[k] = nrm[k] / len;
+    if (c->body == HSO_BODY_CYLINDER) {
+        t1[0] = -nrm[1]; t1[1] = nrm[0];
+        t2[2] = 1.0;
+    } else {
+        int e = 0;
+        if (fabs(nrm[1]) < fabs(nrm[e])) e = 1;
+        if (fabs(nrm[2]) < fabs(nrm[e])) e = 2;
+        double ev[3] = { 0.0, 0.0, 0.0 };
+        ev[e] = 1.0;
+        t1[0] = ev[1] * nrm[2] - ev[2] * nrm[1];
+        t1[1] = ev[2] * nrm[0] - ev[0] * nrm[2];
+        t1[2] = ev[0] * nrm[1] - ev[1] * nrm[0];
+        double l1 = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+        for (int k = 0; k < 3; ++k) t1[k] = t1[k] / l1;
+        t2[0] = nrm[1] * t1[2] - nrm[2] * t1[1];
+        t2[1] = nrm[2] * t1[0] - nrm[0] * t1[2];
+        t2[2] = nrm[0] * t1[1] - nrm[1] * t1[0];
+    }
+    double a = sqrt(2.0 * R * c->body_T);
+    double cn = a * sqrt(-log(hso_uniform(w[0])));
+    double rr = sqrt(-log(hso_uniform(w[2])));
+    double cs = a * cos(2.0 * PI * hso_uniform(w[1])) * rr;
+    double ct = a * sin(2.0 * PI * hso_uniform(w[1])) * rr;
+    for (int k = 0; k < 3; ++k) v[k] = cn * nrm[k] + cs * t1[k] + ct * t2[k];
+}
+
+/* Free transport, Eq. 4: x <- x + c t, with the body's diffuse wall, specular domain
+ * walls, and removal through open faces (Step (2)).  Returns the new case-local cell, or
+ * -1 when the particle has left the domain. */
+static int32_t move_particle(const hso_gas *g, ocase *oc, double *x, double *v, int64_t id,
+                             double t)
+{
+    const hso_case *c = &oc->p;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    if (c->body != HSO_BODY_NONE) {
+        for (int b = 0;; ++b) {
+            double th = body_hit(c, x, v, t);
+            if (th < 0.0) break;
+            for (int k = 0; k < c->dim; ++k) x[k] = x[k] + v[k] * th;
+            t = t - th;
+            oc->cnt.wall_hits++;
+            if (b == MAX_BOUNCE) { oc->cnt.bounce_cap++; t = 0.0; break; }
+            uint32_t w[4];
+            hso_draw(c->seed, ST_PARTICLE, (uint64_t)id, st, (uint32_t)(DRAW_BOUNCE + b), w);
+            diffuse_reflect(c, R, x, w, v);
+        }
+    }
+    for (int k = 0; k < c->dim; ++k) x[k] = x[k] + v[k] * t;
+    int64_t n[3] = { c->nx, c->ny, c->nz };
+    int64_t idx[3] = { 0, 0, 0 };
+    for (int k = 0; k < c->dim; ++k) {
+        double hi = c->lo[k] + (double)n[k] * c->h[k];
+        if (x[k] < c->lo[k]) {
+            if (c->bc[2 * k] != HSO_BC_SPECULAR) return -1;
+            x[k] = 2.0 * c->lo[k] - x[k];
+            v[k] = -v[k];
+        } else if (x[k] >= hi) {
+            if (c->bc[2 * k + 1] != HSO_BC_SPECULAR) return -1;
+            x[k] = 2.0 * hi - x[k];
+            v[k] = -v[k];
+        }
+        int64_t i = (int64_t)floor((x[k] - c->lo[k]) / c->h[k]);
+        if (i < 0) i = 0;
+        if (i > n[k] - 1) i = n[k] - 1;
+        idx[k] = i;
+    }
+    return (int32_t)(idx[0] + (int64_t)c->nx * (idx[1] + (int64_t)c->ny * idx[2]));
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Step (3): index particles into cells (stable counting sort)                            */
+/* ------------------------------------------------------------------------------------ */
+
+static void sort_by_cell(ocase *oc)
+{
+    int64_t nc = oc->ncells;
+    memset(oc->count, 0, sizeof(int64_t) * (size_t)(nc + 1));
+    for (int64_t i = 0; i < oc->np; ++i)
+        if (oc->cell[i] >= 0) oc->count[oc->cell[i]]++;
+    int64_t run = 0;
+    for (int64_t k = 0; k < nc; ++k) { int64_t t = oc->count[k]; oc->count[k] = run; run += t; }
+    oc->count[nc] = run;
+    int64_t removed = 0;
+    for (int64_t i = 0; i < oc->np; ++i) {
+        int32_t k = oc->cell[i];
+        if (k < 0) { ++removed; continue; }
+        int64_t d = oc->count[k]++;
+        memcpy(&oc->x2[3 * d], &oc->x[3 * i], 3 * sizeof(double));
+        memcpy(&oc->v2[3 * d], &oc->v[3 * i], 3 * sizeof(double));
+        oc->cell2[d] = k;
+        oc->id2[d] = oc->id[i];
+    }
+    oc->cnt.removed += removed;
+    double *tx = oc->x; oc->x = oc->x2; oc->x2 = tx;
+    double *tv = oc->v; oc->v = oc->v2; oc->v2 = tv;
+    int32_t *tc = oc->cell; oc->cell = oc->cell2; oc->cell2 = tc;
+    int64_t *ti = oc->id; oc->id = oc->id2; oc->id2 = ti;
+    oc->np = run;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Step (3) moments, Step (4) collisions                                                 */
+/* ------------------------------------------------------------------------------------ */
+
+/* Unbiased estimators of Step (3): U = mean c; T = m sum|C|^2 / (3 k (N-1));
+ * Q = n N / ((N-1)(N-2)) sum (1/2) m |C|^2 C with n = N F_N / V (the printed prefactor
+ * 1/V is read as the number density n, the third-central-moment k-statistic factor). */
+int hso_cell_moments(const hso_gas *g, int64_t N, const double *v, double F_N, double vol,
+                     double U[3], double *T, double Q[3])
+{
+    U[0] = U[1] = U[2] = 0.0; Q[0] = Q[1] = Q[2] = 0.0; *T = 0.0;
+    if (N < 1) return HSO_OK;
+    for (int64_t i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) U[a] = U[a] + v[3 * i + a];
+    for (int a = 0; a < 3; ++a) U[a] = U[a] / (double)N;
+    if (N < 2) return HSO_OK;
+    double s2 = 0.0, s3[3] = { 0.0, 0.0, 0.0 };
+    for (int64_t i = 0; i < N; ++i) {
+        double C[3], c2 = 0.0;
+        for (int a = 0; a < 3; ++a) { C[a] = v[3 * i + a] - U[a]; c2 = c2 + C[a] * C[a]; }
+        s2 = s2 + c2;
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] + c2 * C[a];
+    }
+    *T = g->m * s2 / (3.0 * KB * (double)(N - 1));
+    if (N >= 3 && vol > 0.0) {
+        double n = (double)N * F_N / vol;
+        double f = n * (double)N / ((double)(N - 1) * (double)(N - 2));
+        for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * g->m * s3[a];
+    }
+    return HSO_OK;
+}
+
+/* Eq. 27-28: with local observation step dt_c and relaxation time tau, the global step
+ * dt_G is narrowed proportionally: DSMC gets dt_G (dt_c <= tau) or (tau/dt_c) dt_G, the
+ * Shakhov relaxation gets the rest. */
+void hso_split(double dt_c, double tau, double dt_G, double *dt_dsmc, double *dt_sbgk)
+{
+    if (dt_c <= tau) {
+        *dt_dsmc = dt_G;
+        *dt_sbgk = 0.0;
+    } else {
+        *dt_dsmc = (tau / dt_c) * dt_G;
+        *dt_sbgk = dt_G - *dt_dsmc;
+    }
+}
+
+/* Eq. 17-18: draw C from the Maxwellian, weight A = 1 + (1-Pr) Q.C/(5 p R T)
+ * (C^2/(R T) - 5) (the standard Shakhov polynomial; the printed C^2/(2RT) is read as a
+ * typo), accept when A / A_max > R5, else draw again.  After n_attempts rejections the
+ * last draw is kept (return value negative). */
+int hso_shakhov_sample(const hso_gas *g, double T, double p, const double Q[3], double a_max,
+                       const uint32_t *w, int n_attempts, double C[3])
+{
+    double R = KB / g->m;
+    double RT = R * T;
+    for (int a = 0; a < n_attempts; ++a) {
+        maxwell_eq17(T, R, &w[5 * a], C);
+        double c2 = C[0] * C[0] + C[1] * C[1] + C[2] * C[2];
+        double qc = Q[0] * C[0] + Q[1] * C[1] + Q[2] * C[2];
+        double A = 1.0 + (1.0 - g->Pr) * qc / (5.0 * p * RT) * (c2 / RT - 5.0);
+        if (A / a_max > hso_uniform(w[5 * a + 4])) return a + 1;
+    }
+    return -n_attempts;
+}
+
+static void sums4(const double *v, int64_t N, double out[4])
+{
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int a = 0; a < 3; ++a) out[a] = out[a] + v[3 * i + a];
+        out[3] = out[3] + v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+    }
+}
+
+/* Step (4) for one cell: moments, time split, NTC DSMC sub-step (Eq. 5-9), SP-Shakhov
+ * sub-step (Eq. 16-18), conservation rescale (Eq. 19); then Step (5) sampling. */
+static void collide_cell(const hso_gas *g, ocase *oc, int64_t k, int64_t s0, int64_t N,
+                         int trace_on)
+{
+    const hso_case *c = &oc->p;
+    uint32_t st = (uint32_t)oc->step;
+    double *v = &oc->v[3 * s0];
+    const int64_t *ids = &oc->id[s0];
+    double vol = oc->vol[k];
+    double R = KB / g->m;
+    hso_trace tr;
+    memset(&tr, 0, sizeof(tr));
+    tr.n = N;
+    if (trace_on) sums4(v, N, tr.pre_sum);
+
+    double U[3], T, Q[3];
+    hso_cell_moments(g, N, v, c->F_N, vol, U, &T, Q);
+    int active = N >= 2 && T > 0.0 && vol > 0.0;
+    if (!active && N >= 2) oc->cnt.skipped_cells++;
+    if (active) {
+        double n = (double)N * c->F_N / vol;
+        double p = n * KB * T;
+        double tau = hso_viscosity(g, T) / p;
+        double dtG = oc->dt_cell[k];
+        double dtc;
+        if (c->dim == 0) {
+            dtc = dtG;
+        } else {
+            /* Eq. 25 with L_cell = the cell's minimum edge */
+            double L = c->h[0];
+            for (int a = 1; a < c->dim; ++a) if (c->h[a] < L) L = c->h[a];
+            double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+            dtc = L / (um + sqrt(g->gamma * R * T));
+        }
+        double dtD, dtS;
+        hso_split(dtc, tau, dtG, &dtD, &dtS);
+        double p_relax = -expm1(-dtS / tau);             /* Eq. 16 */
+        tr.T = T; tr.tau = tau; tr.dt_dsmc = dtD; tr.p_relax = p_relax;
+
+        /* NTC (Eq. 5-6): N_col = floor(M + u) candidates; (sigma c)_max is held fixed
+         * during the step and raised afterwards to the largest value seen. */
+        double scmax = oc->sigc_max[k];
+        double M = 0.5 * (double)N * (double)(N - 1) * c->F_N * scmax * dtD / vol;
+        uint32_t w[4];
+        hso_draw(c->seed, ST_CELL, (uint64_t)k, st, 0, w);
+        int64_t ncol = (int64_t)floor(M + hso_uniform(w[0]));
+        double obs = 0.0;
+        for (int64_t kk = 0; kk < ncol; ++kk) {
+            hso_draw(c->seed, ST_CELL, (uint64_t)k, st, (uint32_t)(1 + 2 * kk), w);
+            uint32_t i = hso_index(w[0], (uint32_t)N);
+            uint32_t j = hso_index(w[1], (uint32_t)(N - 1));
+            if (j >= i) ++j;
+            double ua = hso_uniform(w[2]);
+            double *ci = &v[3 * i], *cj = &v[3 * j];
+            double gx = ci[0] - cj[0], gy = ci[1] - cj[1], gz = ci[2] - cj[2];
+            double cr = sqrt(gx * gx + gy * gy + gz * gz);
+            double sc = hso_sigma_c(g, cr);
+            if (sc > obs) obs = sc;
+            if (ua < sc / scmax) {
+                /* Eq. 7-9: isotropic VHS scattering */
+                hso_draw(c->seed, ST_CELL, (uint64_t)k, st, (uint32_t)(2 + 2 * kk), w);
+                double cchi = 2.0 * hso_uniform(w[0]) - 1.0;
+                double schi = sqrt(1.0 - cchi * cchi);
+                double th = 2.0 * PI * hso_uniform(w[1]);
+                double om[3] = { cchi, schi * cos(th), schi * sin(th) };
+                for (int a = 0; a < 3; ++a) {
+                    double sum = ci[a] + cj[a];
+                    ci[a] = 0.5 * (sum - cr * om[a]);
+                    cj[a] = 0.5 * (sum + cr * om[a]);
+                }
+                tr.nacc++;
+                tr.acc_hash ^= (uint64_t)(kk + 1) * 0x9E3779B97F4A7C15ull;
+            }
+        }
+        tr.ncol = ncol;
+        if (obs > oc->sigc_max[k]) oc->sigc_max[k] = obs;
+        oc->cnt.candidates += ncol;
+        oc->cnt.accepted += tr.nacc;
+
+        /* SP-Shakhov (Eq. 16-18): each particle independently relaxes with probability
+         * P = 1 - exp(-dt_sbgk / tau) to a draw from g^S built from the Step (3) moments */
+        double a_max = 1.0;
+        if (p_relax > 0.0) {
+            double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+            a_max = 1.0 + 20.0 * (1.0 - g->Pr) * qm / (p * sqrt(R * T));
+            tr.a_max = a_max;
+            uint32_t ws[5 * MAX_AR];
+            for (int64_t q = 0; q < N; ++q) {
+                hso_draw(c->seed, ST_PARTICLE, (uint64_t)ids[q], st, DRAW_RELAX, w);
+                if (!(hso_uniform(w[0]) < p_relax)) continue;
+                tr.nrelax++;
+                for (int a = 0; a < MAX_AR; ++a) {
+                    uint32_t w2[4];
+                    hso_draw(c->seed, ST_PARTICLE, (uint64_t)ids[q], st, (uint32_t)(DRAW_AR + 2 * a), w2);
+                    memcpy(&ws[5 * a], w2, 4 * sizeof(uint32_t));
+                    hso_draw(c->seed, ST_PARTICLE, (uint64_t)ids[q], st, (uint32_t)(DRAW_AR + 2 * a + 1), w2);
+                    ws[5 * a + 4] = w2[0];
+                }
+                double C[3];
+                int used = hso_shakhov_sample(g, T, p, Q, a_max, ws, MAX_AR, C);
+                if (used < 0) { tr.ar_cap++; used = -used; }
+                tr.ar_attempts += used;
+                for (int a = 0; a < 3; ++a) v[3 * q + a] = U[a] + C[a];
+            }
+        }
+        oc->cnt.relaxed += tr.nrelax;
+        oc->cnt.ar_attempts += tr.ar_attempts;
+        oc->cnt.ar_cap += tr.ar_cap;
+
+        /* Eq. 19: rescale every particle of the cell, c' = U + (c - U_p) sqrt(T / T_p) */
+        double Up[3], Tp, Qp[3];
+        hso_cell_moments(g, N, v, c->F_N, vol, Up, &Tp, Qp);
+        if (Tp > 0.0) {
+            double f = sqrt(T / Tp);
+            for (int64_t q = 0; q < N; ++q)
+                for (int a = 0; a < 3; ++a) v[3 * q + a] = U[a] + (v[3 * q + a] - Up[a]) * f;
+        }
+    }
+
+    /* Step (5): time-averaged sampling once step >= n_steady */
+    if ((int64_t)oc->step >= c->n_steady) {
+        double *A = &oc->acc[13 * k];
+        A[0] = A[0] + (double)N;
+        for (int64_t q = 0; q < N; ++q) {
+            const double *cv = &v[3 * q];
+            double c2 = cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2];
+            A[1] = A[1] + cv[0]; A[2] = A[2] + cv[1]; A[3] = A[3] + cv[2];
+            A[4] = A[4] + cv[0] * cv[0]; A[5] = A[5] + cv[1] * cv[1]; A[6] = A[6] + cv[2] * cv[2];
+            A[7] = A[7] + cv[0] * cv[1]; A[8] = A[8] + cv[0] * cv[2]; A[9] = A[9] + cv[1] * cv[2];
+            A[10] = A[10] + c2 * cv[0]; A[11] = A[11] + c2 * cv[1]; A[12] = A[12] + c2 * cv[2];
+        }
+    }
+    if (trace_on) {
+        sums4(v, N, tr.post_sum);
+        oc->trace[k] = tr;
+    }
+}
+
+static int step_case(const hso_gas *g, ocase *oc, int trace_on)
+{
+    const hso_case *c = &oc->p;
+    if (c->dim > 0) {
+        int64_t n_old = oc->np;
+        int e = inject(g, oc);
+        if (e) return e;
+        for (int64_t i = 0; i < oc->np; ++i) {
+            double t = c->dt_G;
+            if (i >= n_old) {
+                uint32_t w[4];
+                hso_draw(c->seed, ST_PARTICLE, (uint64_t)oc->id[i], (uint32_t)oc->step, DRAW_INJ_TIME, w);
+                t = c->dt_G * hso_uniform(w[0]);
+            }
+            oc->cell[i] = move_particle(g, oc, &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
+        }
+        sort_by_cell(oc);
+    } else {
+        /* 0-D: no transport; the particles must already be grouped by cell */
+        for (int64_t i = 1; i < oc->np; ++i)
+            if (oc->cell[i] < oc->cell[i - 1]) return HSO_ESTATE;
+        memset(oc->count, 0, sizeof(int64_t) * (size_t)(oc->ncells + 1));
+        for (int64_t i = 0; i < oc->np; ++i) oc->count[oc->cell[i]]++;
+        int64_t run = 0;
+        for (int64_t k = 0; k < oc->ncells; ++k) { run += oc->count[k]; oc->count[k] = run; }
+    }
+    /* count[k] now holds the end offset of cell k in the grouped array */
+    int64_t start = 0;
+    for (int64_t k = 0; k < oc->ncells; ++k) {
+        int64_t end = oc->count[k];
+        collide_cell(g, oc, k, start, end - start, trace_on);
+        start = end;
+    }
+    for (int64_t i = 0; i < oc->np * 3; ++i)
+        if (!isfinite(oc->v[i])) return HSO_ENUM;
+    if ((int64_t)oc->step >= c->n_steady) oc->n_samples++;
+    oc->step++;
+    return HSO_OK;
+}
+
+int hso_step(hso_sim *s, int64_t n)
+{
+    if (!s) return HSO_EARG;
+    if (s->failed) return HSO_ESTATE;
+    for (int64_t it = 0; it < n; ++it)
+        for (int i = 0; i < s->n_cases; ++i) {
+            int e = step_case(&s->gas, &s->cases[i], s->trace_on);
+            if (e) { s->failed = e; return e; }
+        }
+    return HSO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Step (6): output                                                                      */
+/* ------------------------------------------------------------------------------------ */
+
+/* mode 0: time averages of the Step (5) sums: n = F_N sum N / (S V), U = <c>,
+ * T = m/(3k) (<|c|^2> - |U|^2), q_i = (1/2) m n (<c_i|c|^2> - 2 U_j <c_i c_j> -
+ * U_i <|c|^2> + 2 U_i |U|^2).  mode 1: the Step (3) estimators of the current state. */
+int hso_sample_moments(hso_sim *s, int ci, int mode, double *n, double *u3, double *T,
+                       double *q3, int64_t *n_samples)
+{
+    if (!s || ci < 0 || ci >= s->n_cases) return HSO_EARG;
+    ocase *oc = &s->cases[ci];
+    const hso_gas *g = &s->gas;
+    if (n_samples) *n_samples = oc->n_samples;
+    if (mode == 0) {
+        for (int64_t k = 0; k < oc->ncells; ++k) {
+            const double *A = &oc->acc[13 * k];
+            double nn = 0.0, U[3] = { 0.0, 0.0, 0.0 }, TT = 0.0, q[3] = { 0.0, 0.0, 0.0 };
+            if (A[0] > 0.0 && oc->n_samples > 0 && oc->vol[k] > 0.0) {
+                nn = oc->p.F_N * A[0] / ((double)oc->n_samples * oc->vol[k]);
+                for (int a = 0; a < 3; ++a) U[a] = A[1 + a] / A[0];
+                double cc = (A[4] + A[5] + A[6]) / A[0];
+                double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+                TT = g->m / (3.0 * KB) * (cc - uu);
+                double cij[3][3] = { { A[4], A[7], A[8] }, { A[7], A[5], A[9] }, { A[8], A[9], A[6] } };
+                for (int a = 0; a < 3; ++a) {
+                    double uc = 0.0;
+                    for (int b = 0; b < 3; ++b) uc = uc + U[b] * cij[a][b] / A[0];
+                    q[a] = 0.5 * g->m * nn * (A[10 + a] / A[0] - 2.0 * uc - U[a] * cc + 2.0 * U[a] * uu);
+                }
+            }
+            if (n) n[k] = nn;
+            if (T) T[k] = TT;
+            for (int a = 0; a < 3; ++a) { if (u3) u3[3 * k + a] = U[a]; if (q3) q3[3 * k + a] = q[a]; }
+        }
+        return HSO_OK;
+    }
+    if (mode != 1) return HSO_EARG;
+    /* current state: group by cell (the state is sorted after every step) */
+    int64_t i0 = 0;
+    for (int64_t k = 0; k < oc->ncells; ++k) {
+        int64_t i1 = i0;
+        while (i1 < oc->np && oc->cell[i1] == k) ++i1;
+        double U[3], TT, q[3];
+        hso_cell_moments(g, i1 - i0, &oc->v[3 * i0], oc->p.F_N, oc->vol[k], U, &TT, q);
+        if (n) n[k] = oc->vol[k] > 0.0 ? (double)(i1 - i0) * oc->p.F_N / oc->vol[k] : 0.0;
+        if (T) T[k] = TT;
+        for (int a = 0; a < 3; ++a) { if (u3) u3[3 * k + a] = U[a]; if (q3) q3[3 * k + a] = q[a]; }
+        i0 = i1;
+    }
+    if (i0 != oc->np) return HSO_ESTATE;
+    return HSO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* State access                                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+int64_t hso_num_particles(const hso_sim *s, int c)
+{
+    if (!s || c < 0 || c >= s->n_cases) return -1;
+    return s->cases[c].np;
+}
+
+int64_t hso_num_cells(const hso_sim *s, int c)
+{
+    if (!s || c < 0 || c >= s->n_cases) return -1;
+    return s->cases[c].ncells;
+}
+
+int64_t hso_num_faces(const hso_sim *s, int c)
+{
+    if (!s || c < 0 || c >= s->n_cases) return -1;
+    return s->cases[c].nfaces;
+}
+
+int hso_face_info(const hso_sim *s, int c, int32_t *cell, int32_t *side, double *lambda)
+{
+    if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
+    const ocase *oc = &s->cases[c];
+    for (int64_t f = 0; f < oc->nfaces; ++f) {
+        if (cell) cell[f] = oc->faces[f].cell;
+        if (side) side[f] = oc->faces[f].side;
+        if (lambda) lambda[f] = oc->faces[f].lambda;
+    }
+    return HSO_OK;
+}
+
+int hso_get_state(const hso_sim *s, int c, double *x3, double *v3, int32_t *cell, int64_t *id,
+                  int64_t *next_id, int64_t *step)
+{
+    if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
+    const ocase *oc = &s->cases[c];
+    size_t n = (size_t)oc->np;
+    if (x3) memcpy(x3, oc->x, 3 * n * sizeof(double));
+    if (v3) memcpy(v3, oc->v, 3 * n * sizeof(double));
+    if (cell) memcpy(cell, oc->cell, n * sizeof(int32_t));
+    if (id) memcpy(id, oc->id, n * sizeof(int64_t));
+    if (next_id) *next_id = oc->next_id;
+    if (step) *step = oc->step;
+    return HSO_OK;
+}
+
+int hso_set_state(hso_sim *s, int c, int64_t np, const double *x3, const double *v3,
+                  const int32_t *cell, const int64_t *id, int64_t next_id, int64_t step)
+{
+    if (!s || c < 0 || c >= s->n_cases || np < 0) return HSO_EARG;
+    ocase *oc = &s->cases[c];
+    if (np > oc->cap) return HSO_ECAP;
+    for (int64_t i = 0; i < np; ++i) {
+        if (cell[i] < 0 || cell[i] >= oc->ncells) return HSO_EARG;
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(v3[3 * i + a]) || (x3 && !isfinite(x3[3 * i + a]))) return HSO_ENUM;
+    }
+    size_t n = (size_t)np;
+    if (x3) memcpy(oc->x, x3, 3 * n * sizeof(double));
+    else memset(oc->x, 0, 3 * n * sizeof(double));
+    memcpy(oc->v, v3, 3 * n * sizeof(double));
+    memcpy(oc->cell, cell, n * sizeof(int32_t));
+    memcpy(oc->id, id, n * sizeof(int64_t));
+    oc->np = np;
+    oc->next_id = next_id;
+    oc->step = step;
+    s->failed = 0;
+    return HSO_OK;
+}
+
+int hso_get_cells(const hso_sim *s, int c, double *vol, double *sigc_max, double *acc13,
+                  int64_t *n_samples)
+{
+    if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
+    const ocase *oc = &s->cases[c];
+    size_t nc = (size_t)oc->ncells;
+    if (vol) memcpy(vol, oc->vol, nc * sizeof(double));
+    if (sigc_max) memcpy(sigc_max, oc->sigc_max, nc * sizeof(double));
+    if (acc13) memcpy(acc13, oc->acc, 13 * nc * sizeof(double));
+    if (n_samples) *n_samples = oc->n_samples;
+    return HSO_OK;
+}
+
+int hso_set_cells(hso_sim *s, int c, const double *sigc_max, const double *acc13,
+                  int64_t n_samples)
+{
+    if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
+    ocase *oc = &s->cases[c];
+    size_t nc = (size_t)oc->ncells;
+    if (sigc_max) memcpy(oc->sigc_max, sigc_max, nc * sizeof(double));
+    if (acc13) memcpy(oc->acc, acc13, 13 * nc * sizeof(double));
+    oc->n_samples = n_samples;
+    return HSO_OK;
+}
+
+int hso_get_trace(const hso_sim *s, int c, hso_trace *out)
+{
+    if (!s || c < 0 || c >= s->n_cases || !s->trace_on) return HSO_EARG;
+    memcpy(out, s->cases[c].trace, sizeof(hso_trace) * (size_t)s->cases[c].ncells);
+    return HSO_OK;
+}
+
+int hso_get_counters(const hso_sim *s, int c, hso_counters *out)
+{
+    if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
+    *out = s->cases[c].cnt;
+    return HSO_OK;
+}

@@ -1,0 +1,124 @@
+/*
+ * hs_oracle.h -- plain FP64 CPU oracle of the per-time-step particle update of the
+ * hybrid stochastic-particle-Shakhov / DSMC method (Jin et al., arXiv 2506.23917).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct reference the
+ * GPU path is checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the product library never does.  It shares no code with
+ * the GPU path (no headers, helpers or tables): everything below is written from the
+ * paper's equations and the readings recorded with the oracle.
+ *
+ * Units are SI throughout.  All arithmetic is IEEE double, single-threaded, loops in
+ * array order.  Every function returns 0 on success, a positive HSO_E* code otherwise.
+ */
+#ifndef HS_ORACLE_H
+#define HS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { HSO_OK = 0, HSO_EARG = 1, HSO_ECAP = 2, HSO_ENUM = 3, HSO_ESTATE = 5 };
+enum { HSO_BC_OUTFLOW = 0, HSO_BC_SPECULAR = 1, HSO_BC_INFLOW = 2 };
+enum { HSO_BODY_NONE = 0, HSO_BODY_CYLINDER = 1, HSO_BODY_SPHERE = 2 };
+
+/* Gas model (Sec. 4 opening paragraph: argon, VHS, d_ref, T_ref, mu_ref, omega). */
+typedef struct {
+    double m, d_ref, T_ref, omega, mu_ref, Pr, gamma;
+} hso_gas;
+
+/* A drifting Maxwellian macrostate: number density, mean velocity, temperature. */
+typedef struct {
+    double n, u[3], T;
+} hso_state;
+
+/* One flow case on a uniform Cartesian grid (cells x-fastest).  dim = 0 is the
+ * spatially homogeneous (0-D) mode: nx cells, no transport, per-cell time steps. */
+typedef struct {
+    int32_t dim, nx, ny, nz;
+    double lo[3], h[3];              /* unused axes: h is the unit depth/area          */
+    int32_t bc[6];                   /* faces -x,+x,-y,+y,-z,+z                        */
+    hso_state inflow;                /* state injected through HSO_BC_INFLOW faces     */
+    double slot_lo[3], slot_hi[3];   /* inflow only where the face centre lies inside  */
+    int32_t body;                    /* HSO_BODY_*; diffuse wall at body_T             */
+    double body_c[3], body_r, body_T;
+    int32_t n_regions;               /* initial state: first region containing a cell  */
+    const double *region_box;        /* 6 per region: lo[3], hi[3]                     */
+    const hso_state *region_state;
+    double F_N, dt_G, T_sigma;       /* particle weight, global step, (sigma c)_max T  */
+    const double *dt_over_tau;       /* dim 0 only: per-cell dt_G / tau_0              */
+    uint64_t seed;
+    int64_t n_steady, capacity;
+} hso_case;
+
+typedef struct hso_sim hso_sim;
+
+/* Per-cell record of the last step, for parity checks. */
+typedef struct {
+    int64_t n, ncol, nacc, nrelax, ar_attempts, ar_cap;
+    uint64_t acc_hash;
+    double T, tau, dt_dsmc, p_relax, a_max;
+    double pre_sum[4];    /* sum c_x, c_y, c_z, sum |c|^2 before the collision step */
+    double post_sum[4];   /* the same after the conservation rescale               */
+} hso_trace;
+
+/* Case-wide event counters (cumulative). */
+typedef struct {
+    int64_t injected, removed, wall_hits, candidates, accepted, relaxed,
+            ar_attempts, ar_cap, bounce_cap, inject_cap, skipped_cells;
+} hso_counters;
+
+int  hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace,
+                hso_sim **out);
+void hso_destroy(hso_sim *s);
+int  hso_init_particles(hso_sim *s);                   /* Step (1)                  */
+int  hso_step(hso_sim *s, int64_t n);                  /* Steps (2)-(5), n times    */
+int  hso_sample_moments(hso_sim *s, int c, int mode, double *n, double *u3, double *T,
+                        double *q3, int64_t *n_samples); /* Step (6); mode 1 = now  */
+
+/* State access: positions are absolute (x,y,z per particle), velocities 3 per particle,
+ * cell is the case-local cell index, particles in array order. */
+int64_t hso_num_particles(const hso_sim *s, int c);
+int  hso_get_state(const hso_sim *s, int c, double *x3, double *v3, int32_t *cell,
+                   int64_t *id, int64_t *next_id, int64_t *step);
+int  hso_set_state(hso_sim *s, int c, int64_t np, const double *x3, const double *v3,
+                   const int32_t *cell, const int64_t *id, int64_t next_id, int64_t step);
+int  hso_get_cells(const hso_sim *s, int c, double *vol, double *sigc_max, double *acc13,
+                   int64_t *n_samples);
+int  hso_set_cells(hso_sim *s, int c, const double *sigc_max, const double *acc13,
+                   int64_t n_samples);
+int  hso_get_trace(const hso_sim *s, int c, hso_trace *out);
+int  hso_get_counters(const hso_sim *s, int c, hso_counters *out);
+int64_t hso_num_cells(const hso_sim *s, int c);
+int64_t hso_num_faces(const hso_sim *s, int c);
+int  hso_face_info(const hso_sim *s, int c, int32_t *cell, int32_t *side, double *lambda);
+
+/* Building blocks exposed for the pin tests. */
+void   hso_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void   hso_draw(uint64_t seed, uint32_t stream, uint64_t entity, uint32_t step,
+                uint32_t draw, uint32_t out[4]);
+double hso_uniform(uint32_t w);
+uint32_t hso_index(uint32_t w, uint32_t n);
+double hso_sigma_c(const hso_gas *g, double cr);
+double hso_viscosity(const hso_gas *g, double T);
+double hso_mean_free_path(const hso_gas *g, double n, double T);
+double hso_inflow_number_flux(const hso_gas *g, const hso_state *st, const double nrm[3]);
+/* flux-weighted normal speed draw (units of 1/beta), 4 words per attempt */
+double hso_sample_normal_speed(double s, const uint32_t *words, int n_attempts, int *used);
+/* Moments of a velocity set with the unbiased estimators of Step (3). */
+int    hso_cell_moments(const hso_gas *g, int64_t N, const double *v3, double F_N,
+                        double vol, double U[3], double *T, double Q[3]);
+/* Shakhov AR sampling of one thermal velocity with the given draw words
+ * (5 words per attempt: R1..R4, R5).  Returns attempts used (negative if capped). */
+int    hso_shakhov_sample(const hso_gas *g, double T, double p, const double Q[3],
+                          double a_max, const uint32_t *words, int n_attempts, double C[3]);
+/* Timescale split of Step (4): returns dt_dsmc, dt_sbgk for given dt_c, tau, dt_G. */
+void   hso_split(double dt_c, double tau, double dt_G, double *dt_dsmc, double *dt_sbgk);
+/* Number of 16^dim sub-cell centres of a cell outside the body. */
+int64_t hso_cut_count(const hso_case *c, int i, int j, int k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
