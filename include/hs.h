@@ -1,0 +1,213 @@
+/*
+ * hs.h -- C ABI of the MI355X (gfx950) implementation of the per-time-step particle update
+ * of the hybrid stochastic-particle-Shakhov / DSMC method (Jin, Liu, Yang, Cao, Zhuo,
+ * Zhong, arXiv 2506.23917, Sec. 3).
+ *
+ * One step, on the GPU, for a batch of independent flow cases sharing one particle array:
+ *   inflow injection -> free transport with walls (Step 2, Eq. 4, Eq. 30) -> stable cell
+ *   counting sort (Step 3) -> per cell: moments (Eq. 31), time split (Eq. 25-28), NTC DSMC
+ *   (Eq. 5-9), SP-Shakhov resampling (Eq. 16-18), conservation rescale (Eq. 19),
+ *   time-averaged sampling (Step 5).
+ *
+ * Conventions
+ *  - SI units.  Cells of a case are numbered x-fastest; cell c = i + nx (j + ny k).
+ *  - Memory: the CALLER owns all device memory.  hs_plan() gives the workspace size; the
+ *    caller allocates it (e.g. a torch uint8 tensor on the GPU) and passes it to
+ *    hs_init_particles(), which carves every buffer out of it.  The workspace must
+ *    outlive the sim.  The sim handle owns host metadata only.
+ *  - Streams: all GPU work of a sim is enqueued on the hipStream_t given at init
+ *    (passed as void*; NULL = the default stream).  hs_step() does not synchronise.
+ *    Calls that return data (hs_sample_moments, hs_export_state, hs_last_trace,
+ *    hs_counters, hs_sync) synchronise that stream.
+ *  - Errors: every call returns an hs_status.  Argument errors return at once and
+ *    change nothing.  Faults found on the device (capacity overflow, a cell denser than
+ *    the per-cell limit, a non-finite moment, inconsistent state) are latched in a
+ *    device error word and reported by the next synchronising call; after that the sim
+ *    answers HS_ERR_STATE to everything but hs_error_string/hs_destroy.
+ *  - Not thread-safe: one sim, one host thread, one stream.
+ *  - Randomness: Philox4x32-10 keyed by each case's seed; counters are
+ *    (entity, stream, step, draw) with entities local to the case, so a case gives the
+ *    same result alone or in any batch.  Seeds must differ between cases of a batch.
+ */
+#ifndef HS_H
+#define HS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HS_OK = 0,
+    HS_ERR_ARG = 1,        /* invalid argument                                        */
+    HS_ERR_CAPACITY = 2,   /* particle capacity or per-cell particle limit exceeded   */
+    HS_ERR_NUMERIC = 3,    /* non-finite velocity or moment                           */
+    HS_ERR_DEVICE = 4,     /* a HIP runtime call failed                               */
+    HS_ERR_STATE = 5       /* the sim is in a failed state                            */
+} hs_status;
+
+typedef enum { HS_FP64 = 0, HS_FP32_MIXED = 1 } hs_precision;
+typedef enum { HS_BC_OUTFLOW = 0, HS_BC_SPECULAR = 1, HS_BC_INFLOW = 2 } hs_bc;
+typedef enum { HS_BODY_NONE = 0, HS_BODY_CYLINDER = 1, HS_BODY_SPHERE = 2 } hs_body;
+
+enum {
+    HS_FLAG_TRACE = 1,         /* keep a per-cell record of the last step (hs_last_trace)  */
+    HS_FLAG_NO_PARTICLES = 2,  /* hs_init_particles leaves the domain empty (for import)    */
+    HS_FLAG_GRAPH = 4          /* replay each step as a captured hipGraph                   */
+};
+
+/* Kernel groups of one step, for hs_kernel_timing. */
+enum {
+    HS_KERNEL_INJECT = 0,      /* inflow counts, scan and fill                              */
+    HS_KERNEL_MOVE = 1,        /* free transport + per-cell counts                          */
+    HS_KERNEL_SCAN = 2,        /* exclusive scan of the cell counts                         */
+    HS_KERNEL_SCATTER = 3,     /* stable scatter of particle indices                        */
+    HS_KERNEL_COLLIDE = 4,     /* per-cell gather, moments, collisions, rescale, sampling  */
+    HS_KERNEL_STEP = 5,        /* the whole step                                            */
+    HS_NUM_KERNELS = 6
+};
+
+/* Gas (Sec. 4): molecular mass, VHS reference diameter / temperature / viscosity and
+ * exponent omega, Prandtl number (Shakhov model, Eq. 12), specific-heat ratio (Eq. 25). */
+typedef struct {
+    double m, d_ref, T_ref, omega, mu_ref, Pr, gamma;
+} hs_gas;
+
+/* Drifting Maxwellian: number density (1/m^3), velocity (m/s), temperature (K). */
+typedef struct {
+    double n, u[3], T;
+} hs_state;
+
+/* One flow case on a uniform Cartesian grid.
+ *  dim 1..3: cells nx (x ny (x nz)); lo = lower corner, h = cell edges; for unused axes
+ *    h is the unit depth/area, so every cell volume is h0 h1 h2 times its fluid fraction.
+ *  dim 0: nx independent homogeneous cells (no transport), each with its own step
+ *    dt_over_tau[k] * tau_0, tau_0 = mu(T) / (n k T) of region_state[0].
+ *  bc: faces -x,+x,-y,+y,-z,+z.  OUTFLOW removes leaving particles; SPECULAR reflects;
+ *    INFLOW removes leaving particles and injects the inflow state's one-way flux
+ *    (only through faces whose centre lies inside [slot_lo, slot_hi) on every tangential
+ *    axis with slot_hi > slot_lo).
+ *  body: a diffusely reflecting cylinder (axis z) or sphere at T body_T, strictly inside
+ *    the domain; cells are cut by it (fluid fraction = share of 16^dim sub-cell centres
+ *    outside).  SPECULAR walls cannot be combined with a body.
+ *  regions: initial state; a cell takes the state of the first box holding its centre
+ *    (6 doubles per box: lo xyz, hi xyz); cells in no box start empty.
+ *  F_N: real molecules per particle; dt_G: global time step (fixed; Eq. 26 evaluated by
+ *    the caller); T_sigma: temperature setting the initial (sigma_T c_r)_max at
+ *    c* = 10 sqrt(k T_sigma / m); n_steady: first sampled step (Step 5); capacity: the
+ *    largest number of particles the case may hold.  Arrays are copied at init. */
+typedef struct {
+    int32_t dim, nx, ny, nz;
+    double lo[3], h[3];
+    int32_t bc[6];
+    hs_state inflow;
+    double slot_lo[3], slot_hi[3];
+    int32_t body;
+    double body_c[3], body_r, body_T;
+    int32_t n_regions;
+    const double *region_box;
+    const hs_state *region_state;
+    double F_N, dt_G, T_sigma;
+    const double *dt_over_tau;
+    uint64_t seed;
+    int64_t n_steady, capacity;
+} hs_case;
+
+typedef struct hs_sim hs_sim;
+
+/* Per-cell record of the last step (with HS_FLAG_TRACE): particle count, NTC candidates,
+ * accepted pairs, relaxed particles, Shakhov attempts and capped draws, an
+ * order-independent hash of the accepted candidate indices, the cell's T, tau,
+ * DSMC sub-step, relaxation probability, Shakhov envelope, and sum c, sum |c|^2 before
+ * the collision stage and after the rescale (FP64, before any rounding to FP32). */
+typedef struct {
+    int64_t n, ncol, nacc, nrelax, ar_attempts, ar_cap;
+    uint64_t acc_hash;
+    double T, tau, dt_dsmc, p_relax, a_max;
+    double pre_sum[4];
+    double post_sum[4];
+} hs_trace;
+
+/* Cumulative per-case event counters, in this order. */
+enum {
+    HS_CNT_INJECTED = 0, HS_CNT_REMOVED, HS_CNT_WALL_HITS, HS_CNT_CANDIDATES,
+    HS_CNT_ACCEPTED, HS_CNT_RELAXED, HS_CNT_AR_ATTEMPTS, HS_CNT_AR_CAP,
+    HS_CNT_BOUNCE_CAP, HS_CNT_INJECT_CAP, HS_CNT_SKIPPED_CELLS, HS_NUM_COUNTERS
+};
+
+/* Size in bytes of the device workspace for this batch (no GPU work). */
+hs_status hs_plan(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
+                  uint32_t flags, size_t *dev_bytes);
+
+/* Step (1), Sec. 3.2: validate and copy the cases, lay out the workspace, compute cut-cell
+ * volumes, draw the initial particles (uniform positions in each cell's fluid part,
+ * velocities U + Eq. 17 Maxwellian, N = floor(n V / F_N + u) per cell, ids in cell order)
+ * and set (sigma_T c_r)_max.  dev_workspace: device pointer to >= hs_plan() bytes, owned
+ * by the caller.  hip_stream: the hipStream_t to use.  On success *out is a new sim. */
+hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases,
+                            hs_precision prec, uint32_t flags, void *dev_workspace,
+                            size_t dev_bytes, void *hip_stream, hs_sim **out);
+
+/* Steps (2)-(5), n times, enqueued asynchronously on the sim's stream. */
+hs_status hs_step(hs_sim *sim, int64_t n);
+
+/* Block until the sim's stream is idle; report latched device errors. */
+hs_status hs_sync(hs_sim *sim);
+
+/* Step (6): per-cell output for case_id into caller-owned host arrays of ncells entries
+ * (u3, q3: 3 per cell).  mode 0: time averages of the Step (5) sums since n_steady;
+ * mode 1: the Eq. 31 estimators of the current particles.  Any pointer may be NULL. */
+hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, double *u3,
+                            double *T, double *q3, int64_t *n_samples);
+
+/* Checkpoint of one case (native precision, bit-exact resume).  Layout: hs_state_header,
+ * then pos[3][np], vel[3][np] (element size 8 for HS_FP64, 4 for HS_FP32_MIXED; pos is
+ * the cell-relative position in [0,1) per axis), cell[np] (int32, case-local),
+ * id[np] (int64), sigc_max[ncells], acc[ncells][13] (double).  Particles are sorted by
+ * cell.  hs_state_bytes gives the size.  Importing requires cells non-decreasing; it sets
+ * the sim's step counter (shared by all cases). */
+typedef struct {
+    uint32_t magic, version, precision, dim;
+    int64_t np, ncells, next_id, step, n_samples;
+} hs_state_header;
+size_t hs_state_bytes(hs_sim *sim, int case_id);
+hs_status hs_export_state(hs_sim *sim, int case_id, void *host_buf, size_t bytes);
+hs_status hs_import_state(hs_sim *sim, int case_id, const void *host_buf, size_t bytes);
+
+/* Per-cell records of the last step (needs HS_FLAG_TRACE); out has ncells entries. */
+hs_status hs_last_trace(hs_sim *sim, int case_id, hs_trace *out);
+
+/* Cumulative counters of case_id, HS_NUM_COUNTERS int64 values. */
+hs_status hs_counters(hs_sim *sim, int case_id, int64_t *out);
+
+/* Number of cells / live particles of a case (the latter synchronises). */
+int64_t hs_num_cells(const hs_sim *sim, int case_id);
+int64_t hs_num_particles(hs_sim *sim, int case_id);
+
+/* Per-kernel timing with HIP events recorded on the sim's stream around each kernel group
+ * of every step enqueued while timing is on (steps then run as plain launches, not as a
+ * graph).  hs_kernel_timing synchronises and returns the average duration (ms) of kernel
+ * group `which` (HS_KERNEL_*) over the timed steps and their number; hs_clear_timing
+ * forgets them. */
+hs_status hs_set_timing(hs_sim *sim, int enable);
+hs_status hs_kernel_timing(hs_sim *sim, int which, double *avg_ms, int64_t *launches);
+hs_status hs_clear_timing(hs_sim *sim);
+
+/* Human-readable description of the last error (never NULL). */
+const char *hs_error_string(const hs_sim *sim);
+
+/* Release host metadata (the workspace stays the caller's). */
+void hs_destroy(hs_sim *sim);
+
+/* Philox4x32-10 words for counters (entity, stream, step, draw) of one seed, computed on
+ * the GPU into a caller-owned device array of 4 * n uint32 (entity = first_entity + i);
+ * synchronous.  For cross-checking the generator. */
+hs_status hs_debug_philox(uint64_t seed, uint32_t stream, uint64_t first_entity,
+                          uint32_t step, uint32_t draw, int64_t n, void *dev_out,
+                          void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

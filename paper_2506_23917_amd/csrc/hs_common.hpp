@@ -1,0 +1,143 @@
+// hs_common.hpp -- data layout shared by the host runtime and the gfx950 kernels.
+//
+// One sim holds a batch of cases flattened into one global cell range and one particle
+// array.  Particles are structure-of-arrays in two ping-pong buffers; the step counter on
+// the device selects which one is current (step & 1), so every launch of a step has
+// fixed arguments and can be replayed from a graph.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/hs.h"
+
+namespace hsk {
+
+constexpr int kMaxCases = 256;
+constexpr int kMaxBounce = 8;        // body reflections per particle per step
+constexpr int kMaxShakhov = 64;      // Shakhov acceptance-rejection attempts
+constexpr int kMaxInjectAR = 64;     // inflow normal-speed attempts
+constexpr int kMaxPosTry = 64;       // initial-position attempts in a cut cell
+constexpr int kSub = 16;             // sub-cells per axis of the cut-cell volume rule
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+
+// Philox streams and per-step draw indices (shared numbering of the method's draws).
+enum : uint32_t { kStreamParticle = 0, kStreamCell = 1, kStreamFace = 2, kStreamInit = 3 };
+enum : uint32_t { kDrawRelax = 0, kDrawShakhov = 1, kDrawBounce = 200, kDrawInjectTime = 300 };
+
+// Error bits of the device error word.
+enum : uint32_t {
+    kErrCapacity = 1u,      // particle capacity exceeded
+    kErrCellLimit = 2u,     // a cell holds more particles than the collide kernels take
+    kErrNumeric = 4u,       // non-finite moment / velocity
+    kErrState = 8u          // internal inconsistency (recomputed move disagrees)
+};
+
+struct GasDev {
+    double m, R, Pr, gamma, mu_ref, T_ref, omega;
+    double K_vhs, vhs_exp;  // sigma_T c_r = K c_r^(2 - 2 omega)
+};
+
+struct CaseDev {
+    int32_t dim, n[3];
+    int32_t cell0, ncells;          // global cell range [cell0, cell0 + ncells)
+    int32_t face0, nfaces;          // global inflow-face range
+    int32_t region0, nregions;
+    int32_t bc[6];
+    int32_t body;
+    uint32_t seed_lo, seed_hi;
+    int64_t n_steady, capacity;
+    double lo[3], h[3], dt_over_h[3];
+    double body_c[3], body_r, body_T;
+    double F_N, dt_G, L_cell, sigc0, tau0;
+    double in_n, in_u[3], in_T;
+};
+
+struct FaceDev {
+    int32_t cell;       // global boundary cell
+    int32_t side;       // 0..5
+    int32_t case_id;
+    int32_t local;      // face index within the case (Philox entity)
+    double lambda;      // expected entering particles per step
+};
+
+struct StateDev {
+    double n, u[3], T;
+};
+
+struct Globals {
+    int64_t step;
+    int32_t n_live;          // particles in the current buffer
+    int32_t n_total;         // after injection
+    int32_t n_new;           // after the sort
+    int32_t n_big;           // cells handed to the block-per-cell collide kernel
+    uint32_t err;
+    uint32_t halt;
+    int32_t n_inject;        // particles injected this step
+    int32_t pad;
+    int64_t next_id[kMaxCases];
+    int64_t inj_id_base[kMaxCases];
+    int64_t n_samples[kMaxCases];
+    long long counters[kMaxCases][HS_NUM_COUNTERS];
+};
+
+// Cell trace record (same field order as hs_trace).
+struct TraceDev {
+    int64_t n, ncol, nacc, nrelax, ar_attempts, ar_cap;
+    uint64_t acc_hash;
+    double T, tau, dt_dsmc, p_relax, a_max;
+    double pre_sum[4];
+    double post_sum[4];
+};
+static_assert(sizeof(TraceDev) == sizeof(hs_trace), "trace layout");
+
+struct PartBuf {
+    void *pos[3];
+    void *vel[3];
+    int32_t *cell;
+    int64_t *id;
+};
+
+// Everything a kernel needs, passed by value.
+struct Ctx {
+    const CaseDev *cases;
+    const FaceDev *faces;
+    const double *region_box;
+    const StateDev *region_state;
+    const double *dt_cell;        // per global cell (0-D cases), else unused
+    GasDev gas;
+    PartBuf buf[2];
+    int32_t *newcell, *slot, *perm;
+    int32_t *count, *cstart;      // per cell; cstart has ncells_total + 1 entries
+    double *sigc, *acc, *vol;     // (sigma c)_max, 13 sums per cell, fluid volume
+    int32_t *face_cnt, *face_start;
+    int32_t *scan_part;
+    int32_t *big_list;
+    TraceDev *trace;              // nullptr unless tracing
+    Globals *g;
+    int32_t n_cases, n_faces, ncells_total, cap_wave;
+    int32_t cap_block, precision;
+    int64_t capacity;             // total particle capacity of the batch
+};
+
+// Launchers (defined in hs_kernels.hip).
+struct Launch {
+    static void init_cells(const Ctx &c, void *stream);
+    static void init_count(const Ctx &c, void *stream);
+    static void init_fill(const Ctx &c, void *stream);
+    static void init_finish(const Ctx &c, void *stream);
+    static void scan_cells(const Ctx &c, void *stream, int build_big);
+    static void inject(const Ctx &c, void *stream);
+    static void move_count(const Ctx &c, void *stream);
+    static void scatter(const Ctx &c, void *stream);
+    static void collide(const Ctx &c, void *stream);
+    static void finish_step(const Ctx &c, void *stream);
+    static void philox(uint64_t seed, uint32_t stream_id, uint64_t e0, uint32_t step,
+                       uint32_t draw, int64_t n, uint32_t *out, void *stream);
+};
+
+void launch_moments_now(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
+void launch_build_big(const Ctx &c, void *stream);
+void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
+int cap_wave();
+int cap_block(int precision);
+
+}  // namespace hsk

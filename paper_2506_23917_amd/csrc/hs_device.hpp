@@ -1,0 +1,363 @@
+// hs_device.hpp -- device building blocks of the gfx950 particle update: the counter-based
+// generator, uniform conversions, the VHS gas model, Maxwellian draws, the body geometry
+// and the free-flight move shared by the move/count and collide kernels (the collide kernel
+// re-runs the move of each particle it gathers, bit-identically, instead of storing it).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hs_common.hpp"
+
+namespace hsk {
+
+constexpr double kKB = 1.380649e-23;
+constexpr double kPi = 3.14159265358979323846;
+
+struct W4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32 with ten rounds (Salmon et al., SC'11): per round the first and third
+// counter words are multiplied by the two round constants; the high halves are xored
+// with the other words and the key; the key advances by the two Weyl increments.
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
+        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = h1 ^ c1 ^ k0;
+        const uint32_t n2 = h0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = l1;
+        c2 = n2;
+        c3 = l0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return W4{c0, c1, c2, c3};
+}
+
+// Counter = (entity low word, entity bits 32..59 | stream << 28, step, draw); key = seed.
+__device__ __forceinline__ W4 draw(const CaseDev &cs, uint32_t stream, uint64_t entity,
+                                   uint32_t step, uint32_t d)
+{
+    return philox10((uint32_t)entity, ((uint32_t)(entity >> 32) & 0x0fffffffu) | (stream << 28),
+                    step, d, cs.seed_lo, cs.seed_hi);
+}
+
+// 32-bit word -> double uniform in (0,1): (w + 1/2) 2^-32.
+__device__ __forceinline__ double unid(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+// 32-bit word -> float uniform in (0,1): an odd multiple of 2^-24, exactly representable.
+__device__ __forceinline__ float unif(uint32_t w) { return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f; }
+// 32-bit word -> integer in [0, n): floor(w n / 2^32).
+__device__ __forceinline__ uint32_t unidx(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+template <typename P> struct Real;
+template <> struct Real<double> {
+    __device__ static double uni(uint32_t w) { return unid(w); }
+    __device__ static double sq(double x) { return sqrt(x); }
+    __device__ static double ln(double x) { return log(x); }
+    __device__ static double pw(double x, double y) { return pow(x, y); }
+    __device__ static void sc(double x, double *s, double *c) { sincos(x, s, c); }
+    __device__ static double fl(double x) { return floor(x); }
+    __device__ static double below_one() { return 0x1.fffffffffffffp-1; }
+};
+template <> struct Real<float> {
+    __device__ static float uni(uint32_t w) { return unif(w); }
+    __device__ static float sq(float x) { return sqrtf(x); }
+    __device__ static float ln(float x) { return logf(x); }
+    __device__ static float pw(float x, float y) { return powf(x, y); }
+    __device__ static void sc(float x, float *s, float *c) { sincosf(x, s, c); }
+    __device__ static float fl(float x) { return floorf(x); }
+    __device__ static float below_one() { return 0x1.fffffep-1f; }
+};
+
+// Case of a global cell: binary search over the cases' first cells.
+__device__ __forceinline__ int case_of(const Ctx &C, int g)
+{
+    int lo = 0, hi = C.n_cases - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C.cases[mid].cell0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void cell_ijk(const CaseDev &cs, int local, int ijk[3])
+{
+    ijk[0] = ijk[1] = ijk[2] = 0;
+    if (cs.dim == 0) { ijk[0] = local; return; }
+    ijk[0] = local % cs.n[0];
+    if (cs.dim >= 2) ijk[1] = (local / cs.n[0]) % cs.n[1];
+    if (cs.dim >= 3) ijk[2] = local / (cs.n[0] * cs.n[1]);
+}
+
+__device__ __forceinline__ int cell_local(const CaseDev &cs, const int ijk[3])
+{
+    return ijk[0] + cs.n[0] * (ijk[1] + cs.n[1] * ijk[2]);
+}
+
+__device__ __forceinline__ int body_axes(const CaseDev &cs) { return cs.body == HS_BODY_SPHERE ? 3 : 2; }
+
+// Strictly inside the body: |x - c|^2 < R^2 summed over the body's axes in order x, y, z.
+__device__ __forceinline__ bool in_body(const CaseDev &cs, const double X[3])
+{
+    if (cs.body == HS_BODY_NONE) return false;
+    const int na = body_axes(cs);
+    double d2 = 0.0;
+    for (int a = 0; a < na; ++a) {
+        const double d = X[a] - cs.body_c[a];
+        d2 = d2 + d * d;
+    }
+    return d2 < cs.body_r * cs.body_r;
+}
+
+// Cut-cell rule: number of the 16^dim sub-cell centres lo + (i + (s + 1/2)/16) h outside
+// the body; cells clearly outside / inside (1e-9 relative margin) are classified without
+// sampling.
+__device__ inline int cut_count(const CaseDev &cs, const int ijk[3])
+{
+    int full = 1;
+    for (int a = 0; a < cs.dim; ++a) full *= kSub;
+    if (cs.body == HS_BODY_NONE || cs.dim == 0) return full;
+    const int na = body_axes(cs);
+    double near2 = 0.0, far2 = 0.0;
+    for (int a = 0; a < na; ++a) {
+        const double blo = cs.lo[a] + (double)ijk[a] * cs.h[a];
+        const double bhi = cs.lo[a] + (double)(ijk[a] + 1) * cs.h[a];
+        double dn = 0.0;
+        if (cs.body_c[a] < blo) dn = blo - cs.body_c[a];
+        else if (cs.body_c[a] > bhi) dn = cs.body_c[a] - bhi;
+        const double d1 = fabs(blo - cs.body_c[a]), d2 = fabs(bhi - cs.body_c[a]);
+        const double df = d2 > d1 ? d2 : d1;
+        near2 = near2 + dn * dn;
+        far2 = far2 + df * df;
+    }
+    const double R2 = cs.body_r * cs.body_r;
+    if (near2 > R2 * (1.0 + 1e-9)) return full;
+    if (far2 < R2 * (1.0 - 1e-9)) return 0;
+    int out = 0;
+    const int s2n = cs.dim >= 3 ? kSub : 1, s1n = cs.dim >= 2 ? kSub : 1;
+    for (int s2 = 0; s2 < s2n; ++s2)
+        for (int s1 = 0; s1 < s1n; ++s1)
+            for (int s0 = 0; s0 < kSub; ++s0) {
+                const int sub[3] = {s0, s1, s2};
+                double X[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < cs.dim; ++a)
+                    X[a] = cs.lo[a] + ((double)ijk[a] + ((double)sub[a] + 0.5) / kSub) * cs.h[a];
+                if (!in_body(cs, X)) ++out;
+            }
+    return out;
+}
+
+// First time the path X + V t meets the body surface within [0, t], or -1.
+__device__ __forceinline__ double body_hit(const CaseDev &cs, const double X[3], const double V[3], double t)
+{
+    const int na = body_axes(cs);
+    double a = 0.0, b = 0.0, q = 0.0;
+    for (int k = 0; k < na; ++k) {
+        const double d = X[k] - cs.body_c[k];
+        a = a + V[k] * V[k];
+        b = b + d * V[k];
+        q = q + d * d;
+    }
+    q = q - cs.body_r * cs.body_r;
+    if (!(a > 0.0) || q < 0.0 || b >= 0.0) return -1.0;
+    const double disc = b * b - a * q;
+    if (disc < 0.0) return -1.0;
+    const double th = q / (-b + sqrt(disc));
+    return th <= t ? th : -1.0;
+}
+
+// Diffuse re-emission at the body (full accommodation at body_T): normal speed
+// sqrt(2RT_w) sqrt(-ln R1), tangential speeds sqrt(2RT_w) {cos, sin}(2 pi R3) sqrt(-ln R4)
+// along t1 and t2 (cylinder: t1 = (-n_y, n_x, 0), t2 = z; sphere: t1 = e x n normalised,
+// e the axis of smallest |n_e|, t2 = n x t1).
+__device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, const double X[3], W4 w,
+                                       double V[3])
+{
+    double nr[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+    const int na = body_axes(cs);
+    double len = 0.0;
+    for (int k = 0; k < na; ++k) {
+        nr[k] = X[k] - cs.body_c[k];
+        len = len + nr[k] * nr[k];
+    }
+    len = sqrt(len);
+    for (int k = 0; k < na; ++k) nr[k] = nr[k] / len;
+    if (cs.body == HS_BODY_CYLINDER) {
+        t1[0] = -nr[1];
+        t1[1] = nr[0];
+        t2[2] = 1.0;
+    } else {
+        int e = 0;
+        if (fabs(nr[1]) < fabs(nr[e])) e = 1;
+        if (fabs(nr[2]) < fabs(nr[e])) e = 2;
+        double ev[3] = {0.0, 0.0, 0.0};
+        ev[e] = 1.0;
+        t1[0] = ev[1] * nr[2] - ev[2] * nr[1];
+        t1[1] = ev[2] * nr[0] - ev[0] * nr[2];
+        t1[2] = ev[0] * nr[1] - ev[1] * nr[0];
+        const double l1 = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+        for (int k = 0; k < 3; ++k) t1[k] = t1[k] / l1;
+        t2[0] = nr[1] * t1[2] - nr[2] * t1[1];
+        t2[1] = nr[2] * t1[0] - nr[0] * t1[2];
+        t2[2] = nr[0] * t1[1] - nr[1] * t1[0];
+    }
+    const double a = sqrt(2.0 * gas.R * cs.body_T);
+    const double cn = a * sqrt(-log(unid(w.x)));
+    const double rr = sqrt(-log(unid(w.z)));
+    double sn, cs_;
+    sincos(2.0 * kPi * unid(w.y), &sn, &cs_);
+    const double ct1 = a * cs_ * rr, ct2 = a * sn * rr;
+    for (int k = 0; k < 3; ++k) V[k] = cn * nr[k] + ct1 * t1[k] + ct2 * t2[k];
+}
+
+struct MoveStats {
+    int hits, capped;
+};
+
+// Free flight (Eq. 4) for time t of one particle stored as (cell, cell-relative position
+// xr in [0,1)^dim, velocity v): body reflections in FP64 on absolute coordinates, plain
+// flight in cell units in the storage precision, specular walls by mirroring, removal
+// through open faces.  Returns the new case-local cell or -1.
+// `id` is the particle id, or -1 to load it from *idsrc on the first body reflection.
+template <typename P>
+__device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int local, P xr[3], P v[3],
+                                    int64_t &id, const int64_t *idsrc, double t, bool full_step,
+                                    uint32_t step, MoveStats &ms)
+{
+    const int dim = cs.dim;
+    int ijk[3];
+    cell_ijk(cs, local, ijk);
+    if (cs.body != HS_BODY_NONE) {
+        double X[3] = {0.0, 0.0, 0.0}, V[3];
+        for (int a = 0; a < dim; ++a) X[a] = cs.lo[a] + ((double)ijk[a] + (double)xr[a]) * cs.h[a];
+        for (int a = 0; a < 3; ++a) V[a] = (double)v[a];
+        bool bounced = false;
+        for (int b = 0;; ++b) {
+            const double th = body_hit(cs, X, V, t);
+            if (th < 0.0) break;
+            for (int a = 0; a < dim; ++a) X[a] = X[a] + V[a] * th;
+            t = t - th;
+            ms.hits++;
+            bounced = true;
+            if (b == kMaxBounce) {
+                ms.capped++;
+                t = 0.0;
+                break;
+            }
+            if (id < 0) id = *idsrc;
+            diffuse_reflect(gas, cs, X, draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + b), V);
+        }
+        if (bounced) {
+            for (int a = 0; a < dim; ++a) {
+                X[a] = X[a] + V[a] * t;
+                const double hi = cs.lo[a] + (double)cs.n[a] * cs.h[a];
+                if (X[a] < cs.lo[a]) {
+                    if (cs.bc[2 * a] != HS_BC_SPECULAR) return -1;
+                    X[a] = 2.0 * cs.lo[a] - X[a];
+                    V[a] = -V[a];
+                } else if (X[a] >= hi) {
+                    if (cs.bc[2 * a + 1] != HS_BC_SPECULAR) return -1;
+                    X[a] = 2.0 * hi - X[a];
+                    V[a] = -V[a];
+                }
+                const double f = (X[a] - cs.lo[a]) / cs.h[a];
+                int i = (int)floor(f);
+                i = i < 0 ? 0 : (i > cs.n[a] - 1 ? cs.n[a] - 1 : i);
+                double r = f - (double)i;
+                P rp = (P)r;
+                if (!(rp >= (P)0)) rp = (P)0;
+                if (!(rp < (P)1)) rp = Real<P>::below_one();
+                xr[a] = rp;
+                ijk[a] = i;
+            }
+            for (int a = 0; a < 3; ++a) v[a] = (P)V[a];
+            return cell_local(cs, ijk);
+        }
+    }
+    for (int a = 0; a < dim; ++a) {
+        const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+        P x = xr[a] + v[a] * dth;
+        const P f = Real<P>::fl(x);
+        int i = ijk[a] + (int)f;
+        x = x - f;
+        if (x >= (P)1) { x = x - (P)1; i += 1; }
+        const int n = cs.n[a];
+        if (i < 0) {
+            if (cs.bc[2 * a] != HS_BC_SPECULAR) return -1;
+            i = -i - 1;
+            x = (P)1 - x;
+            v[a] = -v[a];
+        } else if (i >= n) {
+            if (cs.bc[2 * a + 1] != HS_BC_SPECULAR) return -1;
+            i = 2 * n - 1 - i;
+            x = (P)1 - x;
+            v[a] = -v[a];
+        }
+        if (x >= (P)1) { x = x - (P)1; i += 1; }
+        if (i < 0) { i = 0; ms.capped++; }
+        if (i > n - 1) { i = n - 1; ms.capped++; }
+        xr[a] = x;
+        ijk[a] = i;
+    }
+    return cell_local(cs, ijk);
+}
+
+// Flux-weighted normal speed z = beta c_n of a drifting Maxwellian entering a face,
+// density ~ z exp(-(z - s)^2) on z > 0, by exact acceptance-rejection (4 words an
+// attempt): s >= 0 under |y| e^{-y^2}[y > -s] + s e^{-y^2} (y = z - s), accepting with
+// (y + s) / (|y| + s); -3/4 < s < 0 under a Rayleigh envelope accepting with e^{2 z s};
+// s <= -3/4 under a Gamma(2, 2|s|) envelope accepting with e^{-z^2}.
+__device__ inline double normal_speed(const CaseDev &cs, uint32_t face, uint32_t step, uint32_t base, double s,
+                                      int &used)
+{
+    double z = 0.0;
+    if (s >= 0.0) {
+        const double e = exp(-s * s);
+        const double Ma = 1.0 - 0.5 * e, Mb = s * sqrt(kPi);
+        const double pa = Ma / (Ma + Mb);
+        z = s > 0.0 ? s : 1.0;
+        for (int a = 0; a < kMaxInjectAR; ++a) {
+            const W4 w = draw(cs, kStreamFace, face, step, base + (uint32_t)a);
+            const double u0 = unid(w.x), u1 = unid(w.y), u2 = unid(w.z), u3 = unid(w.w);
+            double y;
+            if (u0 < pa) {
+                if (u1 * Ma < 0.5) y = sqrt(-log(u2));
+                else y = -sqrt(-log(1.0 - u2 * (1.0 - e)));
+            } else {
+                y = sqrt(-log(u1)) * cos(2.0 * kPi * u2);
+                if (y <= -s) continue;
+            }
+            const double zz = y + s;
+            if (zz <= 0.0) continue;
+            z = zz;
+            if (u3 * (fabs(y) + s) < zz) { used = a + 1; return zz; }
+        }
+    } else if (s > -0.75) {
+        for (int a = 0; a < kMaxInjectAR; ++a) {
+            const W4 w = draw(cs, kStreamFace, face, step, base + (uint32_t)a);
+            const double zz = sqrt(-log(unid(w.x)));
+            z = zz;
+            if (unid(w.w) < exp(2.0 * zz * s)) { used = a + 1; return zz; }
+        }
+    } else {
+        for (int a = 0; a < kMaxInjectAR; ++a) {
+            const W4 w = draw(cs, kStreamFace, face, step, base + (uint32_t)a);
+            const double zz = -(log(unid(w.x)) + log(unid(w.y))) / (-2.0 * s);
+            z = zz;
+            if (unid(w.w) < exp(-zz * zz)) { used = a + 1; return zz; }
+        }
+    }
+    used = -kMaxInjectAR;
+    return z;
+}
+
+}  // namespace hsk

@@ -1,0 +1,825 @@
+// hs_runtime.cpp -- host side of the C ABI declared in include/hs.h: case validation,
+// inflow-face tables, the workspace layout, initialisation, the step sequence (plain
+// launches, a replayed hipGraph, or launches bracketed by HIP events), output and
+// checkpoints.  All particle work runs in the kernels of hs_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hs_common.hpp"
+
+using namespace hsk;
+
+namespace {
+
+constexpr double kKB_h = 1.380649e-23;
+constexpr double kPi_h = 3.14159265358979323846;
+constexpr uint32_t kMagic = 0x48534331u;  // "HSC1"
+
+struct Layout {
+    size_t total = 0;
+    size_t globals, cases, faces, rbox, rstate, dtcell;
+    size_t pos[2][3], vel[2][3], cell[2], id[2];
+    size_t newcell, slot, perm, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, trace, out;
+};
+
+struct Plan {
+    std::vector<CaseDev> cases;
+    std::vector<FaceDev> faces;
+    std::vector<double> rbox;
+    std::vector<StateDev> rstate;
+    std::vector<double> dtcell;     // per global cell, only if some case is 0-D
+    int64_t ncells = 0, capacity = 0;
+    int dim_max = 0;
+    bool any_spatial = false, any_0d = false;
+    GasDev gas;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+hs_status validate(const hs_gas *g, const hs_case *cs, int n, std::string &why)
+{
+    if (!g || !cs || n <= 0) { why = "null gas/cases or no cases"; return HS_ERR_ARG; }
+    if (n > kMaxCases) { why = "too many cases"; return HS_ERR_ARG; }
+    if (!(g->m > 0) || !(g->d_ref > 0) || !(g->T_ref > 0) || !(g->mu_ref > 0) || !(g->gamma > 1) ||
+        !(g->Pr > 0) || !(g->omega > 0.5 && g->omega < 1.5)) {
+        why = "invalid gas";
+        return HS_ERR_ARG;
+    }
+    int64_t cells = 0, cap = 0;
+    for (int i = 0; i < n; ++i) {
+        const hs_case &c = cs[i];
+        if (c.dim < 0 || c.dim > 3) { why = "dim"; return HS_ERR_ARG; }
+        if (c.nx <= 0 || (c.dim >= 2 && c.ny <= 0) || (c.dim >= 3 && c.nz <= 0)) { why = "grid size"; return HS_ERR_ARG; }
+        for (int a = 0; a < 3; ++a)
+            if (!(c.h[a] > 0)) { why = "cell size"; return HS_ERR_ARG; }
+        if (!(c.F_N > 0) || !(c.T_sigma > 0) || c.capacity < 0) { why = "F_N/T_sigma/capacity"; return HS_ERR_ARG; }
+        if (c.dim == 0) {
+            if (!c.dt_over_tau || c.n_regions < 1 || !c.region_state) { why = "0-D case needs dt_over_tau and a region state"; return HS_ERR_ARG; }
+        } else if (!(c.dt_G > 0)) { why = "dt_G"; return HS_ERR_ARG; }
+        if (c.n_regions < 0 || (c.n_regions > 0 && (!c.region_state || (c.dim > 0 && !c.region_box)))) { why = "regions"; return HS_ERR_ARG; }
+        for (int s = 0; s < 2 * c.dim; ++s)
+            if (c.bc[s] < HS_BC_OUTFLOW || c.bc[s] > HS_BC_INFLOW) { why = "bc"; return HS_ERR_ARG; }
+        bool inflow = false;
+        for (int s = 0; s < 2 * c.dim; ++s) inflow |= c.bc[s] == HS_BC_INFLOW;
+        if (inflow && !(c.inflow.T > 0 && c.inflow.n >= 0)) { why = "inflow state"; return HS_ERR_ARG; }
+        if (c.body != HS_BODY_NONE) {
+            if (c.body == HS_BODY_CYLINDER && c.dim < 2) { why = "cylinder needs dim >= 2"; return HS_ERR_ARG; }
+            if (c.body == HS_BODY_SPHERE && c.dim < 3) { why = "sphere needs dim 3"; return HS_ERR_ARG; }
+            if (c.body < 0 || c.body > 2 || !(c.body_r > 0) || !(c.body_T > 0)) { why = "body"; return HS_ERR_ARG; }
+            for (int s = 0; s < 2 * c.dim; ++s)
+                if (c.bc[s] == HS_BC_SPECULAR) { why = "specular walls with a body"; return HS_ERR_ARG; }
+            const int na = c.body == HS_BODY_SPHERE ? 3 : 2;
+            const int nn[3] = {c.nx, c.ny, c.nz};
+            for (int a = 0; a < na; ++a)
+                if (!(c.body_c[a] - c.body_r > c.lo[a]) || !(c.body_c[a] + c.body_r < c.lo[a] + nn[a] * c.h[a])) {
+                    why = "body must lie strictly inside the domain";
+                    return HS_ERR_ARG;
+                }
+        }
+        for (int j = 0; j < i; ++j)
+            if (cs[j].seed == c.seed) { why = "cases need distinct seeds"; return HS_ERR_ARG; }
+        int64_t nc = c.nx;
+        if (c.dim >= 2) nc *= c.ny;
+        if (c.dim >= 3) nc *= c.nz;
+        cells += nc;
+        cap += c.capacity;
+    }
+    if (cells >= (1ll << 31) - 1 || cap >= (1ll << 31) - 64) { why = "batch too large for 32-bit indices"; return HS_ERR_ARG; }
+    return HS_OK;
+}
+
+double vhs_K(const hs_gas *g)
+{
+    return kPi_h * g->d_ref * g->d_ref * std::pow(4.0 * kKB_h * g->T_ref / g->m, g->omega - 0.5) /
+           std::tgamma(2.5 - g->omega);
+}
+
+// One-way number flux of the inflow state through a face with inward normal +-e_a.
+double face_flux(const hs_gas *g, const hs_state &st, int a, double sg)
+{
+    const double R = kKB_h / g->m;
+    const double beta = 1.0 / std::sqrt(2.0 * R * st.T);
+    double nrm[3] = {0.0, 0.0, 0.0};
+    nrm[a] = sg;
+    const double s = beta * (st.u[0] * nrm[0] + st.u[1] * nrm[1] + st.u[2] * nrm[2]);
+    return st.n * (std::exp(-s * s) + std::sqrt(kPi_h) * s * (1.0 + std::erf(s))) / (2.0 * beta * std::sqrt(kPi_h));
+}
+
+void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
+{
+    P.gas.m = g->m;
+    P.gas.R = kKB_h / g->m;
+    P.gas.Pr = g->Pr;
+    P.gas.gamma = g->gamma;
+    P.gas.mu_ref = g->mu_ref;
+    P.gas.T_ref = g->T_ref;
+    P.gas.omega = g->omega;
+    P.gas.K_vhs = vhs_K(g);
+    P.gas.vhs_exp = 2.0 - 2.0 * g->omega;
+    int64_t cell0 = 0;
+    for (int i = 0; i < n; ++i) if (cs[i].dim == 0) P.any_0d = true;
+    for (int i = 0; i < n; ++i) {
+        const hs_case &c = cs[i];
+        CaseDev d;
+        std::memset(&d, 0, sizeof(d));
+        d.dim = c.dim;
+        d.n[0] = c.nx;
+        d.n[1] = c.dim >= 2 ? c.ny : 1;
+        d.n[2] = c.dim >= 3 ? c.nz : 1;
+        const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
+        d.cell0 = (int32_t)cell0;
+        d.ncells = (int32_t)nc;
+        for (int a = 0; a < 6; ++a) d.bc[a] = c.bc[a];
+        d.body = c.body;
+        d.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
+        d.seed_hi = (uint32_t)(c.seed >> 32);
+        d.n_steady = c.n_steady;
+        d.capacity = c.capacity;
+        for (int a = 0; a < 3; ++a) {
+            d.lo[a] = c.lo[a];
+            d.h[a] = c.h[a];
+            d.dt_over_h[a] = c.dt_G / c.h[a];
+            d.body_c[a] = c.body_c[a];
+            d.in_u[a] = c.inflow.u[a];
+        }
+        d.body_r = c.body_r;
+        d.body_T = c.body_T;
+        d.F_N = c.F_N;
+        d.dt_G = c.dt_G;
+        double L = c.h[0];
+        for (int a = 1; a < c.dim; ++a) if (c.h[a] < L) L = c.h[a];
+        d.L_cell = L;
+        d.sigc0 = P.gas.K_vhs * std::pow(10.0 * std::sqrt(kKB_h * c.T_sigma / g->m), 2.0 - 2.0 * g->omega);
+        d.in_n = c.inflow.n;
+        d.in_T = c.inflow.T;
+        d.region0 = (int32_t)P.rstate.size();
+        d.nregions = c.n_regions;
+        for (int r = 0; r < c.n_regions; ++r) {
+            for (int k = 0; k < 6; ++k) P.rbox.push_back(c.region_box ? c.region_box[6 * r + k] : 0.0);
+            StateDev st;
+            st.n = c.region_state[r].n;
+            for (int a = 0; a < 3; ++a) st.u[a] = c.region_state[r].u[a];
+            st.T = c.region_state[r].T;
+            P.rstate.push_back(st);
+        }
+        if (P.any_0d) {
+            const double tau0 = c.dim == 0 ? g->mu_ref * std::pow(c.region_state[0].T / g->T_ref, g->omega) /
+                                                 (c.region_state[0].n * kKB_h * c.region_state[0].T)
+                                           : 0.0;
+            d.tau0 = tau0;
+            for (int64_t k = 0; k < nc; ++k) P.dtcell.push_back(c.dim == 0 ? c.dt_over_tau[k] * tau0 : c.dt_G);
+        }
+        // inflow faces: sides -x,+x,-y,+y,-z,+z; boundary cells x-fastest; slot filter
+        d.face0 = (int32_t)P.faces.size();
+        for (int s = 0; s < 2 * c.dim; ++s) {
+            if (c.bc[s] != HS_BC_INFLOW) continue;
+            const int a = s / 2;
+            const double sg = (s % 2 == 0) ? 1.0 : -1.0;
+            double area = 1.0;
+            for (int t = 0; t < 3; ++t) if (t != a) area *= c.h[t];
+            const double lam = face_flux(g, c.inflow, a, sg) * area * c.dt_G / c.F_N;
+            for (int64_t k = 0; k < nc; ++k) {
+                const int ijk[3] = {(int)(k % d.n[0]), (int)((k / d.n[0]) % d.n[1]), (int)(k / ((int64_t)d.n[0] * d.n[1]))};
+                if (ijk[a] != ((s % 2 == 0) ? 0 : d.n[a] - 1)) continue;
+                bool ok = true;
+                for (int t = 0; t < c.dim; ++t) {
+                    if (t == a || !(c.slot_hi[t] > c.slot_lo[t])) continue;
+                    const double ctr = c.lo[t] + ((double)ijk[t] + 0.5) * c.h[t];
+                    if (!(ctr >= c.slot_lo[t] && ctr < c.slot_hi[t])) ok = false;
+                }
+                if (!ok) continue;
+                FaceDev f;
+                f.cell = (int32_t)(cell0 + k);
+                f.side = s;
+                f.case_id = i;
+                f.local = (int32_t)(P.faces.size() - d.face0);
+                f.lambda = lam;
+                P.faces.push_back(f);
+            }
+        }
+        d.nfaces = (int32_t)(P.faces.size() - d.face0);
+        P.cases.push_back(d);
+        cell0 += nc;
+        P.capacity += c.capacity;
+        P.dim_max = std::max(P.dim_max, c.dim);
+        if (c.dim > 0) P.any_spatial = true;
+    }
+    P.ncells = cell0;
+}
+
+Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
+{
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+    const size_t es = prec == HS_FP64 ? 8 : 4;
+    const size_t cap = (size_t)std::max<int64_t>(P.capacity, 1);
+    const size_t nc = (size_t)P.ncells;
+    L.globals = take(sizeof(Globals));
+    L.cases = take(sizeof(CaseDev) * P.cases.size());
+    L.faces = take(sizeof(FaceDev) * std::max<size_t>(P.faces.size(), 1));
+    L.rbox = take(sizeof(double) * std::max<size_t>(P.rbox.size(), 1));
+    L.rstate = take(sizeof(StateDev) * std::max<size_t>(P.rstate.size(), 1));
+    L.dtcell = P.any_0d ? take(sizeof(double) * nc) : 0;
+    for (int b = 0; b < 2; ++b) {
+        for (int a = 0; a < 3; ++a) L.pos[b][a] = a < P.dim_max ? take(es * cap) : 0;
+        for (int a = 0; a < 3; ++a) L.vel[b][a] = take(es * cap);
+        L.cell[b] = take(4 * cap);
+        L.id[b] = take(8 * cap);
+    }
+    if (P.any_spatial) {
+        L.newcell = take(4 * cap);
+        L.slot = take(4 * cap);
+        L.perm = take(4 * cap);
+    } else {
+        L.newcell = L.slot = L.perm = 0;
+    }
+    L.count = take(4 * nc);
+    L.cstart = take(4 * (nc + 1));
+    L.sigc = take(8 * nc);
+    L.acc = take(8 * 13 * nc);
+    L.vol = take(8 * nc);
+    L.facecnt = take(4 * std::max<size_t>(P.faces.size(), 1));
+    L.facestart = take(4 * (P.faces.size() + 1));
+    L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
+    L.big = take(4 * nc);
+    L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
+    size_t maxcase = 1;
+    for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
+    L.out = take(8 * 8 * maxcase);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct hs_sim {
+    hs_precision prec;
+    uint32_t flags;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Plan plan;
+    Layout lay;
+    Ctx ctx;
+    std::vector<hs_case> cases;
+    int failed = 0;
+    std::string err;
+    bool graph_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    std::vector<hipEvent_t> events;   // HS_NUM_KERNELS+1 per timed step... see enqueue
+    int64_t timed_steps = 0;
+};
+
+namespace {
+
+hs_status fail(hs_sim *s, hs_status st, const std::string &why)
+{
+    if (s) {
+        s->err = why;
+        if (st != HS_ERR_ARG) s->failed = st;
+    }
+    return st;
+}
+
+#define HIPCHK(sim, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(sim, HS_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+hs_status read_globals(hs_sim *s, Globals &G)
+{
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, hipMemcpy(&G, s->ws + s->lay.globals, sizeof(Globals), hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+hs_status check_device(hs_sim *s)
+{
+    if (s->failed) return HS_ERR_STATE;
+    Globals G;
+    hs_status st = read_globals(s, G);
+    if (st) return st;
+    if (G.err) {
+        std::string why = "device error:";
+        hs_status code = HS_ERR_STATE;
+        if (G.err & kErrCapacity) { why += " particle capacity exceeded"; code = HS_ERR_CAPACITY; }
+        if (G.err & kErrCellLimit) { why += " a cell exceeds the per-cell particle limit"; code = HS_ERR_CAPACITY; }
+        if (G.err & kErrNumeric) { why += " non-finite moment"; if (code == HS_ERR_STATE) code = HS_ERR_NUMERIC; }
+        if (G.err & kErrState) { why += " inconsistent state"; }
+        s->err = why;
+        s->failed = code;
+        return code;
+    }
+    return HS_OK;
+}
+
+void enqueue_step(hs_sim *s, int timed)
+{
+    const Ctx &c = s->ctx;
+    void *st = (void *)s->stream;
+    hipEvent_t *ev = nullptr;
+    if (timed) {
+        const size_t base = s->events.size();
+        s->events.resize(base + 6);
+        for (size_t k = base; k < base + 6; ++k) hipEventCreate(&s->events[k]);
+        ev = &s->events[base];
+        hipEventRecord(ev[0], s->stream);
+    }
+    if (s->plan.any_spatial) {
+        Launch::inject(c, st);
+        if (ev) hipEventRecord(ev[1], s->stream);
+        Launch::move_count(c, st);
+        if (ev) hipEventRecord(ev[2], s->stream);
+        Launch::scan_cells(c, st, 1);
+        if (ev) hipEventRecord(ev[3], s->stream);
+        Launch::scatter(c, st);
+        if (ev) hipEventRecord(ev[4], s->stream);
+    } else if (ev) {
+        for (int k = 1; k <= 4; ++k) hipEventRecord(ev[k], s->stream);
+    }
+    Launch::collide(c, st);
+    if (ev) hipEventRecord(ev[5], s->stream);
+    Launch::finish_step(c, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_plan(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec, uint32_t flags,
+                  size_t *dev_bytes)
+{
+    std::string why;
+    if (!dev_bytes || (prec != HS_FP64 && prec != HS_FP32_MIXED)) return HS_ERR_ARG;
+    hs_status st = validate(gas, cases, n_cases, why);
+    if (st) return st;
+    Plan P;
+    build_plan(gas, cases, n_cases, P);
+    *dev_bytes = make_layout(P, prec, flags).total;
+    return HS_OK;
+}
+
+hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
+                            uint32_t flags, void *dev_workspace, size_t dev_bytes, void *hip_stream, hs_sim **out)
+{
+    std::string why;
+    if (!out || !dev_workspace || (prec != HS_FP64 && prec != HS_FP32_MIXED)) return HS_ERR_ARG;
+    hs_status st = validate(gas, cases, n_cases, why);
+    if (st) return st;
+    hs_sim *s = new hs_sim();
+    s->prec = prec;
+    s->flags = flags;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (char *)dev_workspace;
+    s->ws_bytes = dev_bytes;
+    build_plan(gas, cases, n_cases, s->plan);
+    s->lay = make_layout(s->plan, prec, flags);
+    if (dev_bytes < s->lay.total) {
+        delete s;
+        return HS_ERR_ARG;
+    }
+    s->cases.assign(cases, cases + n_cases);
+    const Layout &L = s->lay;
+    char *w = s->ws;
+    Ctx &c = s->ctx;
+    std::memset(&c, 0, sizeof(c));
+    c.cases = (const CaseDev *)(w + L.cases);
+    c.faces = (const FaceDev *)(w + L.faces);
+    c.region_box = (const double *)(w + L.rbox);
+    c.region_state = (const StateDev *)(w + L.rstate);
+    c.dt_cell = s->plan.any_0d ? (const double *)(w + L.dtcell) : nullptr;
+    c.gas = s->plan.gas;
+    for (int b = 0; b < 2; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            c.buf[b].pos[a] = a < s->plan.dim_max ? (void *)(w + L.pos[b][a]) : nullptr;
+            c.buf[b].vel[a] = w + L.vel[b][a];
+        }
+        c.buf[b].cell = (int32_t *)(w + L.cell[b]);
+        c.buf[b].id = (int64_t *)(w + L.id[b]);
+    }
+    c.newcell = s->plan.any_spatial ? (int32_t *)(w + L.newcell) : nullptr;
+    c.slot = s->plan.any_spatial ? (int32_t *)(w + L.slot) : nullptr;
+    c.perm = s->plan.any_spatial ? (int32_t *)(w + L.perm) : nullptr;
+    c.count = (int32_t *)(w + L.count);
+    c.cstart = (int32_t *)(w + L.cstart);
+    c.sigc = (double *)(w + L.sigc);
+    c.acc = (double *)(w + L.acc);
+    c.vol = (double *)(w + L.vol);
+    c.face_cnt = (int32_t *)(w + L.facecnt);
+    c.face_start = (int32_t *)(w + L.facestart);
+    c.scan_part = (int32_t *)(w + L.scanpart);
+    c.big_list = (int32_t *)(w + L.big);
+    c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
+    c.g = (Globals *)(w + L.globals);
+    c.n_cases = n_cases;
+    c.n_faces = (int32_t)s->plan.faces.size();
+    c.ncells_total = (int32_t)s->plan.ncells;
+    c.cap_wave = cap_wave();
+    c.cap_block = cap_block(prec);
+    c.precision = prec;
+    c.capacity = s->plan.capacity;
+
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s->stream);
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : up(L.cases, s->plan.cases.data(), sizeof(CaseDev) * s->plan.cases.size());
+    e = e ? e : up(L.faces, s->plan.faces.data(), sizeof(FaceDev) * s->plan.faces.size());
+    e = e ? e : up(L.rbox, s->plan.rbox.data(), sizeof(double) * s->plan.rbox.size());
+    e = e ? e : up(L.rstate, s->plan.rstate.data(), sizeof(StateDev) * s->plan.rstate.size());
+    if (s->plan.any_0d) e = e ? e : up(L.dtcell, s->plan.dtcell.data(), sizeof(double) * s->plan.dtcell.size());
+    e = e ? e : hipMemsetAsync(w + L.globals, 0, sizeof(Globals), s->stream);
+    if (e != hipSuccess) {
+        std::string m = hipGetErrorString(e);
+        delete s;
+        (void)m;
+        return HS_ERR_DEVICE;
+    }
+    const int fill = (flags & HS_FLAG_NO_PARTICLES) ? 0 : 1;
+    Ctx ci = c;
+    if (fill) Launch::init_cells(ci, s->stream);
+    else Launch::init_count(ci, s->stream);
+    Launch::scan_cells(ci, s->stream, 0);
+    if (fill) Launch::init_fill(ci, s->stream);
+    Launch::init_finish(ci, s->stream);
+    if (!s->plan.any_spatial) launch_build_big(ci, s->stream);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return HS_ERR_DEVICE;
+    }
+    *out = s;
+    hs_status cs = check_device(s);
+    return cs;
+}
+
+hs_status hs_step(hs_sim *s, int64_t n)
+{
+    if (!s || n < 0) return HS_ERR_ARG;
+    if (s->failed) return HS_ERR_STATE;
+    if (s->timing) {
+        for (int64_t k = 0; k < n; ++k) enqueue_step(s, 1);
+        s->timed_steps += n;
+    } else if (s->flags & HS_FLAG_GRAPH) {
+        if (!s->graph_ready) {
+            HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            enqueue_step(s, 0);
+            HIPCHK(s, hipStreamEndCapture(s->stream, &s->graph));
+            HIPCHK(s, hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+            s->graph_ready = true;
+        }
+        for (int64_t k = 0; k < n; ++k) HIPCHK(s, hipGraphLaunch(s->gexec, s->stream));
+    } else {
+        for (int64_t k = 0; k < n; ++k) enqueue_step(s, 0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s, HS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return HS_OK;
+}
+
+hs_status hs_sync(hs_sim *s)
+{
+    if (!s) return HS_ERR_ARG;
+    return check_device(s);
+}
+
+int64_t hs_num_cells(const hs_sim *s, int c)
+{
+    if (!s || c < 0 || c >= (int)s->plan.cases.size()) return -1;
+    return s->plan.cases[c].ncells;
+}
+
+static hs_status case_range(hs_sim *s, int c, int32_t &a, int32_t &b)
+{
+    const CaseDev &cs = s->plan.cases[c];
+    HIPCHK(s, hipMemcpy(&a, s->ctx.cstart + cs.cell0, 4, hipMemcpyDeviceToHost));
+    HIPCHK(s, hipMemcpy(&b, s->ctx.cstart + cs.cell0 + cs.ncells, 4, hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+int64_t hs_num_particles(hs_sim *s, int c)
+{
+    if (!s || c < 0 || c >= (int)s->plan.cases.size()) return -1;
+    if (check_device(s)) return -1;
+    int32_t a, b;
+    if (case_range(s, c, a, b)) return -1;
+    return (int64_t)b - a;
+}
+
+hs_status hs_sample_moments(hs_sim *s, int c, int mode, double *n, double *u3, double *T, double *q3,
+                            int64_t *n_samples)
+{
+    if (!s || c < 0 || c >= (int)s->plan.cases.size() || (mode != 0 && mode != 1)) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const int nc = s->plan.cases[c].ncells;
+    double *out = (double *)(s->ws + s->lay.out);
+    if (mode == 0) launch_finalize(s->ctx, s->stream, c, nc, out);
+    else launch_moments_now(s->ctx, s->stream, c, nc, out);
+    std::vector<double> h((size_t)nc * 8);
+    HIPCHK(s, hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int k = 0; k < nc; ++k) {
+        const double *o = &h[8 * (size_t)k];
+        if (n) n[k] = o[0];
+        if (T) T[k] = o[4];
+        for (int a = 0; a < 3; ++a) {
+            if (u3) u3[3 * k + a] = o[1 + a];
+            if (q3) q3[3 * k + a] = o[5 + a];
+        }
+    }
+    if (n_samples) {
+        Globals G;
+        st = read_globals(s, G);
+        if (st) return st;
+        *n_samples = G.n_samples[c];
+    }
+    return HS_OK;
+}
+
+size_t hs_state_bytes(hs_sim *s, int c)
+{
+    if (!s || c < 0 || c >= (int)s->plan.cases.size()) return 0;
+    if (check_device(s)) return 0;
+    int32_t a, b;
+    if (case_range(s, c, a, b)) return 0;
+    const size_t np = (size_t)(b - a), nc = (size_t)s->plan.cases[c].ncells;
+    const size_t es = s->prec == HS_FP64 ? 8 : 4;
+    return sizeof(hs_state_header) + np * (6 * es + 4 + 8) + nc * 8 * 14;
+}
+
+hs_status hs_export_state(hs_sim *s, int c, void *host_buf, size_t bytes)
+{
+    if (!s || !host_buf || c < 0 || c >= (int)s->plan.cases.size()) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const size_t need = hs_state_bytes(s, c);
+    if (bytes < need) return HS_ERR_ARG;
+    int32_t a, b;
+    if ((st = case_range(s, c, a, b))) return st;
+    Globals G;
+    if ((st = read_globals(s, G))) return st;
+    const CaseDev &cs = s->plan.cases[c];
+    const size_t np = (size_t)(b - a), nc = (size_t)cs.ncells;
+    const size_t es = s->prec == HS_FP64 ? 8 : 4;
+    hs_state_header hd;
+    hd.magic = kMagic;
+    hd.version = 1;
+    hd.precision = s->prec;
+    hd.dim = cs.dim;
+    hd.np = (int64_t)np;
+    hd.ncells = (int64_t)nc;
+    hd.next_id = G.next_id[c];
+    hd.step = G.step;
+    hd.n_samples = G.n_samples[c];
+    char *p = (char *)host_buf;
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    const PartBuf &B = s->ctx.buf[G.step & 1];
+    for (int d = 0; d < 3; ++d) {
+        if (d < cs.dim && np) HIPCHK(s, hipMemcpy(p, (char *)B.pos[d] + es * a, es * np, hipMemcpyDeviceToHost));
+        else std::memset(p, 0, es * np);
+        p += es * np;
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (np) HIPCHK(s, hipMemcpy(p, (char *)B.vel[d] + es * a, es * np, hipMemcpyDeviceToHost));
+        p += es * np;
+    }
+    int32_t *cellp = (int32_t *)p;
+    if (np) HIPCHK(s, hipMemcpy(p, B.cell + a, 4 * np, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < np; ++i) cellp[i] -= cs.cell0;
+    p += 4 * np;
+    if (np) HIPCHK(s, hipMemcpy(p, B.id + a, 8 * np, hipMemcpyDeviceToHost));
+    p += 8 * np;
+    HIPCHK(s, hipMemcpy(p, s->ctx.sigc + cs.cell0, 8 * nc, hipMemcpyDeviceToHost));
+    p += 8 * nc;
+    HIPCHK(s, hipMemcpy(p, s->ctx.acc + 13 * (size_t)cs.cell0, 8 * 13 * nc, hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
+{
+    if (!s || !host_buf || c < 0 || c >= (int)s->plan.cases.size()) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    if (bytes < sizeof(hs_state_header)) return HS_ERR_ARG;
+    hs_state_header hd;
+    std::memcpy(&hd, host_buf, sizeof(hd));
+    const CaseDev &cs = s->plan.cases[c];
+    const size_t es = s->prec == HS_FP64 ? 8 : 4;
+    if (hd.magic != kMagic || hd.precision != (uint32_t)s->prec || hd.dim != (uint32_t)cs.dim ||
+        hd.ncells != cs.ncells || hd.np < 0 || hd.step < 0) {
+        s->err = "state header does not match the case";
+        return HS_ERR_ARG;
+    }
+    const size_t np = (size_t)hd.np, nc = (size_t)cs.ncells;
+    if (bytes < sizeof(hd) + np * (6 * es + 12) + nc * 8 * 14) return HS_ERR_ARG;
+    if ((int64_t)np > cs.capacity) { s->err = "import exceeds the case capacity"; return HS_ERR_CAPACITY; }
+    const char *p = (const char *)host_buf + sizeof(hd);
+    const char *pos = p, *vel = p + 3 * es * np;
+    const int32_t *cell = (const int32_t *)(p + 6 * es * np);
+    const int64_t *ids = (const int64_t *)(p + 6 * es * np + 4 * np);
+    const double *sigc = (const double *)(p + 6 * es * np + 12 * np);
+    const double *acc = sigc + nc;
+    auto rd = [&](const char *base, size_t i) -> double {
+        return es == 8 ? ((const double *)base)[i] : (double)((const float *)base)[i];
+    };
+    for (size_t i = 0; i < np; ++i) {
+        if (cell[i] < 0 || cell[i] >= cs.ncells || (i && cell[i] < cell[i - 1])) {
+            s->err = "imported cells must be in range and non-decreasing";
+            return HS_ERR_ARG;
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(rd(vel + d * es * np, i))) { s->err = "non-finite imported velocity"; return HS_ERR_NUMERIC; }
+            if (d < cs.dim) {
+                const double x = rd(pos + d * es * np, i);
+                if (!(x >= 0.0 && x < 1.0)) { s->err = "imported positions must be cell-relative in [0,1)"; return HS_ERR_ARG; }
+            }
+        }
+    }
+    // rebuild the whole particle array with this case replaced
+    Globals G;
+    if ((st = read_globals(s, G))) return st;
+    const int ncase = (int)s->plan.cases.size();
+    std::vector<int32_t> cst((size_t)s->plan.ncells + 1);
+    HIPCHK(s, hipMemcpy(cst.data(), s->ctx.cstart, 4 * cst.size(), hipMemcpyDeviceToHost));
+    const PartBuf &Bo = s->ctx.buf[G.step & 1];
+    const PartBuf &Bn = s->ctx.buf[hd.step & 1];
+    const int dmax = s->plan.dim_max;
+    std::vector<std::vector<char>> arrs(6);
+    std::vector<int32_t> ncell;
+    std::vector<int64_t> nid;
+    for (int k = 0; k < ncase; ++k) {
+        const CaseDev &ck = s->plan.cases[k];
+        if (k == c) {
+            for (int d = 0; d < 3; ++d) {
+                if (d < dmax) {
+                    const size_t at = arrs[d].size();
+                    arrs[d].resize(at + es * np);
+                    std::memcpy(arrs[d].data() + at, pos + d * es * np, es * np);
+                }
+                const size_t at = arrs[3 + d].size();
+                arrs[3 + d].resize(at + es * np);
+                std::memcpy(arrs[3 + d].data() + at, vel + d * es * np, es * np);
+            }
+            for (size_t i = 0; i < np; ++i) {
+                ncell.push_back(cell[i] + ck.cell0);
+                nid.push_back(ids[i]);
+            }
+        } else {
+            const int32_t a = cst[ck.cell0], b = cst[ck.cell0 + ck.ncells];
+            const size_t m = (size_t)(b - a);
+            for (int d = 0; d < 3; ++d) {
+                if (d < dmax) {
+                    const size_t at = arrs[d].size();
+                    arrs[d].resize(at + es * m);
+                    if (m) HIPCHK(s, hipMemcpy(arrs[d].data() + at, (char *)Bo.pos[d] + es * a, es * m, hipMemcpyDeviceToHost));
+                }
+                const size_t at = arrs[3 + d].size();
+                arrs[3 + d].resize(at + es * m);
+                if (m) HIPCHK(s, hipMemcpy(arrs[3 + d].data() + at, (char *)Bo.vel[d] + es * a, es * m, hipMemcpyDeviceToHost));
+            }
+            const size_t at = ncell.size();
+            ncell.resize(at + m);
+            nid.resize(at + m);
+            if (m) {
+                HIPCHK(s, hipMemcpy(ncell.data() + at, Bo.cell + a, 4 * m, hipMemcpyDeviceToHost));
+                HIPCHK(s, hipMemcpy(nid.data() + at, Bo.id + a, 8 * m, hipMemcpyDeviceToHost));
+            }
+        }
+    }
+    const size_t total = ncell.size();
+    if ((int64_t)total > s->plan.capacity) return HS_ERR_CAPACITY;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dmax && total) HIPCHK(s, hipMemcpy(Bn.pos[d], arrs[d].data(), es * total, hipMemcpyHostToDevice));
+        if (total) HIPCHK(s, hipMemcpy(Bn.vel[d], arrs[3 + d].data(), es * total, hipMemcpyHostToDevice));
+    }
+    if (total) {
+        HIPCHK(s, hipMemcpy(Bn.cell, ncell.data(), 4 * total, hipMemcpyHostToDevice));
+        HIPCHK(s, hipMemcpy(Bn.id, nid.data(), 8 * total, hipMemcpyHostToDevice));
+    }
+    std::vector<int32_t> cnt((size_t)s->plan.ncells + 1, 0);
+    for (size_t i = 0; i < total; ++i) cnt[(size_t)ncell[i] + 1]++;
+    for (size_t g = 1; g < cnt.size(); ++g) cnt[g] += cnt[g - 1];
+    HIPCHK(s, hipMemcpy(s->ctx.cstart, cnt.data(), 4 * cnt.size(), hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(s->ctx.sigc + cs.cell0, sigc, 8 * nc, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(s->ctx.acc + 13 * (size_t)cs.cell0, acc, 8 * 13 * nc, hipMemcpyHostToDevice));
+    G.step = hd.step;
+    G.n_live = (int32_t)total;
+    G.n_total = (int32_t)total;
+    G.n_new = (int32_t)total;
+    G.n_big = 0;
+    G.next_id[c] = hd.next_id;
+    G.n_samples[c] = hd.n_samples;
+    HIPCHK(s, hipMemcpy(s->ws + s->lay.globals, &G, sizeof(G), hipMemcpyHostToDevice));
+    if (!s->plan.any_spatial) {
+        launch_build_big(s->ctx, s->stream);
+        HIPCHK(s, hipGetLastError());
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+    }
+    return HS_OK;
+}
+
+hs_status hs_last_trace(hs_sim *s, int c, hs_trace *out)
+{
+    if (!s || !out || c < 0 || c >= (int)s->plan.cases.size() || !s->ctx.trace) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const CaseDev &cs = s->plan.cases[c];
+    HIPCHK(s, hipMemcpy(out, s->ctx.trace + cs.cell0, sizeof(hs_trace) * cs.ncells, hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+hs_status hs_counters(hs_sim *s, int c, int64_t *out)
+{
+    if (!s || !out || c < 0 || c >= (int)s->plan.cases.size()) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    Globals G;
+    if ((st = read_globals(s, G))) return st;
+    for (int k = 0; k < HS_NUM_COUNTERS; ++k) out[k] = G.counters[c][k];
+    return HS_OK;
+}
+
+hs_status hs_set_timing(hs_sim *s, int enable)
+{
+    if (!s) return HS_ERR_ARG;
+    s->timing = enable != 0;
+    return HS_OK;
+}
+
+hs_status hs_kernel_timing(hs_sim *s, int which, double *avg_ms, int64_t *launches)
+{
+    if (!s || which < 0 || which >= HS_NUM_KERNELS || !avg_ms) return HS_ERR_ARG;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const size_t nst = s->events.size() / 6;
+    double tot = 0.0;
+    for (size_t k = 0; k < nst; ++k) {
+        hipEvent_t *ev = &s->events[6 * k];
+        float ms = 0.f;
+        hipEvent_t a, b;
+        switch (which) {
+            case HS_KERNEL_INJECT: a = ev[0]; b = ev[1]; break;
+            case HS_KERNEL_MOVE: a = ev[1]; b = ev[2]; break;
+            case HS_KERNEL_SCAN: a = ev[2]; b = ev[3]; break;
+            case HS_KERNEL_SCATTER: a = ev[3]; b = ev[4]; break;
+            case HS_KERNEL_COLLIDE: a = ev[4]; b = ev[5]; break;
+            default: a = ev[0]; b = ev[5]; break;
+        }
+        HIPCHK(s, hipEventElapsedTime(&ms, a, b));
+        tot += ms;
+    }
+    *avg_ms = nst ? tot / (double)nst : 0.0;
+    if (launches) *launches = (int64_t)nst;
+    return HS_OK;
+}
+
+hs_status hs_clear_timing(hs_sim *s)
+{
+    if (!s) return HS_ERR_ARG;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (auto e : s->events) hipEventDestroy(e);
+    s->events.clear();
+    s->timed_steps = 0;
+    return HS_OK;
+}
+
+const char *hs_error_string(const hs_sim *s)
+{
+    if (!s) return "no sim";
+    return s->err.empty() ? "ok" : s->err.c_str();
+}
+
+void hs_destroy(hs_sim *s)
+{
+    if (!s) return;
+    hipStreamSynchronize(s->stream);
+    for (auto e : s->events) hipEventDestroy(e);
+    if (s->gexec) hipGraphExecDestroy(s->gexec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    delete s;
+}
+
+hs_status hs_debug_philox(uint64_t seed, uint32_t stream, uint64_t first_entity, uint32_t step, uint32_t draw,
+                          int64_t n, void *dev_out, void *hip_stream)
+{
+    if (!dev_out || n < 0 || stream > 15) return HS_ERR_ARG;
+    if (n == 0) return HS_OK;
+    Launch::philox(seed, stream, first_entity, step, draw, n, (uint32_t *)dev_out, hip_stream);
+    if (hipGetLastError() != hipSuccess) return HS_ERR_DEVICE;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return HS_ERR_DEVICE;
+    return HS_OK;
+}
+
+}  // extern "C"
