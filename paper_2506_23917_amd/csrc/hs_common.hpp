@@ -49,6 +49,7 @@ struct CaseDev {
     double body_c[3], body_r, body_T;
     double F_N, dt_G, L_cell, sigc0, tau0;
     double in_n, in_u[3], in_T;
+    int32_t bb_lo[3], bb_hi[3];     // cell-index box around the body (1-cell margin)
 };
 
 struct FaceDev {
@@ -72,6 +73,8 @@ struct Globals {
     uint32_t err;
     uint32_t halt;
     int32_t n_inject;        // particles injected this step
+    int32_t n_work;          // particles routed to the body-reflection kernel
+    int32_t n_tiles;         // tiles of the collide kernel this step
     int32_t pad;
     int64_t next_id[kMaxCases];
     int64_t inj_id_base[kMaxCases];
@@ -111,10 +114,11 @@ struct Ctx {
     int32_t *face_cnt, *face_start;
     int32_t *scan_part;
     int32_t *big_list;
+    int32_t *work;                // body worklist (particle indices)
     TraceDev *trace;              // nullptr unless tracing
     Globals *g;
-    int32_t n_cases, n_faces, ncells_total, cap_wave;
-    int32_t cap_block, precision;
+    int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
+    int32_t cap_block, precision, tile_w, pad;
     int64_t capacity;             // total particle capacity of the batch
 };
 
@@ -126,7 +130,7 @@ struct Launch {
     static void init_finish(const Ctx &c, void *stream);
     static void scan_cells(const Ctx &c, void *stream, int build_big);
     static void inject(const Ctx &c, void *stream);
-    static void move_count(const Ctx &c, void *stream);
+    static void move_count(const Ctx &c, void *stream, int any_body);
     static void scatter(const Ctx &c, void *stream);
     static void collide(const Ctx &c, void *stream);
     static void finish_step(const Ctx &c, void *stream);
@@ -138,6 +142,7 @@ void launch_moments_now(const Ctx &c, void *stream, int case_id, int ncells, dou
 void launch_build_big(const Ctx &c, void *stream);
 void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
 int cap_wave();
+int tile_width();
 int cap_block(int precision);
 
 }  // namespace hsk

@@ -63,7 +63,8 @@ template <> struct Real<double> {
     __device__ static double sq(double x) { return sqrt(x); }
     __device__ static double ln(double x) { return log(x); }
     __device__ static double pw(double x, double y) { return pow(x, y); }
-    __device__ static void sc(double x, double *s, double *c) { sincos(x, s, c); }
+    // sin and cos of 2 pi u for u in (0,1), without a large-argument reduction
+    __device__ static void sc2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
     __device__ static double fl(double x) { return floor(x); }
     __device__ static double below_one() { return 0x1.fffffffffffffp-1; }
 };
@@ -72,7 +73,7 @@ template <> struct Real<float> {
     __device__ static float sq(float x) { return sqrtf(x); }
     __device__ static float ln(float x) { return logf(x); }
     __device__ static float pw(float x, float y) { return powf(x, y); }
-    __device__ static void sc(float x, float *s, float *c) { sincosf(x, s, c); }
+    __device__ static void sc2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
     __device__ static float fl(float x) { return floorf(x); }
     __device__ static float below_one() { return 0x1.fffffep-1f; }
 };
@@ -111,7 +112,7 @@ __device__ __forceinline__ bool in_body(const CaseDev &cs, const double X[3])
     if (cs.body == HS_BODY_NONE) return false;
     const int na = body_axes(cs);
     double d2 = 0.0;
-    for (int a = 0; a < na; ++a) {
+    for (int a = 0; a < 3; ++a) if (a < na) {
         const double d = X[a] - cs.body_c[a];
         d2 = d2 + d * d;
     }
@@ -124,11 +125,11 @@ __device__ __forceinline__ bool in_body(const CaseDev &cs, const double X[3])
 __device__ inline int cut_count(const CaseDev &cs, const int ijk[3])
 {
     int full = 1;
-    for (int a = 0; a < cs.dim; ++a) full *= kSub;
+    for (int a = 0; a < 3; ++a) if (a < cs.dim) full *= kSub;
     if (cs.body == HS_BODY_NONE || cs.dim == 0) return full;
     const int na = body_axes(cs);
     double near2 = 0.0, far2 = 0.0;
-    for (int a = 0; a < na; ++a) {
+    for (int a = 0; a < 3; ++a) if (a < na) {
         const double blo = cs.lo[a] + (double)ijk[a] * cs.h[a];
         const double bhi = cs.lo[a] + (double)(ijk[a] + 1) * cs.h[a];
         double dn = 0.0;
@@ -161,7 +162,7 @@ __device__ __forceinline__ double body_hit(const CaseDev &cs, const double X[3],
 {
     const int na = body_axes(cs);
     double a = 0.0, b = 0.0, q = 0.0;
-    for (int k = 0; k < na; ++k) {
+    for (int k = 0; k < 3; ++k) if (k < na) {
         const double d = X[k] - cs.body_c[k];
         a = a + V[k] * V[k];
         b = b + d * V[k];
@@ -185,12 +186,12 @@ __device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, con
     double nr[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
     const int na = body_axes(cs);
     double len = 0.0;
-    for (int k = 0; k < na; ++k) {
+    for (int k = 0; k < 3; ++k) if (k < na) {
         nr[k] = X[k] - cs.body_c[k];
         len = len + nr[k] * nr[k];
     }
     len = sqrt(len);
-    for (int k = 0; k < na; ++k) nr[k] = nr[k] / len;
+    for (int k = 0; k < 3; ++k) if (k < na) nr[k] = nr[k] / len;
     if (cs.body == HS_BODY_CYLINDER) {
         t1[0] = -nr[1];
         t1[1] = nr[0];
@@ -214,7 +215,7 @@ __device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, con
     const double cn = a * sqrt(-log(unid(w.x)));
     const double rr = sqrt(-log(unid(w.z)));
     double sn, cs_;
-    sincos(2.0 * kPi * unid(w.y), &sn, &cs_);
+    sincospi(2.0 * unid(w.y), &sn, &cs_);
     const double ct1 = a * cs_ * rr, ct2 = a * sn * rr;
     for (int k = 0; k < 3; ++k) V[k] = cn * nr[k] + ct1 * t1[k] + ct2 * t2[k];
 }
@@ -238,13 +239,13 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
     cell_ijk(cs, local, ijk);
     if (cs.body != HS_BODY_NONE) {
         double X[3] = {0.0, 0.0, 0.0}, V[3];
-        for (int a = 0; a < dim; ++a) X[a] = cs.lo[a] + ((double)ijk[a] + (double)xr[a]) * cs.h[a];
+        for (int a = 0; a < 3; ++a) if (a < dim) X[a] = cs.lo[a] + ((double)ijk[a] + (double)xr[a]) * cs.h[a];
         for (int a = 0; a < 3; ++a) V[a] = (double)v[a];
         bool bounced = false;
         for (int b = 0;; ++b) {
             const double th = body_hit(cs, X, V, t);
             if (th < 0.0) break;
-            for (int a = 0; a < dim; ++a) X[a] = X[a] + V[a] * th;
+            for (int a = 0; a < 3; ++a) if (a < dim) X[a] = X[a] + V[a] * th;
             t = t - th;
             ms.hits++;
             bounced = true;
@@ -257,7 +258,7 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
             diffuse_reflect(gas, cs, X, draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + b), V);
         }
         if (bounced) {
-            for (int a = 0; a < dim; ++a) {
+            for (int a = 0; a < 3; ++a) if (a < dim) {
                 X[a] = X[a] + V[a] * t;
                 const double hi = cs.lo[a] + (double)cs.n[a] * cs.h[a];
                 if (X[a] < cs.lo[a]) {
@@ -283,7 +284,7 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
             return cell_local(cs, ijk);
         }
     }
-    for (int a = 0; a < dim; ++a) {
+    for (int a = 0; a < 3; ++a) if (a < dim) {
         const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
         P x = xr[a] + v[a] * dth;
         const P f = Real<P>::fl(x);
@@ -305,6 +306,60 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
         if (x >= (P)1) { x = x - (P)1; i += 1; }
         if (i < 0) { i = 0; ms.capped++; }
         if (i > n - 1) { i = n - 1; ms.capped++; }
+        xr[a] = x;
+        ijk[a] = i;
+    }
+    return cell_local(cs, ijk);
+}
+
+// Plain flight (Eq. 4) in cell units for particles that cannot meet the body this step:
+// specular walls by mirroring, removal through open faces.  Returns the new case-local
+// cell, -1 when the particle left, or -2 when the cell box of the straight path overlaps
+// the body's cell box (the caller then runs move_particle on the untouched state).
+// vchg is set when a wall changed the velocity.
+template <typename P>
+__device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v[3], double t, bool full_step,
+                                      bool &vchg)
+{
+    const int dim = cs.dim;
+    int ijk[3];
+    cell_ijk(cs, local, ijk);
+    if (cs.body != HS_BODY_NONE) {
+        const int na = body_axes(cs);
+        bool near = true;
+        for (int a = 0; a < 3; ++a) if (a < na) {
+            const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+            const P x = xr[a] + v[a] * dth;
+            const int i = ijk[a] + (int)Real<P>::fl(x);
+            const int lo = i < ijk[a] ? i : ijk[a], hi = i < ijk[a] ? ijk[a] : i;
+            if (hi < cs.bb_lo[a] || lo > cs.bb_hi[a]) near = false;
+        }
+        if (near) return -2;
+    }
+    vchg = false;
+    for (int a = 0; a < 3; ++a) if (a < dim) {
+        const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+        P x = xr[a] + v[a] * dth;
+        const P f = Real<P>::fl(x);
+        int i = ijk[a] + (int)f;
+        x = x - f;
+        if (x >= (P)1) { x = x - (P)1; i += 1; }
+        const int n = cs.n[a];
+        if (i < 0) {
+            if (cs.bc[2 * a] != HS_BC_SPECULAR) return -1;
+            i = -i - 1;
+            x = (P)1 - x;
+            v[a] = -v[a];
+            vchg = true;
+        } else if (i >= n) {
+            if (cs.bc[2 * a + 1] != HS_BC_SPECULAR) return -1;
+            i = 2 * n - 1 - i;
+            x = (P)1 - x;
+            v[a] = -v[a];
+            vchg = true;
+        }
+        if (x >= (P)1) { x = x - (P)1; i += 1; }
+        i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
         xr[a] = x;
         ijk[a] = i;
     }
@@ -333,7 +388,7 @@ __device__ inline double normal_speed(const CaseDev &cs, uint32_t face, uint32_t
                 if (u1 * Ma < 0.5) y = sqrt(-log(u2));
                 else y = -sqrt(-log(1.0 - u2 * (1.0 - e)));
             } else {
-                y = sqrt(-log(u1)) * cos(2.0 * kPi * u2);
+                y = sqrt(-log(u1)) * cospi(2.0 * u2);
                 if (y <= -s) continue;
             }
             const double zz = y + s;

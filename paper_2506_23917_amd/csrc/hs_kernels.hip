@@ -149,7 +149,7 @@ __device__ inline const StateDev *region_of(const Ctx &C, const CaseDev &cs, con
     for (int r = 0; r < cs.nregions; ++r) {
         const double *b = &C.region_box[6 * (cs.region0 + r)];
         bool in = true;
-        for (int a = 0; a < cs.dim; ++a) {
+        for (int a = 0; a < 3; ++a) if (a < cs.dim) {
             const double ctr = cs.lo[a] + ((double)ijk[a] + 0.5) * cs.h[a];
             if (!(ctr >= b[a] && ctr < b[3 + a])) in = false;
         }
@@ -167,7 +167,7 @@ __global__ void k_init_cells(Ctx C, int fill)
     int ijk[3];
     cell_ijk(cs, lc, ijk);
     int full = 1;
-    for (int a = 0; a < cs.dim; ++a) full *= kSub;
+    for (int a = 0; a < 3; ++a) if (a < cs.dim) full *= kSub;
     const double vfull = cs.h[0] * cs.h[1] * cs.h[2];
     double vol = vfull;
     if (cs.body != HS_BODY_NONE && cs.dim > 0) vol = (double)cut_count(cs, ijk) / (double)full * vfull;
@@ -212,7 +212,7 @@ __global__ void k_init_fill(Ctx C)
                 const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, (uint32_t)(1 + 128 * q + t));
                 const uint32_t ww[3] = {w.x, w.y, w.z};
                 double X[3] = {0.0, 0.0, 0.0};
-                for (int d = 0; d < cs.dim; ++d) {
+                for (int d = 0; d < 3; ++d) if (d < cs.dim) {
                     xr[d] = unid(ww[d]);
                     X[d] = cs.lo[d] + ((double)ijk[d] + xr[d]) * cs.h[d];
                 }
@@ -225,7 +225,7 @@ __global__ void k_init_fill(Ctx C)
                         for (int s0 = 0; s0 < kSub && !placed; ++s0) {
                             const int sub[3] = {s0, s1, s2};
                             double X[3] = {0.0, 0.0, 0.0};
-                            for (int d = 0; d < cs.dim; ++d) {
+                            for (int d = 0; d < 3; ++d) if (d < cs.dim) {
                                 xr[d] = ((double)sub[d] + 0.5) / kSub;
                                 X[d] = cs.lo[d] + ((double)ijk[d] + xr[d]) * cs.h[d];
                             }
@@ -235,8 +235,8 @@ __global__ void k_init_fill(Ctx C)
         }
         const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, (uint32_t)(1 + 128 * q + 64));
         double s1, c1, s3, c3;
-        sincos(2.0 * kPi * unid(w.x), &s1, &c1);
-        sincos(2.0 * kPi * unid(w.z), &s3, &c3);
+        sincospi(2.0 * unid(w.x), &s1, &c1);
+        sincospi(2.0 * unid(w.z), &s3, &c3);
         const double r2 = sqrt(-log(unid(w.y))), r4 = sqrt(-log(unid(w.w)));
         const double C3[3] = {a * c1 * r2, a * c3 * r4, a * s3 * r4};
         const size_t i = (size_t)s + q;
@@ -369,6 +369,7 @@ __global__ void k_scan_final(Ctx C, int build_big, int nparts)
         const int all = C.scan_part[nparts];
         C.cstart[C.ncells_total] = all;
         C.g->n_new = all;
+        C.g->n_tiles = (int)(((long long)all + 4ll * C.ncells_total + C.tile_w - 1) / C.tile_w);
     }
 }
 
@@ -451,7 +452,7 @@ __global__ void k_inject_fill(Ctx C)
         const W4 wv = draw(cs, kStreamFace, (uint64_t)fd.local, st, base + 1);
         const double rr = sqrt(-log(unid(wv.y)));
         double sn2, cs2;
-        sincos(2.0 * kPi * unid(wv.x), &sn2, &cs2);
+        sincospi(2.0 * unid(wv.x), &sn2, &cs2);
         v[t1] = cs.in_u[t1] + ath * cs2 * rr;
         v[t2] = cs.in_u[t2] + ath * sn2 * rr;
         int used;
@@ -475,25 +476,37 @@ __global__ void k_inject_fill(Ctx C)
 // Free transport and cell counts (Step 2 -> Step 3 histogram)
 // ------------------------------------------------------------------------------------
 
-template <typename P>
-__device__ __forceinline__ int transport(const Ctx &C, const Parts<P> &S, int i, int g, const CaseDev &cs,
-                                         int n_live, uint32_t st, P xr[3], P v[3], int64_t &id, MoveStats &ms)
+// Wave-aggregated slot allocation: one atomic per distinct destination cell in the wave;
+// returns this lane's slot in its cell (order within a cell is arbitrary; the collide
+// kernels restore the stable order).
+__device__ __forceinline__ int wave_slot(int32_t *count, int nc, bool want)
 {
-    for (int a = 0; a < cs.dim; ++a) xr[a] = S.pos[a][i];
-    for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
-    if (cs.dim == 0) return g;
-    const bool full = i < n_live;
-    double t = cs.dt_G;
-    if (!full) {
-        if (id < 0) id = S.id[i];
-        t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(want);
+    int leader = 0, rank = 0, cnt = 0;
+    // group the lanes by destination cell (ALU only), then one batched atomic per wave
+    while (pending) {
+        const int l0 = __ffsll((long long)pending) - 1;
+        const int c0 = __shfl(nc, l0, 64);
+        const unsigned long long same = __ballot(want && nc == c0) & pending;
+        if (lane == l0) cnt = __popcll(same);
+        if ((same >> lane) & 1ull) {
+            leader = l0;
+            rank = __popcll(same & ((1ull << lane) - 1ull));
+        }
+        pending &= ~same;
     }
-    const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms);
-    return nl >= 0 ? cs.cell0 + nl : -1;
+    int old = 0;
+    if (cnt) old = atomicAdd(&count[nc], cnt);
+    old = __shfl(old, leader, 64);
+    return old + rank;
 }
 
+// Every particle: straight flight with specular / open walls, the moved position written
+// back in place (velocity too when a wall changed it), new cell and slot recorded.
+// Particles whose path may meet the body go to a worklist for k_move_body.
 template <typename P>
-__global__ __launch_bounds__(kBlock) void k_move_count(Ctx C)
+__global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
 {
     Globals *G = C.g;
     if (G->halt) return;
@@ -501,34 +514,95 @@ __global__ __launch_bounds__(kBlock) void k_move_count(Ctx C)
     const uint32_t st = (uint32_t)G->step;
     const Parts<P> S(C.buf[G->step & 1]);
     const int stride = gridDim.x * blockDim.x;
-    const int lane = threadIdx.x & 63;
     for (int base = blockIdx.x * blockDim.x; base < n_total; base += stride) {
         const int i = base + threadIdx.x;
         const bool valid = i < n_total;
         int nc = -1, cid = 0;
-        MoveStats ms{0, 0};
+        bool to_body = false;
         if (valid) {
             const int g = S.cell[i];
             cid = case_of(C, g);
             const CaseDev &cs = C.cases[cid];
+            if (cs.dim == 0) {
+                nc = g;
+            } else {
+                P xr[3], v[3];
+                for (int a = 0; a < 3; ++a) if (a < cs.dim) xr[a] = S.pos[a][i];
+                for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+                const bool full = i < n_live;
+                double t = cs.dt_G;
+                if (!full) t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
+                bool vchg = false;
+                const int nl = flight<P>(cs, g - cs.cell0, xr, v, t, full, vchg);
+                if (nl == -2) {
+                    to_body = true;
+                } else if (nl >= 0) {
+                    nc = cs.cell0 + nl;
+                    for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
+                    if (vchg)
+                        for (int a = 0; a < 3; ++a) if (a < cs.dim) S.vel[a][i] = v[a];
+                }
+            }
+        }
+        // worklist of body candidates
+        {
+            const int lane = threadIdx.x & 63;
+            const unsigned long long m = __ballot(to_body);
+            if (m) {
+                int basew = 0;
+                const int leader = __ffsll((long long)m) - 1;
+                if (lane == leader) basew = atomicAdd(&G->n_work, __popcll(m));
+                basew = __shfl(basew, leader, 64);
+                if (to_body) C.work[basew + __popcll(m & ((1ull << lane) - 1ull))] = i;
+            }
+        }
+        const bool counted = valid && !to_body && nc >= 0;
+        if (valid && !to_body) C.newcell[i] = nc;
+        const int myslot = wave_slot(C.count, nc, counted);
+        if (counted) C.slot[i] = myslot;
+        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, valid && !to_body && nc < 0);
+    }
+}
+
+// Worklist particles: the full move with FP64 body reflections (diffuse wall).
+template <typename P>
+__global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
+{
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int nw = G->n_work, n_live = G->n_live;
+    const uint32_t st = (uint32_t)G->step;
+    const Parts<P> S(C.buf[G->step & 1]);
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < nw; base += stride) {
+        const int w = base + threadIdx.x;
+        const bool valid = w < nw;
+        int nc = -1, cid = 0, i = 0;
+        MoveStats ms{0, 0};
+        if (valid) {
+            i = C.work[w];
+            const int g = S.cell[i];
+            cid = case_of(C, g);
+            const CaseDev &cs = C.cases[cid];
             P xr[3], v[3];
+            for (int a = 0; a < 3; ++a) if (a < cs.dim) xr[a] = S.pos[a][i];
+            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+            const bool full = i < n_live;
             int64_t id = -1;
-            nc = transport<P>(C, S, i, g, cs, n_live, st, xr, v, id, ms);
+            double t = cs.dt_G;
+            if (!full) {
+                id = S.id[i];
+                t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
+            }
+            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms);
+            if (nl >= 0) {
+                nc = cs.cell0 + nl;
+                for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
+                for (int a = 0; a < 3; ++a) S.vel[a][i] = v[a];
+            }
             C.newcell[i] = nc;
         }
-        // wave-aggregated slot allocation in the destination cell
-        unsigned long long pending = __ballot(valid && nc >= 0);
-        int myslot = 0;
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int c0 = __shfl(nc, leader, 64);
-            const unsigned long long same = __ballot(valid && nc == c0) & pending;
-            int old = 0;
-            if (lane == leader) old = atomicAdd(&C.count[c0], __popcll(same));
-            old = __shfl(old, leader, 64);
-            if ((same >> lane) & 1ull) myslot = old + __popcll(same & ((1ull << lane) - 1ull));
-            pending &= ~same;
-        }
+        const int myslot = wave_slot(C.count, nc, valid && nc >= 0);
         if (valid && nc >= 0) C.slot[i] = myslot;
         wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, valid && nc < 0);
         wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_WALL_HITS, ms.hits, valid);
@@ -548,119 +622,67 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Ctx C)
 }
 
 // ------------------------------------------------------------------------------------
-// Collision stage (Step 3 moments, Step 4, Step 5) for one cell
+// Collision stage (Step 3 moments, Step 4, Step 5)
 // ------------------------------------------------------------------------------------
 
 struct CellCounts {
     long long cand, acc, relax, ar, arcap, skipped;
 };
 
-// Sort `a[0..p2)` ascending in LDS with a bitonic network (p2 a power of two).
-template <int TEAM>
-__device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
-{
-    for (int k = 2; k <= p2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < p2; i += TEAM) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const int32_t x = a[i], y = a[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        a[i] = y;
-                        a[ixj] = x;
-                    }
-                }
-            }
-            team_sync<TEAM>();
-        }
-    }
-}
+// Per-cell results of the moments / split / NTC stage, kept in LDS between stages.
+template <typename P>
+struct CellSlot {
+    double *U;      // [3] Step (3) mean velocity
+    double *T;      // Step (3) temperature
+    double *pr;     // relaxation probability (0 when the cell is inactive)
+    double *obs;    // largest sigma c seen by the NTC chain
+    int *act;       // collision stage active
+    P *par;         // [7] Q[3], p, RT, sqrt(2RT), A_max for the Shakhov draws
+};
 
-template <typename P, int TEAM>
-__device__ void collide_cell(const Ctx &C, int g, int tid, int32_t *s_src, P *s_v, int cap, double *red,
-                             long long *redl, int *redi, CellCounts &cc)
+// Sequential per-cell stage (one lane, particles in sorted order in LDS):
+// Eq. 31 moments, Eq. 10 / 25-28 timescales and split, NTC chain (Eq. 5-9).
+template <typename P>
+__device__ void cell_stage_a(const Ctx &C, const CaseDev &cs, int g, uint32_t st, P *vx, P *vy, P *vz, int n,
+                             const CellSlot<P> &o, CellCounts &cc)
 {
-    Globals *G = C.g;
-    const int cid = case_of(C, g);
-    const CaseDev &cs = C.cases[cid];
     const GasDev &gas = C.gas;
-    const int lc = g - cs.cell0;
-    const int64_t step = G->step;
-    const uint32_t st = (uint32_t)step;
-    const Parts<P> S(C.buf[step & 1]);
-    const Parts<P> D(C.buf[(step & 1) ^ 1]);
-    const int s = C.cstart[g];
-    const int n = C.cstart[g + 1] - s;
-    const bool sampling = step >= cs.n_steady;
-    const bool tracing = C.trace != nullptr;
-    TraceDev tr = {};
-    tr.n = n;
-    if (n == 0) {
-        if (tracing && tid == 0) C.trace[g] = tr;
-        return;
-    }
-    P *vx = s_v, *vy = s_v + cap, *vz = s_v + 2 * cap;
-
-    // sources of this cell in their previous array order
-    const bool use_perm = C.perm != nullptr;
-    if (use_perm) {
-        int p2 = 1;
-        while (p2 < n) p2 <<= 1;
-        for (int k = tid; k < p2; k += TEAM) s_src[k] = k < n ? C.perm[s + k] : 0x7fffffff;
-        team_sync<TEAM>();
-        bool unsorted = false;
-        for (int k = tid; k + 1 < n; k += TEAM) unsorted |= s_src[k] > s_src[k + 1];
-        if (team_any<TEAM>(unsorted, redi)) bitonic_sort<TEAM>(s_src, p2, tid);
-    }
-    // gather, re-run the move, write position / cell / id of the sorted state
-    const int n_live = G->n_live;
-    bool bad = false;
-    for (int k = tid; k < n; k += TEAM) {
-        const int i = use_perm ? s_src[k] : s + k;
-        P xr[3], v[3];
-        int64_t id = S.id[i];
-        MoveStats ms{0, 0};
-        if (use_perm) {
-            const int nc = transport<P>(C, S, i, S.cell[i], cs, n_live, st, xr, v, id, ms);
-            bad |= nc != g;
-        } else {
-            for (int a = 0; a < cs.dim; ++a) xr[a] = S.pos[a][i];
-            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
-        }
-        const size_t o = (size_t)s + k;
-        for (int a = 0; a < cs.dim; ++a) D.pos[a][o] = xr[a];
-        D.cell[o] = g;
-        D.id[o] = id;
-        vx[k] = v[0];
-        vy[k] = v[1];
-        vz[k] = v[2];
-    }
-    if (bad) raise_error(G, kErrState);
-    team_sync<TEAM>();
-
-    // Eq. 31 moments: mean first, then central sums (FP64 across the team)
-    double m1[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = tid; k < n; k += TEAM) {
+    TraceDev *tr = C.trace ? &C.trace[g] : nullptr;
+    double s1[3] = {0.0, 0.0, 0.0}, s2 = 0.0;
+    for (int k = 0; k < n; ++k) {
         const double a = (double)vx[k], b = (double)vy[k], c = (double)vz[k];
-        m1[0] = m1[0] + a;
-        m1[1] = m1[1] + b;
-        m1[2] = m1[2] + c;
-        m1[3] = m1[3] + (a * a + b * b + c * c);
+        s1[0] = s1[0] + a;
+        s1[1] = s1[1] + b;
+        s1[2] = s1[2] + c;
+        s2 = s2 + (a * a + b * b + c * c);
     }
-    team_sum<TEAM, 4>(m1, red);
-    for (int a = 0; a < 4; ++a) tr.pre_sum[a] = m1[a];
-    const double U[3] = {m1[0] / (double)n, m1[1] / (double)n, m1[2] / (double)n};
-    double m2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tr) {
+        *tr = TraceDev{};
+        tr->n = n;
+        tr->pre_sum[0] = s1[0];
+        tr->pre_sum[1] = s1[1];
+        tr->pre_sum[2] = s1[2];
+        tr->pre_sum[3] = s2;
+    }
+    double U[3];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a) U[a] = n > 0 ? s1[a] / (double)n : 0.0;
+    o.U[0] = U[0];
+    o.U[1] = U[1];
+    o.U[2] = U[2];
+    *o.T = 0.0;
+    *o.pr = 0.0;
+    *o.obs = 0.0;
+    *o.act = 0;
+    if (n < 2) return;
+    double c2s = 0.0, c3s[3] = {0.0, 0.0, 0.0};
     if constexpr (sizeof(P) == 4) {
-        // FP32 peculiar velocities and products with compensated (TwoSum) per-thread sums,
-        // FP64 across the team.  C = (c - U_f) - (U - U_f): the first difference is exact
-        // for c near U, the second removes the rounding of U to FP32.
+        // FP32 peculiar velocities and products, compensated (TwoSum) sums
         const float uf[3] = {(float)U[0], (float)U[1], (float)U[2]};
         const float df[3] = {(float)(U[0] - (double)uf[0]), (float)(U[1] - (double)uf[1]),
                              (float)(U[2] - (double)uf[2])};
         float sum[4] = {0.f, 0.f, 0.f, 0.f}, cmp[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int k = tid; k < n; k += TEAM) {
+        for (int k = 0; k < n; ++k) {
             const float cx = ((float)vx[k] - uf[0]) - df[0];
             const float cy = ((float)vy[k] - uf[1]) - df[1];
             const float cz = ((float)vz[k] - uf[2]) - df[2];
@@ -674,227 +696,224 @@ __device__ void collide_cell(const Ctx &C, int g, int tid, int32_t *s_src, P *s_
                 sum[j] = t;
             }
         }
-        for (int j = 0; j < 4; ++j) m2[j] = (double)sum[j] + (double)cmp[j];
-        team_sum<TEAM, 4>(m2, red);
+        c2s = (double)sum[0] + (double)cmp[0];
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) c3s[a] = (double)sum[1 + a] + (double)cmp[1 + a];
     } else {
-        for (int k = tid; k < n; k += TEAM) {
+        for (int k = 0; k < n; ++k) {
             const double cx = vx[k] - U[0], cy = vy[k] - U[1], cz = vz[k] - U[2];
             const double c2 = cx * cx + cy * cy + cz * cz;
-            m2[0] = m2[0] + c2;
-            m2[1] = m2[1] + c2 * cx;
-            m2[2] = m2[2] + c2 * cy;
-            m2[3] = m2[3] + c2 * cz;
+            c2s = c2s + c2;
+            c3s[0] = c3s[0] + c2 * cx;
+            c3s[1] = c3s[1] + c2 * cy;
+            c3s[2] = c3s[2] + c2 * cz;
         }
-        team_sum<TEAM, 4>(m2, red);
     }
     const double vol = C.vol[g];
-    double T = 0.0, Q[3] = {0.0, 0.0, 0.0};
-    if (n >= 2) {
-        if constexpr (sizeof(P) == 4) {
-            // FP32-mixed: T from the FP64 sums sum c and sum |c|^2, the form the FP64
-            // rescale restores exactly (energy n|U|^2 + 3k(n-1)T/m)
-            const double e = m1[3] - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]) / (double)n;
-            T = gas.m * e / (3.0 * kKB * (double)(n - 1));
-        } else {
-            T = gas.m * m2[0] / (3.0 * kKB * (double)(n - 1));
-        }
+    double T;
+    if constexpr (sizeof(P) == 4) {
+        // FP32-mixed: T from the FP64 sums, the form the FP64 rescale restores exactly
+        T = gas.m * (s2 - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)n) /
+            (3.0 * kKB * (double)(n - 1));
+    } else {
+        T = gas.m * c2s / (3.0 * kKB * (double)(n - 1));
     }
+    *o.T = T;
+    double Q[3] = {0.0, 0.0, 0.0};
     if (n >= 3 && vol > 0.0) {
         const double nd = (double)n * cs.F_N / vol;
         const double f = nd * (double)n / ((double)(n - 1) * (double)(n - 2));
-        for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * m2[1 + a];
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * c3s[a];
     }
-    if (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2])) raise_error(G, kErrNumeric);
-    const bool active = n >= 2 && T > 0.0 && vol > 0.0;
-    if (!active && n >= 2) cc.skipped++;
-
-    if (active) {
-        // Eq. 10, 25-28, 16, 5: timescales and sub-step lengths in FP64
-        const double nd = (double)n * cs.F_N / vol;
-        const double p = nd * kKB * T;
-        const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
-        const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
-        double dtc;
-        if (cs.dim == 0) {
-            dtc = dtG;
-        } else {
-            const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-            dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
-        }
-        double dtD, dtS;
-        if (dtc <= tau) {
-            dtD = dtG;
-            dtS = 0.0;
-        } else {
-            dtD = (tau / dtc) * dtG;
-            dtS = dtG - dtD;
-        }
-        const double p_relax = -expm1(-dtS / tau);
-        tr.T = T;
-        tr.tau = tau;
-        tr.dt_dsmc = dtD;
-        tr.p_relax = p_relax;
-        const double scmax = C.sigc[g];
-        const double M = 0.5 * (double)n * (double)(n - 1) * cs.F_N * scmax * dtD / vol;
-        const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)lc, st, 0).x);
-        long long ncol = 0;
-        if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
-        else raise_error(G, kErrNumeric);
-
-        // NTC chain (Eq. 5-9), sequential in the candidate index, one thread
-        if (tid == 0) {
-            const P scm = (P)scmax;
-            const P K = (P)gas.K_vhs, ex = (P)gas.vhs_exp;
-            double obs = 0.0;
-            long long nacc = 0;
-            uint64_t hash = 0;
-            for (long long k = 0; k < ncol; ++k) {
-                const W4 w = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(1 + 2 * k));
-                const uint32_t i = unidx(w.x, (uint32_t)n);
-                uint32_t j = unidx(w.y, (uint32_t)(n - 1));
-                if (j >= i) ++j;
-                const P ua = Real<P>::uni(w.z);
-                const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
-                const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
-                const P sc = K * Real<P>::pw(cr, ex);
-                if ((double)sc > obs) obs = (double)sc;
-                if (ua < sc / scm) {
-                    const W4 w2 = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(2 + 2 * k));
-                    const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
-                    const P schi = Real<P>::sq((P)1 - cchi * cchi);
-                    P sth, cth;
-                    Real<P>::sc((P)(2.0 * kPi) * Real<P>::uni(w2.y), &sth, &cth);
-                    const P om[3] = {cchi, schi * cth, schi * sth};
-                    P *vv[3] = {vx, vy, vz};
-                    for (int a = 0; a < 3; ++a) {
-                        const P sum = vv[a][i] + vv[a][j];
-                        vv[a][i] = (P)0.5 * (sum - cr * om[a]);
-                        vv[a][j] = (P)0.5 * (sum + cr * om[a]);
-                    }
-                    ++nacc;
-                    hash ^= (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
-                }
+    if (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2])) raise_error(C.g, kErrNumeric);
+    if (!(T > 0.0 && vol > 0.0)) {
+        cc.skipped++;
+        return;
+    }
+    *o.act = 1;
+    const double nd = (double)n * cs.F_N / vol;
+    const double p = nd * kKB * T;
+    const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
+    const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+    double dtc;
+    if (cs.dim == 0) {
+        dtc = dtG;
+    } else {
+        const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+        dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+    }
+    double dtD, dtS;
+    if (dtc <= tau) {
+        dtD = dtG;
+        dtS = 0.0;
+    } else {
+        dtD = (tau / dtc) * dtG;
+        dtS = dtG - dtD;
+    }
+    const double p_relax = -expm1(-dtS / tau);
+    *o.pr = p_relax;
+    double a_max = 1.0;
+    if (p_relax > 0.0) {
+        const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+        a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
+        o.par[0] = (P)Q[0];
+        o.par[1] = (P)Q[1];
+        o.par[2] = (P)Q[2];
+        o.par[3] = (P)p;
+        o.par[4] = (P)(gas.R * T);
+        o.par[5] = (P)sqrt(2.0 * gas.R * T);
+        o.par[6] = (P)a_max;
+    }
+    if (tr) {
+        tr->T = T;
+        tr->tau = tau;
+        tr->dt_dsmc = dtD;
+        tr->p_relax = p_relax;
+        tr->a_max = p_relax > 0.0 ? a_max : 0.0;
+    }
+    // NTC (Eq. 5-9): candidates in index order, (sigma c)_max fixed during the step
+    const int lc = g - cs.cell0;
+    const double scmax = C.sigc[g];
+    const double M = 0.5 * (double)n * (double)(n - 1) * cs.F_N * scmax * dtD / vol;
+    const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)lc, st, 0).x);
+    long long ncol = 0;
+    if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
+    else raise_error(C.g, kErrNumeric);
+    const P scm = (P)scmax;
+    const P K = (P)gas.K_vhs, ex = (P)gas.vhs_exp;
+    double obs = 0.0;
+    long long nacc = 0;
+    uint64_t hash = 0;
+    for (long long k = 0; k < ncol; ++k) {
+        const W4 w = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(1 + 2 * k));
+        const uint32_t i = unidx(w.x, (uint32_t)n);
+        uint32_t j = unidx(w.y, (uint32_t)(n - 1));
+        if (j >= i) ++j;
+        const P ua = Real<P>::uni(w.z);
+        const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
+        const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
+        const P sc = K * Real<P>::pw(cr, ex);
+        if ((double)sc > obs) obs = (double)sc;
+        if (ua < sc / scm) {
+            const W4 w2 = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(2 + 2 * k));
+            const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
+            const P schi = Real<P>::sq((P)1 - cchi * cchi);
+            P sth, cth;
+            Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
+            const P om[3] = {cchi, schi * cth, schi * sth};
+            P *vv[3] = {vx, vy, vz};
+            #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const P sum = vv[a][i] + vv[a][j];
+                vv[a][i] = (P)0.5 * (sum - cr * om[a]);
+                vv[a][j] = (P)0.5 * (sum + cr * om[a]);
             }
-            if (obs > C.sigc[g]) C.sigc[g] = obs;
-            tr.ncol = ncol;
-            tr.nacc = nacc;
-            tr.acc_hash = hash;
-            cc.cand += ncol;
-            cc.acc += nacc;
+            ++nacc;
+            hash ^= (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
         }
-        team_sync<TEAM>();
+    }
+    *o.obs = obs;
+    if (tr) {
+        tr->ncol = ncol;
+        tr->nacc = nacc;
+        tr->acc_hash = hash;
+    }
+    cc.cand += ncol;
+    cc.acc += nacc;
+}
 
-        // SP-Shakhov (Eq. 16-18) from the Step (3) moments
-        long long nrel = 0, nar = 0, ncap = 0;
-        if (p_relax > 0.0) {
-            const double RT = gas.R * T;
-            const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
-            const double a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(RT));
-            tr.a_max = a_max;
-            const P am = (P)a_max, one_m_pr = (P)(1.0 - gas.Pr), pP = (P)p, RTP = (P)RT;
-            const P ath = (P)sqrt(2.0 * gas.R * T);
-            const P QP[3] = {(P)Q[0], (P)Q[1], (P)Q[2]};
-            for (int k = tid; k < n; k += TEAM) {
-                const int64_t id = D.id[(size_t)s + k];
-                if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < p_relax)) continue;
-                ++nrel;
-                P Cv[3];
-                int used = -kMaxShakhov;
-                for (int a = 0; a < kMaxShakhov; ++a) {
-                    const W4 w = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a);
-                    const W4 w5 = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a + 1);
-                    P s1, c1, s3, c3;
-                    Real<P>::sc((P)(2.0 * kPi) * Real<P>::uni(w.x), &s1, &c1);
-                    Real<P>::sc((P)(2.0 * kPi) * Real<P>::uni(w.z), &s3, &c3);
-                    const P r2 = Real<P>::sq(-Real<P>::ln(Real<P>::uni(w.y)));
-                    const P r4 = Real<P>::sq(-Real<P>::ln(Real<P>::uni(w.w)));
-                    Cv[0] = ath * c1 * r2;
-                    Cv[1] = ath * c3 * r4;
-                    Cv[2] = ath * s3 * r4;
-                    const P c2 = Cv[0] * Cv[0] + Cv[1] * Cv[1] + Cv[2] * Cv[2];
-                    const P qc = QP[0] * Cv[0] + QP[1] * Cv[1] + QP[2] * Cv[2];
-                    const P A = (P)1 + one_m_pr * qc / ((P)5 * pP * RTP) * (c2 / RTP - (P)5);
-                    if (A / am > Real<P>::uni(w5.x)) {
-                        used = a + 1;
-                        break;
-                    }
-                }
-                if (used < 0) {
-                    ++ncap;
-                    used = -used;
-                }
-                nar += used;
-                vx[k] = (P)(U[0] + (double)Cv[0]);
-                vy[k] = (P)(U[1] + (double)Cv[1]);
-                vz[k] = (P)(U[2] + (double)Cv[2]);
-            }
-        }
-        long long sl[3] = {nrel, nar, ncap};
-        team_sum_i<TEAM, 3>(sl, redl);
-        tr.nrelax = sl[0];
-        tr.ar_attempts = sl[1];
-        tr.ar_cap = sl[2];
-        if (tid == 0) {
-            cc.relax += sl[0];
-            cc.ar += sl[1];
-            cc.arcap += sl[2];
-        }
-        team_sync<TEAM>();
+// Shakhov acceptance-rejection draw (Eq. 17-18) for one relaxing particle.
+template <typename P>
+__device__ __forceinline__ int shakhov_draw(const CaseDev &cs, int64_t id, uint32_t st, const P *par, P one_m_pr,
+                                            P Cv[3])
+{
+    const P ath = par[5], p = par[3], RT = par[4], am = par[6];
+    for (int a = 0; a < kMaxShakhov; ++a) {
+        const W4 w = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a);
+        const W4 w5 = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a + 1);
+        P s1, c1, s3, c3;
+        Real<P>::sc2pi(Real<P>::uni(w.x), &s1, &c1);
+        Real<P>::sc2pi(Real<P>::uni(w.z), &s3, &c3);
+        const P r2 = Real<P>::sq(-Real<P>::ln(Real<P>::uni(w.y)));
+        const P r4 = Real<P>::sq(-Real<P>::ln(Real<P>::uni(w.w)));
+        Cv[0] = ath * c1 * r2;
+        Cv[1] = ath * c3 * r4;
+        Cv[2] = ath * s3 * r4;
+        const P c2 = Cv[0] * Cv[0] + Cv[1] * Cv[1] + Cv[2] * Cv[2];
+        const P qc = par[0] * Cv[0] + par[1] * Cv[1] + par[2] * Cv[2];
+        const P A = (P)1 + one_m_pr * qc / ((P)5 * p * RT) * (c2 / RT - (P)5);
+        if (A / am > Real<P>::uni(w5.x)) return a + 1;
+    }
+    return -kMaxShakhov;
+}
 
-        // Eq. 19 conservation rescale in FP64 with the Step (3) U and T
+// Sequential per-cell stage after the Shakhov draws: Eq. 19 rescale in FP64 with the
+// Step (3) U, T; Step (5) sums; (sigma c)_max; trace record.
+template <typename P>
+__device__ void cell_stage_c(const Ctx &C, int g, bool sampling, P *vx, P *vy, P *vz, int n,
+                             const CellSlot<P> &o, const int32_t *rel)
+{
+    TraceDev *tr = C.trace ? &C.trace[g] : nullptr;
+    double post[4] = {0.0, 0.0, 0.0, 0.0};
+    bool rescaled = false;
+    if (*o.act) {
         double r1[3] = {0.0, 0.0, 0.0};
-        for (int k = tid; k < n; k += TEAM) {
+        for (int k = 0; k < n; ++k) {
             r1[0] = r1[0] + (double)vx[k];
             r1[1] = r1[1] + (double)vy[k];
             r1[2] = r1[2] + (double)vz[k];
         }
-        team_sum<TEAM, 3>(r1, red);
         const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
-        double r2[1] = {0.0};
-        for (int k = tid; k < n; k += TEAM) {
+        double r2 = 0.0;
+        for (int k = 0; k < n; ++k) {
             const double cx = (double)vx[k] - Up[0], cy = (double)vy[k] - Up[1], cz = (double)vz[k] - Up[2];
-            r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
+            r2 = r2 + (cx * cx + cy * cy + cz * cz);
         }
-        team_sum<TEAM, 1>(r2, red);
-        const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(n - 1));
-        double post[4] = {0.0, 0.0, 0.0, 0.0};
+        const double Tp = C.gas.m * r2 / (3.0 * kKB * (double)(n - 1));
         if (Tp > 0.0) {
-            const double f = sqrt(T / Tp);
-            for (int k = tid; k < n; k += TEAM) {
-                const double a = U[0] + ((double)vx[k] - Up[0]) * f;
-                const double b = U[1] + ((double)vy[k] - Up[1]) * f;
-                const double c = U[2] + ((double)vz[k] - Up[2]) * f;
-                post[0] = post[0] + a;
-                post[1] = post[1] + b;
-                post[2] = post[2] + c;
-                post[3] = post[3] + (a * a + b * b + c * c);
+            rescaled = true;
+            const double f = sqrt(*o.T / Tp);
+            const double U0 = o.U[0], U1 = o.U[1], U2 = o.U[2];
+            for (int k = 0; k < n; ++k) {
+                const double a = U0 + ((double)vx[k] - Up[0]) * f;
+                const double b = U1 + ((double)vy[k] - Up[1]) * f;
+                const double c = U2 + ((double)vz[k] - Up[2]) * f;
+                if (tr) {
+                    post[0] = post[0] + a;
+                    post[1] = post[1] + b;
+                    post[2] = post[2] + c;
+                    post[3] = post[3] + (a * a + b * b + c * c);
+                }
                 vx[k] = (P)a;
                 vy[k] = (P)b;
                 vz[k] = (P)c;
             }
         }
-        if (tracing) {
-            if (Tp > 0.0) {
-                team_sum<TEAM, 4>(post, red);
-                for (int a = 0; a < 4; ++a) tr.post_sum[a] = post[a];
-            } else {
-                for (int a = 0; a < 4; ++a) tr.post_sum[a] = 0.0;
+        if (*o.obs > C.sigc[g]) C.sigc[g] = *o.obs;
+    }
+    if (tr) {
+        if (!rescaled) {
+            for (int k = 0; k < n; ++k) {
+                const double a = (double)vx[k], b = (double)vy[k], c = (double)vz[k];
+                post[0] = post[0] + a;
+                post[1] = post[1] + b;
+                post[2] = post[2] + c;
+                post[3] = post[3] + (a * a + b * b + c * c);
             }
         }
-        team_sync<TEAM>();
+        #pragma unroll
+        for (int a = 0; a < 4; ++a) tr->post_sum[a] = post[a];
+        tr->nrelax = rel[0];
+        tr->ar_attempts = rel[1];
+        tr->ar_cap = rel[2];
     }
-
-    // write velocities; Step (5) sums of the final state
-    double sm[12];
-    for (int j = 0; j < 12; ++j) sm[j] = 0.0;
-    for (int k = tid; k < n; k += TEAM) {
-        const size_t o = (size_t)s + k;
-        const P a = vx[k], b = vy[k], c = vz[k];
-        D.vel[0][o] = a;
-        D.vel[1][o] = b;
-        D.vel[2][o] = c;
-        if (sampling || (tracing && !active)) {
-            const double x = (double)a, y = (double)b, z = (double)c;
+    if (sampling) {
+        double sm[12];
+        #pragma unroll
+        for (int j = 0; j < 12; ++j) sm[j] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double x = (double)vx[k], y = (double)vy[k], z = (double)vz[k];
             const double c2 = x * x + y * y + z * z;
             sm[0] = sm[0] + x;
             sm[1] = sm[1] + y;
@@ -909,23 +928,11 @@ __device__ void collide_cell(const Ctx &C, int g, int tid, int32_t *s_src, P *s_
             sm[10] = sm[10] + c2 * y;
             sm[11] = sm[11] + c2 * z;
         }
+        double *A = &C.acc[13 * (size_t)g];
+        A[0] += (double)n;
+        #pragma unroll
+        for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
     }
-    if (sampling || (tracing && !active)) team_sum<TEAM, 12>(sm, red);
-    if (tracing && !active) {
-        tr.post_sum[0] = sm[0];
-        tr.post_sum[1] = sm[1];
-        tr.post_sum[2] = sm[2];
-        tr.post_sum[3] = sm[3] + sm[4] + sm[5];
-    }
-    if (tid == 0) {
-        if (sampling) {
-            double *A = &C.acc[13 * (size_t)g];
-            A[0] += (double)n;
-            for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
-        }
-        if (tracing) C.trace[g] = tr;
-    }
-    team_sync<TEAM>();
 }
 
 __device__ __forceinline__ void flush_counts(const Ctx &C, int cid, CellCounts &cc)
@@ -940,54 +947,781 @@ __device__ __forceinline__ void flush_counts(const Ctx &C, int cid, CellCounts &
     cc = CellCounts{0, 0, 0, 0, 0, 0};
 }
 
-// One wavefront per cell of at most CAPW particles; four wavefronts per block.
-template <typename P, int CAPW>
-__global__ __launch_bounds__(kBlock) void k_collide_wave(Ctx C)
+// ---- wavefront-tile collide kernel ----------------------------------------------------
+
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ int wave_incl_scan(int v)
 {
-    if (C.g->halt) return;
-    __shared__ int32_t s_src[4][CAPW];
-    __shared__ P s_v[4][3 * CAPW];
-    __shared__ double red[4][16];
-    __shared__ long long redl[4][8];
-    __shared__ int redi[4][2];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nwaves = gridDim.x * 4;
-    CellCounts cc{0, 0, 0, 0, 0, 0};
-    int cur_case = -1;
-    for (int g = blockIdx.x * 4 + w; g < C.ncells_total; g += nwaves) {
-        const int n = C.cstart[g + 1] - C.cstart[g];
-        if (n > CAPW) continue;
-        const int cid = case_of(C, g);
-        if (cid != cur_case) {
-            if (cur_case >= 0 && lane == 0) flush_counts(C, cur_case, cc);
-            cur_case = cid;
-        }
-        collide_cell<P, 64>(C, g, lane, s_src[w], s_v[w], CAPW, red[w], redl[w], redi[w], cc);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
     }
-    if (cur_case >= 0 && lane == 0) flush_counts(C, cur_case, cc);
+    return v;
 }
 
-// One 256-thread block per dense cell (more than the wave kernel's limit).
-template <typename P, int CAPB>
-__global__ __launch_bounds__(kBlock) void k_collide_block(Ctx C)
+// One round of segmented sums: lane holds K values of slot base + lane; `head` is the first
+// lane of that slot's cell within the round (cells are contiguous runs of slots).  After
+// the segmented scan, the owner lane of each cell pulls its run's sum from `tail` (the last
+// lane of its run in this round, or -1) and adds it to acc.  The order of additions is
+// fixed, so results are reproducible.
+template <int K>
+__device__ __forceinline__ void seg_round(double (&x)[K], int head, int tail, double (&acc)[K])
 {
-    if (C.g->halt) return;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const bool take = lane - off >= head;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double y = __shfl_up(x[k], off, 64);
+            if (take) x[k] = x[k] + y;
+        }
+    }
+    const int src = tail >= 0 ? tail : lane;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double y = __shfl(x[k], src, 64);
+        if (tail >= 0) acc[k] = acc[k] + y;
+    }
+}
+
+// Tiles of the collision stage: a 64-thread block takes the cells whose weight
+// w(c) = cell_start[c] + 4 c falls in [t TW, (t+1) TW): at most TW/4 = 64 cells and TW + D
+// particles; cells denser than D go to k_collide_dense.  This kernel restores the stable
+// order of each cell's particles (source order) and writes the sorted state.
+template <typename P, int TW, int D>
+__global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
+{
+    constexpr int MAXC = TW / 4;
+    constexpr int MAXP = TW + D;
+    __shared__ int32_t s_src[MAXP];
+    __shared__ uint8_t s_lc[MAXP];
+    __shared__ int32_t c_start[MAXC], c_off[MAXC + 1];
+    __shared__ uint8_t c_case[MAXC], c_dim[MAXC];
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int lane = threadIdx.x;
+    const int64_t step = G->step;
+    const uint32_t st = (uint32_t)step;
+    const Parts<P> S(C.buf[step & 1]);
+    const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
+    const bool use_perm = C.perm != nullptr;
+    const int ntiles = G->n_tiles;
+    const int NC = C.ncells_total;
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0;
+        if (lane < 2) {
+            const long long wt = (long long)(t + lane) * TW;
+            int hi = NC;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((long long)C.cstart[mid] + 4ll * mid >= wt) hi = mid;
+                else lo = mid + 1;
+            }
+        }
+        const int cb = __shfl(lo, 0, 64);
+        const int ncl = __shfl(lo, 1, 64) - cb;
+        // owner lane = local cell
+        const bool own = lane < ncl;
+        const int g = cb + lane;
+        int n = 0, start = 0, cid = 0;
+        bool dense = false;
+        if (own) {
+            start = C.cstart[g];
+            n = C.cstart[g + 1] - start;
+            dense = n > D;
+            cid = case_of(C, g);
+            c_start[lane] = start;
+            c_case[lane] = (uint8_t)cid;
+            c_dim[lane] = (uint8_t)C.cases[cid].dim;
+        }
+        const int nn = (own && !dense) ? n : 0;
+        const int incl = wave_incl_scan(nn);
+        const int off = incl - nn;
+        const int np = __shfl(incl, 63, 64);
+        if (own) c_off[lane] = off;
+        if (lane == 0) c_off[ncl] = np;
+        team_sync<64>();
+        // slots -> cells, sources (all index loads issued before any is used)
+        constexpr int R = (MAXP + 63) / 64;
+        {
+            int pidx[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = lane + 64 * r;
+                pidx[r] = -1;
+                if (s < np) {
+                    int a = 0, b = ncl - 1;
+                    while (a < b) {
+                        const int mid = (a + b + 1) >> 1;
+                        if (c_off[mid] <= s) a = mid;
+                        else b = mid - 1;
+                    }
+                    s_lc[s] = (uint8_t)a;
+                    pidx[r] = c_start[a] + (s - c_off[a]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (pidx[r] >= 0) pidx[r] = use_perm ? C.perm[pidx[r]] : pidx[r];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (pidx[r] >= 0) s_src[lane + 64 * r] = pidx[r];
+        }
+        team_sync<64>();
+        // stable order inside each cell, gather (all loads first), write position / cell / id
+        {
+            P gv[R][3], gp[R][3];
+            int64_t gid[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = lane + 64 * r;
+                if (s < np) {
+                    const int src = s_src[s];
+                    const int dim = c_dim[s_lc[s]];
+                    gv[r][0] = S.vel[0][src];
+                    gv[r][1] = S.vel[1][src];
+                    gv[r][2] = S.vel[2][src];
+                    gid[r] = S.id[src];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) gp[r][a] = a < dim ? S.pos[a][src] : (P)0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = lane + 64 * r;
+                if (s < np) {
+                    const int lc = s_lc[s];
+                    const int o = c_off[lc], e = c_off[lc + 1];
+                    const int src = s_src[s];
+                    int rk = 0;
+                    for (int u = o; u < e; ++u) rk += s_src[u] < src;
+                    const size_t dst = (size_t)c_start[lc] + rk;
+                    const int dim = c_dim[lc];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        if (a < dim) Dd.pos[a][dst] = gp[r][a];
+                    Dd.cell[dst] = cb + lc;
+                    Dd.id[dst] = gid[r];
+                    Dd.vel[0][dst] = gv[r][0];
+                    Dd.vel[1][dst] = gv[r][1];
+                    Dd.vel[2][dst] = gv[r][2];
+                }
+            }
+        }
+        team_sync<64>();
+
+    }
+}
+
+// Collision stage of the tiles: moments, split, NTC, Shakhov, rescale and sampling on the
+// sorted velocities of the tile's cells (contiguous in the new state), in LDS.  Slot-wise
+// stages use every lane; per-cell scalars are formed by the owner lanes from segmented
+// sums.
+template <typename P, int TW, int D>
+__global__ __launch_bounds__(64) void k_collide_phys(Ctx C)
+{
+    constexpr int MAXC = TW / 4;
+    constexpr int MAXP = TW + D;
+    constexpr int MAXK = 128;             // NTC candidates prepared per chunk (two per lane)
+    static_assert(MAXC <= 64, "one owner lane per cell");
+    constexpr int KB = (int)(4 + 4 + 1 + 4 * sizeof(P));          // bytes per prepared candidate
+    constexpr int SCR = KB * MAXK;
+    __shared__ __align__(16) char s_scr[SCR];   // prepared NTC candidates
+    __shared__ uint8_t s_lc[MAXP];
+    __shared__ int32_t s_first[MAXP];
+    __shared__ P s_v[3][MAXP];
+    __shared__ int32_t c_start[MAXC], c_off[MAXC + 1], c_kb[MAXC + 1];
+    __shared__ double c_U[MAXC][3], c_Up[MAXC][3], c_f[MAXC], c_pr[MAXC];
+    __shared__ P c_par[MAXC][7];
+    __shared__ P c_scm[MAXC];
+    __shared__ unsigned long long c_obs[MAXC], c_hash[MAXC];
+    __shared__ int32_t c_nacc[MAXC];
+    __shared__ int32_t c_rel[MAXC][3];
+    __shared__ uint8_t c_case[MAXC], c_dim[MAXC];
+    int32_t *k_k = (int32_t *)s_scr;                      // candidate index within its cell
+    uint16_t *k_i = (uint16_t *)(s_scr + 4 * MAXK);       // tile slots of the pair
+    uint16_t *k_j = k_i + MAXK;
+    P *k_u = (P *)(s_scr + 8 * MAXK);                      // acceptance uniform
+    P *k_om = k_u + MAXK;                                  // [3][MAXK] post-collision direction
+    uint8_t *k_cell = (uint8_t *)(k_om + 3 * MAXK);
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int lane = threadIdx.x;
+    const int64_t step = G->step;
+    const uint32_t st = (uint32_t)step;
+    const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
+    const int ntiles = G->n_tiles;
+    const int NC = C.ncells_total;
+    const GasDev &gas = C.gas;
+    CellCounts cc{0, 0, 0, 0, 0, 0};
+    int my_case = -1;
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0;
+        if (lane < 2) {
+            const long long wt = (long long)(t + lane) * TW;
+            int hi = NC;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((long long)C.cstart[mid] + 4ll * mid >= wt) hi = mid;
+                else lo = mid + 1;
+            }
+        }
+        const int cb = __shfl(lo, 0, 64);
+        const int ncl = __shfl(lo, 1, 64) - cb;
+        // owner lane = local cell
+        const bool own = lane < ncl;
+        const int g = cb + lane;
+        int n = 0, start = 0, cid = 0;
+        bool dense = false;
+        if (own) {
+            start = C.cstart[g];
+            n = C.cstart[g + 1] - start;
+            dense = n > D;
+            cid = case_of(C, g);
+            c_start[lane] = start;
+            c_case[lane] = (uint8_t)cid;
+            c_dim[lane] = (uint8_t)C.cases[cid].dim;
+        }
+        const int nn = (own && !dense) ? n : 0;
+        const int incl = wave_incl_scan(nn);
+        const int off = incl - nn;
+        const int np = __shfl(incl, 63, 64);
+        if (own) c_off[lane] = off;
+        if (lane == 0) c_off[ncl] = np;
+        team_sync<64>();
+        // slots -> cells; velocities of the sorted state (written by k_sort_gather)
+        for (int s = lane; s < np; s += 64) {
+            int a = 0, b = ncl - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (c_off[mid] <= s) a = mid;
+                else b = mid - 1;
+            }
+            s_lc[s] = (uint8_t)a;
+            const size_t i = (size_t)c_start[a] + (s - c_off[a]);
+            s_v[0][s] = Dd.vel[0][i];
+            s_v[1][s] = Dd.vel[1][i];
+            s_v[2][s] = Dd.vel[2][i];
+        }
+        team_sync<64>();
+
+        // ---- Eq. 31 moments: segmented sums of c and |c|^2, then of the central products
+        const int my_o = own ? off : 0, my_e = own ? off + nn : 0;
+        double s1[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < np; base += 64) {
+            const int s = base + lane;
+            double x[4] = {0.0, 0.0, 0.0, 0.0};
+            int head = lane;
+            if (s < np) {
+                const int lc = s_lc[s];
+                head = max(c_off[lc] - base, 0);
+                x[0] = (double)s_v[0][s];
+                x[1] = (double)s_v[1][s];
+                x[2] = (double)s_v[2][s];
+                x[3] = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+            }
+            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
+            seg_round<4>(x, head, tail, s1);
+        }
+        double U[3] = {0.0, 0.0, 0.0};
+        if (own && nn > 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                U[a] = s1[a] / (double)nn;
+                c_U[lane][a] = U[a];
+            }
+        }
+        team_sync<64>();
+        double s2[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < np; base += 64) {
+            const int s = base + lane;
+            double x[4] = {0.0, 0.0, 0.0, 0.0};
+            int head = lane;
+            if (s < np) {
+                const int lc = s_lc[s];
+                head = max(c_off[lc] - base, 0);
+                if constexpr (sizeof(P) == 4) {
+                    // FP32 peculiar velocity and products (C = (c - U_f) - (U - U_f))
+                    float cv[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double u = c_U[lc][a];
+                        const float uf = (float)u;
+                        cv[a] = ((float)s_v[a][s] - uf) - (float)(u - (double)uf);
+                    }
+                    const float c2 = cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2];
+                    x[0] = (double)c2;
+                    x[1] = (double)(c2 * cv[0]);
+                    x[2] = (double)(c2 * cv[1]);
+                    x[3] = (double)(c2 * cv[2]);
+                } else {
+                    const double cx = s_v[0][s] - c_U[lc][0], cy = s_v[1][s] - c_U[lc][1], cz = s_v[2][s] - c_U[lc][2];
+                    const double c2 = cx * cx + cy * cy + cz * cz;
+                    x[0] = c2;
+                    x[1] = c2 * cx;
+                    x[2] = c2 * cy;
+                    x[3] = c2 * cz;
+                }
+            }
+            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
+            seg_round<4>(x, head, tail, s2);
+        }
+
+        // ---- owner lanes: temperature, heat flux, Eq. 10 / 25-28 split, NTC candidate count
+        const bool work = own && !dense;
+        TraceDev *tr = (work && C.trace) ? &C.trace[g] : nullptr;
+        long long ncol = 0;
+        double T = 0.0, pr = 0.0, dtD = 0.0, scmax = 0.0;
+        bool active = false;
+        if (work) {
+            if (cid != my_case) {
+                if (my_case >= 0) flush_counts(C, my_case, cc);
+                my_case = cid;
+            }
+            const CaseDev &cs = C.cases[cid];
+            if (tr) {
+                *tr = TraceDev{};
+                tr->n = nn;
+                for (int a = 0; a < 4; ++a) tr->pre_sum[a] = s1[a];
+            }
+            const double vol = C.vol[g];
+            double Q[3] = {0.0, 0.0, 0.0};
+            if (nn >= 2) {
+                if constexpr (sizeof(P) == 4)
+                    T = gas.m * (s1[3] - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)nn) /
+                        (3.0 * kKB * (double)(nn - 1));
+                else
+                    T = gas.m * s2[0] / (3.0 * kKB * (double)(nn - 1));
+                if (nn >= 3 && vol > 0.0) {
+                    const double nd = (double)nn * cs.F_N / vol;
+                    const double f = nd * (double)nn / ((double)(nn - 1) * (double)(nn - 2));
+                    for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * s2[1 + a];
+                }
+                if (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2])) raise_error(G, kErrNumeric);
+                active = T > 0.0 && vol > 0.0;
+                if (!active) cc.skipped++;
+            }
+            if (active) {
+                const double nd = (double)nn * cs.F_N / vol;
+                const double p = nd * kKB * T;
+                const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
+                const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+                double dtc;
+                if (cs.dim == 0) {
+                    dtc = dtG;
+                } else {
+                    const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+                    dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+                }
+                double dtS;
+                if (dtc <= tau) {
+                    dtD = dtG;
+                    dtS = 0.0;
+                } else {
+                    dtD = (tau / dtc) * dtG;
+                    dtS = dtG - dtD;
+                }
+                pr = -expm1(-dtS / tau);
+                double a_max = 1.0;
+                if (pr > 0.0) {
+                    const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+                    a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
+                    c_par[lane][0] = (P)Q[0];
+                    c_par[lane][1] = (P)Q[1];
+                    c_par[lane][2] = (P)Q[2];
+                    c_par[lane][3] = (P)p;
+                    c_par[lane][4] = (P)(gas.R * T);
+                    c_par[lane][5] = (P)sqrt(2.0 * gas.R * T);
+                    c_par[lane][6] = (P)a_max;
+                }
+                scmax = C.sigc[g];
+                const double M = 0.5 * (double)nn * (double)(nn - 1) * cs.F_N * scmax * dtD / vol;
+                const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)(g - cs.cell0), st, 0).x);
+                if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
+                else raise_error(G, kErrNumeric);
+                if (tr) {
+                    tr->T = T;
+                    tr->tau = tau;
+                    tr->dt_dsmc = dtD;
+                    tr->p_relax = pr;
+                    tr->a_max = pr > 0.0 ? a_max : 0.0;
+                }
+            }
+        }
+        if (own) {
+            c_pr[lane] = pr;
+            c_rel[lane][0] = c_rel[lane][1] = c_rel[lane][2] = 0;
+        }
+        // candidate ranges of the cells
+        const int kincl = wave_incl_scan((int)ncol);
+        const int kall = __shfl(kincl, 63, 64);
+        if (own) c_kb[lane] = kincl - (int)ncol;
+        if (lane == 0) c_kb[ncl] = kall;
+        team_sync<64>();
+
+        // ---- NTC (Eq. 5-9).  Random numbers of a chunk of candidates are drawn by all
+        // lanes; then, in rounds, every candidate whose two particles are not used by an
+        // earlier unprocessed candidate of the chunk is processed (such candidates commute,
+        // so the outcome equals the sequential order of Eq. 5-9); (sigma c)_max is fixed
+        // during the step.
+        if (own) {
+            c_scm[lane] = (P)scmax;
+            c_obs[lane] = 0ull;
+            c_hash[lane] = 0ull;
+            c_nacc[lane] = 0;
+        }
+        for (int kbase = 0; kbase < kall; kbase += MAXK) {
+            const int kn = min(MAXK, kall - kbase);
+            for (int q = lane; q < kn; q += 64) {
+                const int x = kbase + q;
+                int a = 0, b = ncl - 1;
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (c_kb[mid] <= x) a = mid;
+                    else b = mid - 1;
+                }
+                const int k = x - c_kb[a];
+                const int o = c_off[a], cn = c_off[a + 1] - o;
+                const CaseDev &cs = C.cases[c_case[a]];
+                const uint32_t lcid = (uint32_t)(cb + a - cs.cell0);
+                const W4 w = draw(cs, kStreamCell, lcid, st, (uint32_t)(1 + 2 * k));
+                const uint32_t i = unidx(w.x, (uint32_t)cn);
+                uint32_t j = unidx(w.y, (uint32_t)(cn - 1));
+                if (j >= i) ++j;
+                k_k[q] = k;
+                k_i[q] = (uint16_t)(o + i);
+                k_j[q] = (uint16_t)(o + j);
+                k_cell[q] = (uint8_t)a;
+                k_u[q] = Real<P>::uni(w.z);
+                const W4 w2 = draw(cs, kStreamCell, lcid, st, (uint32_t)(2 + 2 * k));
+                const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
+                const P schi = Real<P>::sq((P)1 - cchi * cchi);
+                P sth, cth;
+                Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
+                k_om[q] = cchi;
+                k_om[MAXK + q] = schi * cth;
+                k_om[2 * MAXK + q] = schi * sth;
+            }
+            bool done0 = lane >= kn, done1 = lane + 64 >= kn;
+            for (;;) {
+                for (int t2 = lane; t2 < np; t2 += 64) s_first[t2] = 0x7fffffff;
+                team_sync<64>();
+                if (!done0) {
+                    atomicMin(&s_first[k_i[lane]], lane);
+                    atomicMin(&s_first[k_j[lane]], lane);
+                }
+                if (!done1) {
+                    atomicMin(&s_first[k_i[lane + 64]], lane + 64);
+                    atomicMin(&s_first[k_j[lane + 64]], lane + 64);
+                }
+                if (!__any(!(done0 && done1))) break;
+                team_sync<64>();
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int q = lane + 64 * r;
+                    const bool d = r == 0 ? done0 : done1;
+                    if (d) continue;
+                    const int i = k_i[q], j = k_j[q];
+                    if (s_first[i] != q || s_first[j] != q) continue;
+                    const int lc = k_cell[q];
+                    P *vx = s_v[0], *vy = s_v[1], *vz = s_v[2];
+                    const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
+                    const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
+                    P sc;
+                    if constexpr (sizeof(P) == 4)
+                        sc = cr > (P)0 ? (P)gas.K_vhs * __builtin_amdgcn_exp2f((P)gas.vhs_exp * __builtin_amdgcn_logf(cr))
+                                       : (P)0;
+                    else
+                        sc = gas.K_vhs * pow(cr, gas.vhs_exp);
+                    atomicMax(&c_obs[lc], (unsigned long long)__double_as_longlong((double)sc));
+                    if (k_u[q] < sc / c_scm[lc]) {
+                        const P o0 = k_om[q], o1 = k_om[MAXK + q], o2 = k_om[2 * MAXK + q];
+                        const P sx = vx[i] + vx[j], sy = vy[i] + vy[j], sz = vz[i] + vz[j];
+                        vx[i] = (P)0.5 * (sx - cr * o0);
+                        vx[j] = (P)0.5 * (sx + cr * o0);
+                        vy[i] = (P)0.5 * (sy - cr * o1);
+                        vy[j] = (P)0.5 * (sy + cr * o1);
+                        vz[i] = (P)0.5 * (sz - cr * o2);
+                        vz[j] = (P)0.5 * (sz + cr * o2);
+                        atomicAdd(&c_nacc[lc], 1);
+                        atomicXor(&c_hash[lc], (unsigned long long)(k_k[q] + 1) * 0x9E3779B97F4A7C15ull);
+                    }
+                    if (r == 0) done0 = true;
+                    else done1 = true;
+                }
+                team_sync<64>();
+            }
+            team_sync<64>();
+        }
+        if (work && active) {
+            const double obs = __longlong_as_double((long long)c_obs[lane]);
+            if (obs > scmax) C.sigc[g] = obs;
+            cc.cand += ncol;
+            cc.acc += c_nacc[lane];
+            if (tr) {
+                tr->ncol = ncol;
+                tr->nacc = c_nacc[lane];
+                tr->acc_hash = c_hash[lane];
+            }
+        }
+
+        // ---- SP-Shakhov relaxation (Eq. 16-18), one lane per slot
+        for (int s = lane; s < np; s += 64) {
+            const int lc = s_lc[s];
+            const double p_r = c_pr[lc];
+            if (!(p_r > 0.0)) continue;
+            const CaseDev &cs = C.cases[c_case[lc]];
+            const int64_t id = Dd.id[(size_t)c_start[lc] + (s - c_off[lc])];
+            if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < p_r)) continue;
+            P Cv[3];
+            int used = shakhov_draw<P>(cs, id, st, c_par[lc], (P)(1.0 - gas.Pr), Cv);
+            int capd = 0;
+            if (used < 0) {
+                capd = 1;
+                used = -used;
+            }
+            s_v[0][s] = (P)(c_U[lc][0] + (double)Cv[0]);
+            s_v[1][s] = (P)(c_U[lc][1] + (double)Cv[1]);
+            s_v[2][s] = (P)(c_U[lc][2] + (double)Cv[2]);
+            atomicAdd(&c_rel[lc][0], 1);
+            atomicAdd(&c_rel[lc][1], used);
+            if (capd) atomicAdd(&c_rel[lc][2], 1);
+        }
+        team_sync<64>();
+
+        // ---- Eq. 19 rescale: post-collision sums, factor per cell, applied per slot
+        double r1[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < np; base += 64) {
+            const int s = base + lane;
+            double x[4] = {0.0, 0.0, 0.0, 0.0};
+            int head = lane;
+            if (s < np) {
+                const int lc = s_lc[s];
+                head = max(c_off[lc] - base, 0);
+                x[0] = (double)s_v[0][s];
+                x[1] = (double)s_v[1][s];
+                x[2] = (double)s_v[2][s];
+            }
+            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
+            seg_round<4>(x, head, tail, r1);
+        }
+        if (own) {
+            double f = 0.0;
+            if (active) {
+                const double Up[3] = {r1[0] / (double)nn, r1[1] / (double)nn, r1[2] / (double)nn};
+                for (int a = 0; a < 3; ++a) c_Up[lane][a] = Up[a];
+                f = -1.0;      // the spread is summed in the next pass
+            }
+            c_f[lane] = f;
+        }
+        team_sync<64>();
+        double r2[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < np; base += 64) {
+            const int s = base + lane;
+            double x[4] = {0.0, 0.0, 0.0, 0.0};
+            int head = lane;
+            if (s < np) {
+                const int lc = s_lc[s];
+                head = max(c_off[lc] - base, 0);
+                if (c_f[lc] < 0.0) {
+                    const double cx = (double)s_v[0][s] - c_Up[lc][0], cy = (double)s_v[1][s] - c_Up[lc][1],
+                                 cz = (double)s_v[2][s] - c_Up[lc][2];
+                    x[0] = cx * cx + cy * cy + cz * cz;
+                }
+            }
+            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
+            seg_round<4>(x, head, tail, r2);
+        }
+        if (own) {
+            double f = 0.0;
+            if (active) {
+                const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
+                f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+            }
+            c_f[lane] = f;
+        }
+        team_sync<64>();
+        // apply, then Step (5) sums of the final velocities
+        double sm[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) sm[j] = 0.0;
+        for (int base = 0; base < np; base += 64) {
+            const int s = base + lane;
+            double x[12];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) x[j] = 0.0;
+            int head = lane;
+            if (s < np) {
+                const int lc = s_lc[s];
+                head = max(c_off[lc] - base, 0);
+                double a = (double)s_v[0][s], b = (double)s_v[1][s], c = (double)s_v[2][s];
+                const double f = c_f[lc];
+                if (f > 0.0) {
+                    a = c_U[lc][0] + (a - c_Up[lc][0]) * f;
+                    b = c_U[lc][1] + (b - c_Up[lc][1]) * f;
+                    c = c_U[lc][2] + (c - c_Up[lc][2]) * f;
+                    s_v[0][s] = (P)a;
+                    s_v[1][s] = (P)b;
+                    s_v[2][s] = (P)c;
+                }
+                const double c2 = a * a + b * b + c * c;
+                x[0] = a; x[1] = b; x[2] = c;
+                x[3] = a * a; x[4] = b * b; x[5] = c * c;
+                x[6] = a * b; x[7] = a * c; x[8] = b * c;
+                x[9] = c2 * a; x[10] = c2 * b; x[11] = c2 * c;
+            }
+            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
+            seg_round<12>(x, head, tail, sm);
+        }
+        if (work) {
+            const CaseDev &cs = C.cases[cid];
+            cc.relax += c_rel[lane][0];
+            cc.ar += c_rel[lane][1];
+            cc.arcap += c_rel[lane][2];
+            if (step >= cs.n_steady) {
+                double *A = &C.acc[13 * (size_t)g];
+                A[0] += (double)nn;
+#pragma unroll
+                for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
+            }
+            if (tr) {
+                tr->post_sum[0] = sm[0];
+                tr->post_sum[1] = sm[1];
+                tr->post_sum[2] = sm[2];
+                tr->post_sum[3] = sm[3] + sm[4] + sm[5];
+                tr->nrelax = c_rel[lane][0];
+                tr->ar_attempts = c_rel[lane][1];
+                tr->ar_cap = c_rel[lane][2];
+            }
+        }
+        // write the velocities of the sorted state
+        for (int s = lane; s < np; s += 64) {
+            const int lc = s_lc[s];
+            const size_t dst = (size_t)c_start[lc] + (s - c_off[lc]);
+            Dd.vel[0][dst] = s_v[0][s];
+            Dd.vel[1][dst] = s_v[1][s];
+            Dd.vel[2][dst] = s_v[2][s];
+        }
+        team_sync<64>();
+    }
+    if (my_case >= 0) flush_counts(C, my_case, cc);
+}
+
+// Sort `a[0..p2)` ascending in LDS with a bitonic network (p2 a power of two).
+__device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
+{
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < p2; i += kBlock) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int32_t x = a[i], y = a[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Cells denser than the tile kernel takes: one 256-thread block per cell; the sequential
+// stages run on thread 0, the Shakhov draws on all threads.
+template <typename P, int CAPB>
+__global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
+{
     __shared__ int32_t s_src[CAPB];
-    __shared__ P s_v[3 * CAPB];
-    __shared__ double red[4 * 16];
-    __shared__ long long redl[4 * 8];
-    __shared__ int redi[2];
-    const int nbig = C.g->n_big;
+    __shared__ P s_v[3][CAPB];
+    __shared__ int32_t s_rel[3];
+    __shared__ double s_U[3], s_pr, s_T, s_obs;
+    __shared__ int s_act;
+    __shared__ P s_par[7];
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int tid = threadIdx.x;
+    const int64_t step = G->step;
+    const uint32_t st = (uint32_t)step;
+    const Parts<P> S(C.buf[step & 1]);
+    const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
+    const bool use_perm = C.perm != nullptr;
+    const int nbig = G->n_big;
     CellCounts cc{0, 0, 0, 0, 0, 0};
     for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
         const int g = C.big_list[b];
-        const int n = C.cstart[g + 1] - C.cstart[g];
+        const int s0 = C.cstart[g];
+        const int n = C.cstart[g + 1] - s0;
+        const int cid = case_of(C, g);
+        const CaseDev &cs = C.cases[cid];
         if (n > CAPB) {
-            if (threadIdx.x == 0) raise_error(C.g, kErrCellLimit);
+            if (tid == 0) raise_error(G, kErrCellLimit);
             continue;
         }
-        collide_cell<P, kBlock>(C, g, threadIdx.x, s_src, s_v, CAPB, red, redl, redi, cc);
-        if (threadIdx.x == 0) flush_counts(C, case_of(C, g), cc);
+        int p2 = 1;
+        while (p2 < n) p2 <<= 1;
+        for (int k = tid; k < p2; k += kBlock) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
+        __syncthreads();
+        if (use_perm) bitonic_sort(s_src, p2, tid);
+        for (int k = tid; k < n; k += kBlock) {
+            const int src = s_src[k];
+            const size_t dst = (size_t)s0 + k;
+            for (int a = 0; a < 3; ++a) if (a < cs.dim) Dd.pos[a][dst] = S.pos[a][src];
+            Dd.cell[dst] = g;
+            Dd.id[dst] = S.id[src];
+            s_v[0][k] = S.vel[0][src];
+            s_v[1][k] = S.vel[1][src];
+            s_v[2][k] = S.vel[2][src];
+        }
+        if (tid < 3) s_rel[tid] = 0;
+        __syncthreads();
+        const CellSlot<P> slot{s_U, &s_T, &s_pr, &s_obs, &s_act, s_par};
+        if (tid == 0) cell_stage_a<P>(C, cs, g, st, s_v[0], s_v[1], s_v[2], n, slot, cc);
+        __syncthreads();
+        const double pr = s_pr;
+        if (pr > 0.0) {
+            int nrel = 0, nar = 0, ncap = 0;
+            for (int k = tid; k < n; k += kBlock) {
+                const int64_t id = Dd.id[(size_t)s0 + k];
+                if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
+                P Cv[3];
+                int used = shakhov_draw<P>(cs, id, st, s_par, (P)(1.0 - C.gas.Pr), Cv);
+                if (used < 0) {
+                    ++ncap;
+                    used = -used;
+                }
+                ++nrel;
+                nar += used;
+                s_v[0][k] = (P)(s_U[0] + (double)Cv[0]);
+                s_v[1][k] = (P)(s_U[1] + (double)Cv[1]);
+                s_v[2][k] = (P)(s_U[2] + (double)Cv[2]);
+            }
+            if (nrel) atomicAdd(&s_rel[0], nrel);
+            if (nar) atomicAdd(&s_rel[1], nar);
+            if (ncap) atomicAdd(&s_rel[2], ncap);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            cc.relax += s_rel[0];
+            cc.ar += s_rel[1];
+            cc.arcap += s_rel[2];
+            cell_stage_c<P>(C, g, step >= cs.n_steady, s_v[0], s_v[1], s_v[2], n, slot, s_rel);
+            flush_counts(C, cid, cc);
+        }
+        __syncthreads();
+        for (int k = tid; k < n; k += kBlock) {
+            const size_t dst = (size_t)s0 + k;
+            Dd.vel[0][dst] = s_v[0][k];
+            Dd.vel[1][dst] = s_v[1][k];
+            Dd.vel[2][dst] = s_v[2][k];
+        }
+        __syncthreads();
     }
 }
 
@@ -1015,6 +1749,7 @@ __global__ void k_finish_step(Ctx C, int sorted)
             G->n_live = G->n_new;
             G->n_big = 0;      // rebuilt by the next step's scan
         }
+        G->n_work = 0;
         G->n_total = G->n_live;
         G->step = step + 1;
     }
@@ -1124,7 +1859,8 @@ __global__ void k_philox(uint64_t seed, uint32_t stream, uint64_t e0, uint32_t s
 // launchers
 // ------------------------------------------------------------------------------------
 
-constexpr int kCapWave = 256;
+constexpr int kCapWave = 192;       // densest cell of the tile kernel
+constexpr int kTileW = 256;         // tile weight: particles + 4 per cell
 constexpr int kCapBlock64 = 2048;   // powers of two: the bitonic sort pads to one
 constexpr int kCapBlock32 = 2048;
 
@@ -1168,13 +1904,16 @@ void Launch::inject(const Ctx &c, void *s)
     else
         hipLaunchKernelGGL(k_inject_fill<float>, dim3(blocks_for(c.n_faces, 4)), dim3(kBlock), 0, S_(s), c);
 }
-void Launch::move_count(const Ctx &c, void *s)
+void Launch::move_count(const Ctx &c, void *s, int any_body)
 {
     const int grid = std::min(stream_grid(), blocks_for(c.capacity, kBlock));
-    if (c.precision == HS_FP64)
-        hipLaunchKernelGGL(k_move_count<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-    else
-        hipLaunchKernelGGL(k_move_count<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+    if (c.precision == HS_FP64) {
+        hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
+    } else {
+        hipLaunchKernelGGL(k_move_fast<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(256), dim3(kBlock), 0, S_(s), c);
+    }
 }
 void Launch::scatter(const Ctx &c, void *s)
 {
@@ -1183,14 +1922,17 @@ void Launch::scatter(const Ctx &c, void *s)
 }
 void Launch::collide(const Ctx &c, void *s)
 {
-    const int gw = std::max(1, std::min(blocks_for(c.ncells_total, 4), 256 * 8));
+    const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
+    const int gt = (int)std::max(1ll, std::min(maxtiles, 256ll * 32));
     const int gb = std::max(1, std::min(c.ncells_total, 256 * 2));
     if (c.precision == HS_FP64) {
-        hipLaunchKernelGGL((k_collide_wave<double, kCapWave>), dim3(gw), dim3(kBlock), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_block<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
+        hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_phys<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
     } else {
-        hipLaunchKernelGGL((k_collide_wave<float, kCapWave>), dim3(gw), dim3(kBlock), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_block<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
+        hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_phys<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
     }
 }
 void Launch::finish_step(const Ctx &c, void *s)
@@ -1223,6 +1965,7 @@ void launch_finalize(const Ctx &c, void *s, int case_id, int ncells, double *out
 }
 
 int cap_wave() { return kCapWave; }
+int tile_width() { return kTileW; }
 int cap_block(int precision) { return precision == HS_FP64 ? kCapBlock64 : kCapBlock32; }
 
 }  // namespace hsk

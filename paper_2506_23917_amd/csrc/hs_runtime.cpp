@@ -24,7 +24,7 @@ struct Layout {
     size_t total = 0;
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
-    size_t newcell, slot, perm, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, trace, out;
+    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, trace, out;
 };
 
 struct Plan {
@@ -35,7 +35,7 @@ struct Plan {
     std::vector<double> dtcell;     // per global cell, only if some case is 0-D
     int64_t ncells = 0, capacity = 0;
     int dim_max = 0;
-    bool any_spatial = false, any_0d = false;
+    bool any_spatial = false, any_0d = false, any_body = false;
     GasDev gas;
 };
 
@@ -157,6 +157,18 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         d.sigc0 = P.gas.K_vhs * std::pow(10.0 * std::sqrt(kKB_h * c.T_sigma / g->m), 2.0 - 2.0 * g->omega);
         d.in_n = c.inflow.n;
         d.in_T = c.inflow.T;
+        for (int a = 0; a < 3; ++a) {
+            d.bb_lo[a] = 0;
+            d.bb_hi[a] = d.n[a] - 1;
+        }
+        if (c.body != HS_BODY_NONE) {
+            const int na = c.body == HS_BODY_SPHERE ? 3 : 2;
+            for (int a = 0; a < na; ++a) {
+                d.bb_lo[a] = (int32_t)std::floor((c.body_c[a] - c.body_r - c.lo[a]) / c.h[a]) - 1;
+                d.bb_hi[a] = (int32_t)std::floor((c.body_c[a] + c.body_r - c.lo[a]) / c.h[a]) + 1;
+            }
+            P.any_body = true;
+        }
         d.region0 = (int32_t)P.rstate.size();
         d.nregions = c.n_regions;
         for (int r = 0; r < c.n_regions; ++r) {
@@ -239,6 +251,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     } else {
         L.newcell = L.slot = L.perm = 0;
     }
+    L.work = P.any_body ? take(4 * cap) : 0;
     L.count = take(4 * nc);
     L.cstart = take(4 * (nc + 1));
     L.sigc = take(8 * nc);
@@ -337,7 +350,7 @@ void enqueue_step(hs_sim *s, int timed)
     if (s->plan.any_spatial) {
         Launch::inject(c, st);
         if (ev) hipEventRecord(ev[1], s->stream);
-        Launch::move_count(c, st);
+        Launch::move_count(c, st, s->plan.any_body ? 1 : 0);
         if (ev) hipEventRecord(ev[2], s->stream);
         Launch::scan_cells(c, st, 1);
         if (ev) hipEventRecord(ev[3], s->stream);
@@ -418,6 +431,8 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.face_start = (int32_t *)(w + L.facestart);
     c.scan_part = (int32_t *)(w + L.scanpart);
     c.big_list = (int32_t *)(w + L.big);
+    c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
+    c.tile_w = tile_width();
     c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
     c.g = (Globals *)(w + L.globals);
     c.n_cases = n_cases;
@@ -720,6 +735,8 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     G.n_total = (int32_t)total;
     G.n_new = (int32_t)total;
     G.n_big = 0;
+    G.n_work = 0;
+    G.n_tiles = (int32_t)(((int64_t)total + 4 * s->plan.ncells + tile_width() - 1) / tile_width());
     G.next_id[c] = hd.next_id;
     G.n_samples[c] = hd.n_samples;
     HIPCHK(s, hipMemcpy(s->ws + s->lay.globals, &G, sizeof(G), hipMemcpyHostToDevice));
