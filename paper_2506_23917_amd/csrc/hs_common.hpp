@@ -111,9 +111,11 @@ struct Ctx {
     int32_t *newcell, *slot, *perm;
     int32_t *count, *cstart;      // per cell; cstart has ncells_total + 1 entries
     double *sigc, *acc, *vol;     // (sigma c)_max, 13 sums per cell, fluid volume
+    double *cellrec;              // 16 doubles per cell: scalars of the collision stage
     int32_t *face_cnt, *face_start;
     int32_t *scan_part;
     int32_t *big_list;
+    int32_t *tile_cell;           // first cell of each collide tile (n_tiles + 1 entries)
     int32_t *work;                // body worklist (particle indices)
     TraceDev *trace;              // nullptr unless tracing
     Globals *g;
@@ -129,6 +131,7 @@ struct Launch {
     static void init_fill(const Ctx &c, void *stream);
     static void init_finish(const Ctx &c, void *stream);
     static void scan_cells(const Ctx &c, void *stream, int build_big);
+    static void tile_table(const Ctx &c, void *stream);
     static void inject(const Ctx &c, void *stream);
     static void move_count(const Ctx &c, void *stream, int any_body);
     static void scatter(const Ctx &c, void *stream);

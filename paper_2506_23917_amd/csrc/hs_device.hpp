@@ -47,6 +47,14 @@ __device__ __forceinline__ W4 draw(const CaseDev &cs, uint32_t stream, uint64_t 
                     step, d, cs.seed_lo, cs.seed_hi);
 }
 
+// The same draw with the case's seed words passed directly.
+__device__ __forceinline__ W4 draw_s(uint32_t seed_lo, uint32_t seed_hi, uint32_t stream, uint64_t entity,
+                                     uint32_t step, uint32_t d)
+{
+    return philox10((uint32_t)entity, ((uint32_t)(entity >> 32) & 0x0fffffffu) | (stream << 28), step, d,
+                    seed_lo, seed_hi);
+}
+
 // 32-bit word -> double uniform in (0,1): (w + 1/2) 2^-32.
 __device__ __forceinline__ double unid(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 // 32-bit word -> float uniform in (0,1): an odd multiple of 2^-24, exactly representable.
@@ -68,12 +76,19 @@ template <> struct Real<double> {
     __device__ static double fl(double x) { return floor(x); }
     __device__ static double below_one() { return 0x1.fffffffffffffp-1; }
 };
+// FP32 sampling arithmetic on the hardware transcendental units (a few ulp): square root,
+// log2 (scaled to ln) and the sine / cosine of a turn fraction (v_sin / v_cos take their
+// argument in turns, so 2 pi u needs no range reduction for u in (0, 1)).
 template <> struct Real<float> {
     __device__ static float uni(uint32_t w) { return unif(w); }
-    __device__ static float sq(float x) { return sqrtf(x); }
-    __device__ static float ln(float x) { return logf(x); }
+    __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static float ln(float x) { return __builtin_amdgcn_logf(x) * 0x1.62e430p-1f; }
     __device__ static float pw(float x, float y) { return powf(x, y); }
-    __device__ static void sc2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
+    __device__ static void sc2pi(float u, float *s, float *c)
+    {
+        *s = __builtin_amdgcn_sinf(u);
+        *c = __builtin_amdgcn_cosf(u);
+    }
     __device__ static float fl(float x) { return floorf(x); }
     __device__ static float below_one() { return 0x1.fffffep-1f; }
 };

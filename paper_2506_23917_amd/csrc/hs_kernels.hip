@@ -121,6 +121,14 @@ __device__ __forceinline__ void raise_error(Globals *g, uint32_t bits)
     atomicExch(&g->halt, 1u);
 }
 
+// Load base[byte_off / sizeof(T)] with a 32-bit byte offset (uniform base in SGPRs, the
+// offset in one VGPR).
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+
 template <typename P>
 struct Parts {
     P *pos[3];
@@ -337,6 +345,25 @@ __global__ void k_scan_parts(Ctx C, int nparts)
     if (threadIdx.x == 0) C.scan_part[nparts] = carry;
 }
 
+// Collide tiles: tile t covers the cells c with t TW <= w(c) < (t+1) TW, w(c) = cstart[c] + 4 c
+// (strictly increasing).  Cell g with weight w0 and successor weight w1 writes g + 1 as the
+// first cell of every tile t with w0 < t TW <= w1; tile 0 starts at cell 0, and the entry
+// after the last tile is ncells.
+__device__ __forceinline__ void tile_marks(const Ctx &C, int g, long long w0, long long w1)
+{
+    const long long tw = C.tile_w;
+    for (long long t = w0 / tw + 1; t <= w1 / tw; ++t) C.tile_cell[t] = g + 1;
+    if (g == 0) C.tile_cell[0] = 0;
+    if (g == C.ncells_total - 1 && w1 % tw != 0) C.tile_cell[w1 / tw + 1] = g + 1;
+}
+
+__global__ void k_tile_table(Ctx C)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= C.ncells_total) return;
+    tile_marks(C, g, (long long)C.cstart[g] + 4ll * g, (long long)C.cstart[g + 1] + 4ll * (g + 1));
+}
+
 __global__ void k_scan_final(Ctx C, int build_big, int nparts)
 {
     if (C.g->halt) return;
@@ -362,6 +389,7 @@ __global__ void k_scan_final(Ctx C, int build_big, int nparts)
                 const int slot = atomicAdd(&C.g->n_big, 1);
                 C.big_list[slot] = g;
             }
+            tile_marks(C, g, (long long)run + 4ll * g, (long long)(run + v[k]) + 4ll * (g + 1));
         }
         run += v[k];
     }
@@ -825,13 +853,14 @@ __device__ void cell_stage_a(const Ctx &C, const CaseDev &cs, int g, uint32_t st
 
 // Shakhov acceptance-rejection draw (Eq. 17-18) for one relaxing particle.
 template <typename P>
-__device__ __forceinline__ int shakhov_draw(const CaseDev &cs, int64_t id, uint32_t st, const P *par, P one_m_pr,
-                                            P Cv[3])
+__device__ __forceinline__ int shakhov_draw(uint32_t sd0, uint32_t sd1, int64_t id, uint32_t st, const P *par,
+                                            P one_m_pr, P Cv[3])
 {
     const P ath = par[5], p = par[3], RT = par[4], am = par[6];
+#pragma unroll 1
     for (int a = 0; a < kMaxShakhov; ++a) {
-        const W4 w = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a);
-        const W4 w5 = draw(cs, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a + 1);
+        const W4 w = draw_s(sd0, sd1, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a);
+        const W4 w5 = draw_s(sd0, sd1, kStreamParticle, (uint64_t)id, st, kDrawShakhov + 2 * a + 1);
         P s1, c1, s3, c3;
         Real<P>::sc2pi(Real<P>::uni(w.x), &s1, &c1);
         Real<P>::sc2pi(Real<P>::uni(w.z), &s3, &c3);
@@ -947,6 +976,21 @@ __device__ __forceinline__ void flush_counts(const Ctx &C, int cid, CellCounts &
     cc = CellCounts{0, 0, 0, 0, 0, 0};
 }
 
+// Kernel-end flush of every lane's counts: one atomic per counter and distinct case in the
+// wave (same-address atomics from every lane of every block would serialise in L2).
+__device__ __forceinline__ void wave_flush_counts(const Ctx &C, int cid, CellCounts &cc)
+{
+    long long *base = &C.g->counters[0][0];
+    const bool on = cid >= 0;
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_CANDIDATES, cc.cand, on);
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_ACCEPTED, cc.acc, on);
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_RELAXED, cc.relax, on);
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_AR_ATTEMPTS, cc.ar, on);
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_AR_CAP, cc.arcap, on);
+    wave_add(base, HS_NUM_COUNTERS, cid, HS_CNT_SKIPPED_CELLS, cc.skipped, on);
+    cc = CellCounts{0, 0, 0, 0, 0, 0};
+}
+
 // ---- wavefront-tile collide kernel ----------------------------------------------------
 
 // Inclusive prefix sum over the wavefront.
@@ -1012,18 +1056,12 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     const int NC = C.ncells_total;
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int lo = 0;
-        if (lane < 2) {
-            const long long wt = (long long)(t + lane) * TW;
-            int hi = NC;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((long long)C.cstart[mid] + 4ll * mid >= wt) hi = mid;
-                else lo = mid + 1;
-            }
+        const int cb = C.tile_cell[t];
+        const int ncl = C.tile_cell[t + 1] - cb;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+            if (lane == 0) raise_error(G, kErrState);
+            return;
         }
-        const int cb = __shfl(lo, 0, 64);
-        const int ncl = __shfl(lo, 1, 64) - cb;
         // owner lane = local cell
         const bool own = lane < ncl;
         const int g = cb + lane;
@@ -1117,37 +1155,40 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     }
 }
 
-// Collision stage of the tiles: moments, split, NTC, Shakhov, rescale and sampling on the
-// sorted velocities of the tile's cells (contiguous in the new state), in LDS.  Slot-wise
-// stages use every lane; per-cell scalars are formed by the owner lanes from segmented
-// sums.
+// Butterfly sum over each aligned group of 2^kb lanes.  Every lane of a group ends with
+// the same bits: at each level the two partners add the same two values.
+template <int K>
+__device__ __forceinline__ void group_sum(double (&x)[K], int kb)
+{
+    for (int m = 1; m < (1 << kb); m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = x[k] + __shfl_xor(x[k], m, 64);
+    }
+}
+
+__device__ __forceinline__ int group_sum_i(int x, int kb)
+{
+    for (int m = 1; m < (1 << kb); m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// Per-cell record written by k_cell_scalars for the tile kernel (16 doubles per cell):
+// U[3], T, P_relax, (sigma c)_max, N_col, active, Shakhov parameters Q[3], p, RT,
+// sqrt(2RT), A_max.
+enum : int {
+    kRecU = 0, kRecT = 3, kRecPr = 4, kRecScm = 5, kRecNcol = 6, kRecAct = 7, kRecPar = 8, kRecLen = 16
+};
+
+// Steps (3)-(4a) of the tiles' cells: Eq. 31 moments of the sorted velocities, Eq. 10 / 25-28
+// timescales and split, the NTC candidate count and the Shakhov parameters; one record per
+// cell.  Each cell is served by an aligned group of 2^kb lanes (2^kb ncl <= 64): a lane sums
+// every 2^kb-th particle of its cell straight from memory and the group combines the
+// partial sums by a butterfly, so every lane of the group holds the cell's totals and
+// derives the scalars itself; lane `sub == 0` records them.
 template <typename P, int TW, int D>
-__global__ __launch_bounds__(64) void k_collide_phys(Ctx C)
+__global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
 {
     constexpr int MAXC = TW / 4;
-    constexpr int MAXP = TW + D;
-    constexpr int MAXK = 128;             // NTC candidates prepared per chunk (two per lane)
-    static_assert(MAXC <= 64, "one owner lane per cell");
-    constexpr int KB = (int)(4 + 4 + 1 + 4 * sizeof(P));          // bytes per prepared candidate
-    constexpr int SCR = KB * MAXK;
-    __shared__ __align__(16) char s_scr[SCR];   // prepared NTC candidates
-    __shared__ uint8_t s_lc[MAXP];
-    __shared__ int32_t s_first[MAXP];
-    __shared__ P s_v[3][MAXP];
-    __shared__ int32_t c_start[MAXC], c_off[MAXC + 1], c_kb[MAXC + 1];
-    __shared__ double c_U[MAXC][3], c_Up[MAXC][3], c_f[MAXC], c_pr[MAXC];
-    __shared__ P c_par[MAXC][7];
-    __shared__ P c_scm[MAXC];
-    __shared__ unsigned long long c_obs[MAXC], c_hash[MAXC];
-    __shared__ int32_t c_nacc[MAXC];
-    __shared__ int32_t c_rel[MAXC][3];
-    __shared__ uint8_t c_case[MAXC], c_dim[MAXC];
-    int32_t *k_k = (int32_t *)s_scr;                      // candidate index within its cell
-    uint16_t *k_i = (uint16_t *)(s_scr + 4 * MAXK);       // tile slots of the pair
-    uint16_t *k_j = k_i + MAXK;
-    P *k_u = (P *)(s_scr + 8 * MAXK);                      // acceptance uniform
-    P *k_om = k_u + MAXK;                                  // [3][MAXK] post-collision direction
-    uint8_t *k_cell = (uint8_t *)(k_om + 3 * MAXK);
     Globals *G = C.g;
     if (G->halt) return;
     const int lane = threadIdx.x;
@@ -1157,194 +1198,179 @@ __global__ __launch_bounds__(64) void k_collide_phys(Ctx C)
     const int ntiles = G->n_tiles;
     const int NC = C.ncells_total;
     const GasDev &gas = C.gas;
-    CellCounts cc{0, 0, 0, 0, 0, 0};
+    const bool tracing = C.trace != nullptr;
+    long long skipped = 0;
     int my_case = -1;
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int lo = 0;
-        if (lane < 2) {
-            const long long wt = (long long)(t + lane) * TW;
-            int hi = NC;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((long long)C.cstart[mid] + 4ll * mid >= wt) hi = mid;
-                else lo = mid + 1;
-            }
+        const int cb = C.tile_cell[t];
+        const int ncl = C.tile_cell[t + 1] - cb;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+            if (lane == 0) raise_error(G, kErrState);
+            return;
         }
-        const int cb = __shfl(lo, 0, 64);
-        const int ncl = __shfl(lo, 1, 64) - cb;
-        // owner lane = local cell
-        const bool own = lane < ncl;
-        const int g = cb + lane;
-        int n = 0, start = 0, cid = 0;
-        bool dense = false;
+        if (ncl == 0) continue;
+        const int kb = ncl == 1 ? 6 : 6 - (32 - __clz(ncl - 1));
+        const int kk = 1 << kb;
+        const int gc = lane >> kb, sub = lane & (kk - 1);
+        const bool own = gc < ncl;
+        const int g = cb + gc;
+        int start = 0, n = 0, cid = 0;
+        double vol = 0.0, scm = 0.0;
         if (own) {
             start = C.cstart[g];
             n = C.cstart[g + 1] - start;
-            dense = n > D;
             cid = case_of(C, g);
-            c_start[lane] = start;
-            c_case[lane] = (uint8_t)cid;
-            c_dim[lane] = (uint8_t)C.cases[cid].dim;
+            vol = C.vol[g];
+            scm = C.sigc[g];
         }
-        const int nn = (own && !dense) ? n : 0;
-        const int incl = wave_incl_scan(nn);
-        const int off = incl - nn;
-        const int np = __shfl(incl, 63, 64);
-        if (own) c_off[lane] = off;
-        if (lane == 0) c_off[ncl] = np;
-        team_sync<64>();
-        // slots -> cells; velocities of the sorted state (written by k_sort_gather)
-        for (int s = lane; s < np; s += 64) {
-            int a = 0, b = ncl - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (c_off[mid] <= s) a = mid;
-                else b = mid - 1;
-            }
-            s_lc[s] = (uint8_t)a;
-            const size_t i = (size_t)c_start[a] + (s - c_off[a]);
-            s_v[0][s] = Dd.vel[0][i];
-            s_v[1][s] = Dd.vel[1][i];
-            s_v[2][s] = Dd.vel[2][i];
-        }
-        team_sync<64>();
+        const bool work = own && n <= D;
+        const int nn = work ? n : 0;
+        const bool lead = work && sub == 0;
+        const P *vx = Dd.vel[0] + start, *vy = Dd.vel[1] + start, *vz = Dd.vel[2] + start;
 
-        // ---- Eq. 31 moments: segmented sums of c and |c|^2, then of the central products
-        const int my_o = own ? off : 0, my_e = own ? off + nn : 0;
+        // Eq. 31: sums of c and |c|^2
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int base = 0; base < np; base += 64) {
-            const int s = base + lane;
-            double x[4] = {0.0, 0.0, 0.0, 0.0};
-            int head = lane;
-            if (s < np) {
-                const int lc = s_lc[s];
-                head = max(c_off[lc] - base, 0);
-                x[0] = (double)s_v[0][s];
-                x[1] = (double)s_v[1][s];
-                x[2] = (double)s_v[2][s];
-                x[3] = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-            }
-            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
-            seg_round<4>(x, head, tail, s1);
+        for (int i = sub; i < nn; i += kk) {
+            const double x = (double)vx[i], y = (double)vy[i], z = (double)vz[i];
+            s1[0] = s1[0] + x;
+            s1[1] = s1[1] + y;
+            s1[2] = s1[2] + z;
+            s1[3] = s1[3] + (x * x + y * y + z * z);
         }
+        group_sum<4>(s1, kb);
         double U[3] = {0.0, 0.0, 0.0};
-        if (own && nn > 0) {
+        if (nn > 0) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                U[a] = s1[a] / (double)nn;
-                c_U[lane][a] = U[a];
-            }
+            for (int a = 0; a < 3; ++a) U[a] = s1[a] / (double)nn;
         }
-        team_sync<64>();
+        // sums of the peculiar |C|^2 and |C|^2 C: always in FP64 (T is their first); in
+        // FP32-mixed (T from the raw sums) only where the heat flux is needed
         double s2[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int base = 0; base < np; base += 64) {
-            const int s = base + lane;
-            double x[4] = {0.0, 0.0, 0.0, 0.0};
-            int head = lane;
-            if (s < np) {
-                const int lc = s_lc[s];
-                head = max(c_off[lc] - base, 0);
+        auto peculiar = [&](bool on) {
+            if (on) {
                 if constexpr (sizeof(P) == 4) {
                     // FP32 peculiar velocity and products (C = (c - U_f) - (U - U_f))
-                    float cv[3];
+                    float uf[3], ud[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const double u = c_U[lc][a];
-                        const float uf = (float)u;
-                        cv[a] = ((float)s_v[a][s] - uf) - (float)(u - (double)uf);
+                        uf[a] = (float)U[a];
+                        ud[a] = (float)(U[a] - (double)uf[a]);
                     }
-                    const float c2 = cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2];
-                    x[0] = (double)c2;
-                    x[1] = (double)(c2 * cv[0]);
-                    x[2] = (double)(c2 * cv[1]);
-                    x[3] = (double)(c2 * cv[2]);
+                    for (int i = sub; i < nn; i += kk) {
+                        const float cx = (vx[i] - uf[0]) - ud[0];
+                        const float cy = (vy[i] - uf[1]) - ud[1];
+                        const float cz = (vz[i] - uf[2]) - ud[2];
+                        const float c2 = cx * cx + cy * cy + cz * cz;
+                        s2[0] = s2[0] + (double)c2;
+                        s2[1] = s2[1] + (double)(c2 * cx);
+                        s2[2] = s2[2] + (double)(c2 * cy);
+                        s2[3] = s2[3] + (double)(c2 * cz);
+                    }
                 } else {
-                    const double cx = s_v[0][s] - c_U[lc][0], cy = s_v[1][s] - c_U[lc][1], cz = s_v[2][s] - c_U[lc][2];
-                    const double c2 = cx * cx + cy * cy + cz * cz;
-                    x[0] = c2;
-                    x[1] = c2 * cx;
-                    x[2] = c2 * cy;
-                    x[3] = c2 * cz;
+                    for (int i = sub; i < nn; i += kk) {
+                        const double cx = vx[i] - U[0], cy = vy[i] - U[1], cz = vz[i] - U[2];
+                        const double c2 = cx * cx + cy * cy + cz * cz;
+                        s2[0] = s2[0] + c2;
+                        s2[1] = s2[1] + c2 * cx;
+                        s2[2] = s2[2] + c2 * cy;
+                        s2[3] = s2[3] + c2 * cz;
+                    }
                 }
             }
-            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
-            seg_round<4>(x, head, tail, s2);
-        }
+            group_sum<4>(s2, kb);
+        };
+        if constexpr (sizeof(P) == 8) peculiar(nn >= 2);
 
-        // ---- owner lanes: temperature, heat flux, Eq. 10 / 25-28 split, NTC candidate count
-        const bool work = own && !dense;
-        TraceDev *tr = (work && C.trace) ? &C.trace[g] : nullptr;
-        long long ncol = 0;
-        double T = 0.0, pr = 0.0, dtD = 0.0, scmax = 0.0;
+        TraceDev *tr = (lead && tracing) ? &C.trace[g] : nullptr;
+        if (work && cid != my_case) {
+            if (my_case >= 0 && skipped)
+                atomicAdd((unsigned long long *)&G->counters[my_case][HS_CNT_SKIPPED_CELLS], (unsigned long long)skipped);
+            skipped = 0;
+            my_case = cid;
+        }
+        const CaseDev &cs = C.cases[cid];
+        double T = 0.0, pr = 0.0, p = 0.0, tau = 0.0, dtD = 0.0;
         bool active = false;
-        if (work) {
-            if (cid != my_case) {
-                if (my_case >= 0) flush_counts(C, my_case, cc);
-                my_case = cid;
+        if (work && nn >= 2) {
+            if constexpr (sizeof(P) == 4)
+                T = gas.m * (s1[3] - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)nn) /
+                    (3.0 * kKB * (double)(nn - 1));
+            else
+                T = gas.m * s2[0] / (3.0 * kKB * (double)(nn - 1));
+            if (!isfinite(T)) raise_error(G, kErrNumeric);
+            active = T > 0.0 && vol > 0.0;
+            if (!active && lead) ++skipped;
+        }
+        if (active) {
+            const double nd = (double)nn * cs.F_N / vol;
+            p = nd * kKB * T;
+            tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
+            const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+            double dtc;
+            if (cs.dim == 0) {
+                dtc = dtG;
+            } else {
+                const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+                dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
             }
-            const CaseDev &cs = C.cases[cid];
+            double dtS;
+            if (dtc <= tau) {
+                dtD = dtG;
+                dtS = 0.0;
+            } else {
+                dtD = (tau / dtc) * dtG;
+                dtS = dtG - dtD;
+            }
+            pr = -expm1(-dtS / tau);
+        }
+        // Eq. 32 heat flux (needed by the Shakhov target only)
+        if constexpr (sizeof(P) == 4) {
+            if (__any(pr > 0.0 && nn >= 3)) peculiar(pr > 0.0 && nn >= 3);
+        }
+        double Q[3] = {0.0, 0.0, 0.0};
+        if (work && nn >= 3 && vol > 0.0 && (sizeof(P) == 8 || pr > 0.0)) {
+            const double nd = (double)nn * cs.F_N / vol;
+            const double f = nd * (double)nn / ((double)(nn - 1) * (double)(nn - 2));
+            for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * s2[1 + a];
+            if (!isfinite(Q[0] + Q[1] + Q[2])) raise_error(G, kErrNumeric);
+        }
+        long long ncol = 0;
+        double a_max = 0.0;
+        if (active) {
+            if (pr > 0.0) {
+                const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+                a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
+            }
+            const double M = 0.5 * (double)nn * (double)(nn - 1) * cs.F_N * scm * dtD / vol;
+            const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)(g - cs.cell0), st, 0).x);
+            if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
+            else raise_error(G, kErrNumeric);
+        }
+        if (lead) {
+            double *R = C.cellrec + (size_t)kRecLen * g;
+            R[kRecU + 0] = U[0];
+            R[kRecU + 1] = U[1];
+            R[kRecU + 2] = U[2];
+            R[kRecT] = T;
+            R[kRecPr] = pr;
+            R[kRecScm] = scm;
+            R[kRecNcol] = (double)ncol;
+            R[kRecAct] = active ? 1.0 : 0.0;
+            if (pr > 0.0) {
+                R[kRecPar + 0] = Q[0];
+                R[kRecPar + 1] = Q[1];
+                R[kRecPar + 2] = Q[2];
+                R[kRecPar + 3] = p;
+                R[kRecPar + 4] = gas.R * T;
+                R[kRecPar + 5] = sqrt(2.0 * gas.R * T);
+                R[kRecPar + 6] = a_max;
+            }
             if (tr) {
                 *tr = TraceDev{};
                 tr->n = nn;
                 for (int a = 0; a < 4; ++a) tr->pre_sum[a] = s1[a];
-            }
-            const double vol = C.vol[g];
-            double Q[3] = {0.0, 0.0, 0.0};
-            if (nn >= 2) {
-                if constexpr (sizeof(P) == 4)
-                    T = gas.m * (s1[3] - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)nn) /
-                        (3.0 * kKB * (double)(nn - 1));
-                else
-                    T = gas.m * s2[0] / (3.0 * kKB * (double)(nn - 1));
-                if (nn >= 3 && vol > 0.0) {
-                    const double nd = (double)nn * cs.F_N / vol;
-                    const double f = nd * (double)nn / ((double)(nn - 1) * (double)(nn - 2));
-                    for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * s2[1 + a];
-                }
-                if (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2])) raise_error(G, kErrNumeric);
-                active = T > 0.0 && vol > 0.0;
-                if (!active) cc.skipped++;
-            }
-            if (active) {
-                const double nd = (double)nn * cs.F_N / vol;
-                const double p = nd * kKB * T;
-                const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
-                const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
-                double dtc;
-                if (cs.dim == 0) {
-                    dtc = dtG;
-                } else {
-                    const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-                    dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
-                }
-                double dtS;
-                if (dtc <= tau) {
-                    dtD = dtG;
-                    dtS = 0.0;
-                } else {
-                    dtD = (tau / dtc) * dtG;
-                    dtS = dtG - dtD;
-                }
-                pr = -expm1(-dtS / tau);
-                double a_max = 1.0;
-                if (pr > 0.0) {
-                    const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
-                    a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
-                    c_par[lane][0] = (P)Q[0];
-                    c_par[lane][1] = (P)Q[1];
-                    c_par[lane][2] = (P)Q[2];
-                    c_par[lane][3] = (P)p;
-                    c_par[lane][4] = (P)(gas.R * T);
-                    c_par[lane][5] = (P)sqrt(2.0 * gas.R * T);
-                    c_par[lane][6] = (P)a_max;
-                }
-                scmax = C.sigc[g];
-                const double M = 0.5 * (double)nn * (double)(nn - 1) * cs.F_N * scmax * dtD / vol;
-                const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)(g - cs.cell0), st, 0).x);
-                if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
-                else raise_error(G, kErrNumeric);
-                if (tr) {
+                if (active) {
                     tr->T = T;
                     tr->tau = tau;
                     tr->dt_dsmc = dtD;
@@ -1353,263 +1379,423 @@ __global__ __launch_bounds__(64) void k_collide_phys(Ctx C)
                 }
             }
         }
-        if (own) {
-            c_pr[lane] = pr;
-            c_rel[lane][0] = c_rel[lane][1] = c_rel[lane][2] = 0;
+    }
+    wave_add(&G->counters[0][0], HS_NUM_COUNTERS, my_case, HS_CNT_SKIPPED_CELLS, skipped, my_case >= 0);
+}
+
+// Steps (4)-(5) of the tiles' cells on the sorted state: NTC, SP-Shakhov resampling, Eq. 19
+// rescale and sampling, with the velocities of the tile's cells (contiguous in the new
+// state) staged in LDS and the cell scalars from k_cell_scalars.  Cells are served by lane
+// groups as in k_cell_scalars; after the NTC every lane reads and writes only its own
+// particles.
+template <typename P, int TW, int D>
+__global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
+{
+    constexpr int MAXC = TW / 4;
+    constexpr int MAXP = TW + D;
+    constexpr int MAXK = 128;             // NTC candidates per chunk (two per lane)
+    static_assert(MAXC <= 64, "one lane per cell at least");
+    // claim word per particle slot: (round << 8) | (255 - candidate), rounds numbered across
+    // the whole launch, so words of earlier rounds always lose an atomicMax of this round
+    __shared__ uint32_t s_claim[MAXP];
+    __shared__ P s_v[3][MAXP];
+    __shared__ int32_t c_start[MAXC], c_off[MAXC + 1], c_kb[MAXC + 1];
+    __shared__ P c_scm[MAXC];
+    __shared__ unsigned long long c_obs[MAXC], c_hash[MAXC];
+    __shared__ int32_t c_nacc[MAXC];
+    __shared__ uint8_t c_case[MAXC], c_samp[MAXC];
+    __shared__ uint32_t c_seed[MAXC][2], c_lcid[MAXC];
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int lane = threadIdx.x;
+    for (int s = lane; s < MAXP; s += 64) s_claim[s] = 0u;
+    uint32_t round = 0;
+    const int64_t step = G->step;
+    const uint32_t st = (uint32_t)step;
+    const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
+    const int ntiles = G->n_tiles;
+    const int NC = C.ncells_total;
+    const GasDev &gas = C.gas;
+    const bool tracing = C.trace != nullptr;
+    CellCounts cc{0, 0, 0, 0, 0, 0};
+    int my_case = -1;
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int cb = C.tile_cell[t];
+        const int ncl = C.tile_cell[t + 1] - cb;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+            if (lane == 0) raise_error(G, kErrState);
+            return;
         }
+        if (ncl == 0) continue;          // a tile inside one dense cell
+        // lane groups: 2^kb lanes per cell; the group's cell scalars
+        const int kb = ncl == 1 ? 6 : 6 - (32 - __clz(ncl - 1));
+        const int kk = 1 << kb;
+        const int gc = lane >> kb, sub = lane & (kk - 1);
+        const bool own = gc < ncl;
+        const int g = cb + gc;
+        // cell table: lane = local cell
+        int nn0 = 0, n_lane = 0;
+        if (lane < ncl) {
+            const int g0 = cb + lane;
+            const int start = C.cstart[g0];
+            n_lane = C.cstart[g0 + 1] - start;
+            c_start[lane] = start;
+            const int ci = case_of(C, g0);
+            const CaseDev &cs = C.cases[ci];
+            c_case[lane] = (uint8_t)ci;
+            c_seed[lane][0] = cs.seed_lo;
+            c_seed[lane][1] = cs.seed_hi;
+            c_lcid[lane] = (uint32_t)(g0 - cs.cell0);
+            c_samp[lane] = step >= cs.n_steady ? 1 : 0;
+            nn0 = n_lane > D ? 0 : n_lane;
+        }
+        const int incl = wave_incl_scan(nn0);
+        const int np = __shfl(incl, 63, 64);
+        if (lane < ncl) c_off[lane] = incl - nn0;
+        if (lane == 0) c_off[ncl] = np;
+        team_sync<64>();
+        // velocities of the sorted state (written by k_sort_gather), all loads issued before
+        // the first is used; FP32 words go straight from memory into LDS
+        {
+            constexpr int R = (MAXP + 63) / 64;
+            if constexpr (sizeof(P) == 4) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = lane + 64 * r;
+                    if (s < np) {
+                        int a = 0, b = ncl - 1;
+                        while (a < b) {
+                            const int mid = (a + b + 1) >> 1;
+                            if (c_off[mid] <= s) a = mid;
+                            else b = mid - 1;
+                        }
+                        const uint32_t i = (uint32_t)(c_start[a] + (s - c_off[a]));
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            __builtin_amdgcn_global_load_lds((const void *)(Dd.vel[c] + i),
+                                                             (__attribute__((address_space(3))) void *)&s_v[c][64 * r],
+                                                             4, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): the LDS words have landed
+            } else {
+                uint32_t boff[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = lane + 64 * r;
+                    boff[r] = 0;
+                    if (s < np) {
+                        int a = 0, b = ncl - 1;
+                        while (a < b) {
+                            const int mid = (a + b + 1) >> 1;
+                            if (c_off[mid] <= s) a = mid;
+                            else b = mid - 1;
+                        }
+                        boff[r] = (uint32_t)(c_start[a] + (s - c_off[a])) * (uint32_t)sizeof(P);
+                    }
+                }
+                P gv[R][3];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (lane + 64 * r < np) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) gv[r][c] = ld_off(Dd.vel[c], boff[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = lane + 64 * r;
+                    if (s < np) {
+                        s_v[0][s] = gv[r][0];
+                        s_v[1][s] = gv[r][1];
+                        s_v[2][s] = gv[r][2];
+                    }
+                }
+            }
+        }
+        team_sync<64>();
+        double scmax = 0.0, U[3] = {0.0, 0.0, 0.0}, T = 0.0, pr = 0.0;
+        P par[7] = {(P)0, (P)0, (P)0, (P)0, (P)0, (P)0, (P)0};
+        long long ncol = 0;
+        bool active = false;
+        if (own) {
+            const double *R = C.cellrec + (size_t)kRecLen * g;
+            scmax = R[kRecScm];
+            ncol = (long long)R[kRecNcol];
+            active = R[kRecAct] != 0.0;
+            U[0] = R[kRecU + 0];
+            U[1] = R[kRecU + 1];
+            U[2] = R[kRecU + 2];
+            T = R[kRecT];
+            pr = R[kRecPr];
+            if (pr > 0.0) {
+#pragma unroll
+                for (int j = 0; j < 7; ++j) par[j] = (P)R[kRecPar + j];
+            }
+        }
+        const int cn = __shfl(n_lane, gc & 63, 64);
+        const bool work = own && cn <= D;
+        if (!work) {
+            active = false;
+            ncol = 0;
+            pr = 0.0;
+        }
+        const int cid = own ? c_case[gc] : 0;
+        const bool lead = work && sub == 0;
+        TraceDev *tr = (lead && tracing) ? &C.trace[g] : nullptr;
+        if (work && cid != my_case) {
+            if (my_case >= 0) flush_counts(C, my_case, cc);
+            my_case = cid;
+        }
+
         // candidate ranges of the cells
-        const int kincl = wave_incl_scan((int)ncol);
+        const int nc_l = lead ? (int)ncol : 0;
+        const int kincl = wave_incl_scan(nc_l);
         const int kall = __shfl(kincl, 63, 64);
-        if (own) c_kb[lane] = kincl - (int)ncol;
+        if (sub == 0 && own) {
+            c_kb[gc] = kincl - nc_l;
+            c_scm[gc] = (P)scmax;
+            c_obs[gc] = 0ull;
+            c_hash[gc] = 0ull;
+            c_nacc[gc] = 0;
+        }
         if (lane == 0) c_kb[ncl] = kall;
         team_sync<64>();
 
-        // ---- NTC (Eq. 5-9).  Random numbers of a chunk of candidates are drawn by all
-        // lanes; then, in rounds, every candidate whose two particles are not used by an
-        // earlier unprocessed candidate of the chunk is processed (such candidates commute,
-        // so the outcome equals the sequential order of Eq. 5-9); (sigma c)_max is fixed
-        // during the step.
-        if (own) {
-            c_scm[lane] = (P)scmax;
-            c_obs[lane] = 0ull;
-            c_hash[lane] = 0ull;
-            c_nacc[lane] = 0;
-        }
+        // ---- NTC (Eq. 5-9).  The candidates of a chunk are prepared by all lanes (two per
+        // lane, kept in registers).  Then, in rounds, every pending candidate that is the
+        // lowest-numbered pending user of both its particles is processed: such candidates
+        // share no particle with each other or with an earlier pending candidate, so the
+        // outcome equals the sequential order of Eq. 5-9.  (sigma c)_max is fixed during the
+        // step.
+        const P K_vhs = (P)gas.K_vhs, ex_vhs = (P)gas.vhs_exp;
         for (int kbase = 0; kbase < kall; kbase += MAXK) {
             const int kn = min(MAXK, kall - kbase);
-            for (int q = lane; q < kn; q += 64) {
-                const int x = kbase + q;
-                int a = 0, b = ncl - 1;
-                while (a < b) {
-                    const int mid = (a + b + 1) >> 1;
-                    if (c_kb[mid] <= x) a = mid;
-                    else b = mid - 1;
+            int ci[2], cj[2], clc[2], ck[2];
+            P cu[2], om[2][3];
+            bool pend[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int q = lane + 64 * r;
+                pend[r] = q < kn;
+                ci[r] = cj[r] = clc[r] = ck[r] = 0;
+                cu[r] = om[r][0] = om[r][1] = om[r][2] = (P)0;
+                if (pend[r]) {
+                    const int x = kbase + q;
+                    int a = 0, b = ncl - 1;
+                    while (a < b) {
+                        const int mid = (a + b + 1) >> 1;
+                        if (c_kb[mid] <= x) a = mid;
+                        else b = mid - 1;
+                    }
+                    const int kc = x - c_kb[a];
+                    const int o2 = c_off[a], cn = c_off[a + 1] - o2;
+                    const uint32_t sd0 = c_seed[a][0], sd1 = c_seed[a][1], lcid = c_lcid[a];
+                    const W4 w = draw_s(sd0, sd1, kStreamCell, lcid, st, (uint32_t)(1 + 2 * kc));
+                    const uint32_t i = unidx(w.x, (uint32_t)cn);
+                    uint32_t j = unidx(w.y, (uint32_t)(cn - 1));
+                    if (j >= i) ++j;
+                    ci[r] = o2 + (int)i;
+                    cj[r] = o2 + (int)j;
+                    clc[r] = a;
+                    ck[r] = kc;
+                    cu[r] = Real<P>::uni(w.z);
+                    const W4 w2 = draw_s(sd0, sd1, kStreamCell, lcid, st, (uint32_t)(2 + 2 * kc));
+                    const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
+                    const P schi = Real<P>::sq((P)1 - cchi * cchi);
+                    P sth, cth;
+                    Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
+                    om[r][0] = cchi;
+                    om[r][1] = schi * cth;
+                    om[r][2] = schi * sth;
                 }
-                const int k = x - c_kb[a];
-                const int o = c_off[a], cn = c_off[a + 1] - o;
-                const CaseDev &cs = C.cases[c_case[a]];
-                const uint32_t lcid = (uint32_t)(cb + a - cs.cell0);
-                const W4 w = draw(cs, kStreamCell, lcid, st, (uint32_t)(1 + 2 * k));
-                const uint32_t i = unidx(w.x, (uint32_t)cn);
-                uint32_t j = unidx(w.y, (uint32_t)(cn - 1));
-                if (j >= i) ++j;
-                k_k[q] = k;
-                k_i[q] = (uint16_t)(o + i);
-                k_j[q] = (uint16_t)(o + j);
-                k_cell[q] = (uint8_t)a;
-                k_u[q] = Real<P>::uni(w.z);
-                const W4 w2 = draw(cs, kStreamCell, lcid, st, (uint32_t)(2 + 2 * k));
-                const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
-                const P schi = Real<P>::sq((P)1 - cchi * cchi);
-                P sth, cth;
-                Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
-                k_om[q] = cchi;
-                k_om[MAXK + q] = schi * cth;
-                k_om[2 * MAXK + q] = schi * sth;
             }
-            bool done0 = lane >= kn, done1 = lane + 64 >= kn;
             for (;;) {
-                for (int t2 = lane; t2 < np; t2 += 64) s_first[t2] = 0x7fffffff;
-                team_sync<64>();
-                if (!done0) {
-                    atomicMin(&s_first[k_i[lane]], lane);
-                    atomicMin(&s_first[k_j[lane]], lane);
+                if (!__any(pend[0] || pend[1])) break;
+                if (round == 0xffffffu) {          // round counter exhausted: clear the claims
+                    team_sync<64>();
+                    for (int s2 = lane; s2 < MAXP; s2 += 64) s_claim[s2] = 0u;
+                    round = 0;
+                    team_sync<64>();
                 }
-                if (!done1) {
-                    atomicMin(&s_first[k_i[lane + 64]], lane + 64);
-                    atomicMin(&s_first[k_j[lane + 64]], lane + 64);
+                ++round;
+                uint32_t tag[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    tag[r] = (round << 8) | (uint32_t)(255 - (lane + 64 * r));
+                    if (pend[r]) {
+                        atomicMax(&s_claim[ci[r]], tag[r]);
+                        atomicMax(&s_claim[cj[r]], tag[r]);
+                    }
                 }
-                if (!__any(!(done0 && done1))) break;
                 team_sync<64>();
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
-                    const int q = lane + 64 * r;
-                    const bool d = r == 0 ? done0 : done1;
-                    if (d) continue;
-                    const int i = k_i[q], j = k_j[q];
-                    if (s_first[i] != q || s_first[j] != q) continue;
-                    const int lc = k_cell[q];
+                    if (!pend[r]) continue;
+                    const int i = ci[r], j = cj[r];
+                    if (s_claim[i] != tag[r] || s_claim[j] != tag[r]) continue;
+                    pend[r] = false;
+                    const int lc = clc[r];
                     P *vx = s_v[0], *vy = s_v[1], *vz = s_v[2];
                     const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
                     const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
                     P sc;
                     if constexpr (sizeof(P) == 4)
-                        sc = cr > (P)0 ? (P)gas.K_vhs * __builtin_amdgcn_exp2f((P)gas.vhs_exp * __builtin_amdgcn_logf(cr))
-                                       : (P)0;
+                        sc = cr > (P)0 ? K_vhs * __builtin_amdgcn_exp2f(ex_vhs * __builtin_amdgcn_logf(cr)) : (P)0;
                     else
                         sc = gas.K_vhs * pow(cr, gas.vhs_exp);
                     atomicMax(&c_obs[lc], (unsigned long long)__double_as_longlong((double)sc));
-                    if (k_u[q] < sc / c_scm[lc]) {
-                        const P o0 = k_om[q], o1 = k_om[MAXK + q], o2 = k_om[2 * MAXK + q];
+                    if (cu[r] < sc / c_scm[lc]) {
                         const P sx = vx[i] + vx[j], sy = vy[i] + vy[j], sz = vz[i] + vz[j];
-                        vx[i] = (P)0.5 * (sx - cr * o0);
-                        vx[j] = (P)0.5 * (sx + cr * o0);
-                        vy[i] = (P)0.5 * (sy - cr * o1);
-                        vy[j] = (P)0.5 * (sy + cr * o1);
-                        vz[i] = (P)0.5 * (sz - cr * o2);
-                        vz[j] = (P)0.5 * (sz + cr * o2);
+                        vx[i] = (P)0.5 * (sx - cr * om[r][0]);
+                        vx[j] = (P)0.5 * (sx + cr * om[r][0]);
+                        vy[i] = (P)0.5 * (sy - cr * om[r][1]);
+                        vy[j] = (P)0.5 * (sy + cr * om[r][1]);
+                        vz[i] = (P)0.5 * (sz - cr * om[r][2]);
+                        vz[j] = (P)0.5 * (sz + cr * om[r][2]);
                         atomicAdd(&c_nacc[lc], 1);
-                        atomicXor(&c_hash[lc], (unsigned long long)(k_k[q] + 1) * 0x9E3779B97F4A7C15ull);
+                        atomicXor(&c_hash[lc], (unsigned long long)(ck[r] + 1) * 0x9E3779B97F4A7C15ull);
                     }
-                    if (r == 0) done0 = true;
-                    else done1 = true;
                 }
                 team_sync<64>();
             }
-            team_sync<64>();
         }
-        if (work && active) {
-            const double obs = __longlong_as_double((long long)c_obs[lane]);
+        team_sync<64>();
+        if (lead && active) {
+            const double obs = __longlong_as_double((long long)c_obs[gc]);
             if (obs > scmax) C.sigc[g] = obs;
             cc.cand += ncol;
-            cc.acc += c_nacc[lane];
+            cc.acc += c_nacc[gc];
             if (tr) {
                 tr->ncol = ncol;
-                tr->nacc = c_nacc[lane];
-                tr->acc_hash = c_hash[lane];
+                tr->nacc = c_nacc[gc];
+                tr->acc_hash = c_hash[gc];
             }
         }
 
-        // ---- SP-Shakhov relaxation (Eq. 16-18), one lane per slot
-        for (int s = lane; s < np; s += 64) {
-            const int lc = s_lc[s];
-            const double p_r = c_pr[lc];
-            if (!(p_r > 0.0)) continue;
-            const CaseDev &cs = C.cases[c_case[lc]];
-            const int64_t id = Dd.id[(size_t)c_start[lc] + (s - c_off[lc])];
-            if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < p_r)) continue;
-            P Cv[3];
-            int used = shakhov_draw<P>(cs, id, st, c_par[lc], (P)(1.0 - gas.Pr), Cv);
-            int capd = 0;
-            if (used < 0) {
-                capd = 1;
-                used = -used;
-            }
-            s_v[0][s] = (P)(c_U[lc][0] + (double)Cv[0]);
-            s_v[1][s] = (P)(c_U[lc][1] + (double)Cv[1]);
-            s_v[2][s] = (P)(c_U[lc][2] + (double)Cv[2]);
-            atomicAdd(&c_rel[lc][0], 1);
-            atomicAdd(&c_rel[lc][1], used);
-            if (capd) atomicAdd(&c_rel[lc][2], 1);
-        }
-        team_sync<64>();
+        const int o = work ? c_off[gc] : 0;
+        const int nn = work ? c_off[gc + 1] - o : 0;
 
-        // ---- Eq. 19 rescale: post-collision sums, factor per cell, applied per slot
-        double r1[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int base = 0; base < np; base += 64) {
-            const int s = base + lane;
-            double x[4] = {0.0, 0.0, 0.0, 0.0};
-            int head = lane;
-            if (s < np) {
-                const int lc = s_lc[s];
-                head = max(c_off[lc] - base, 0);
-                x[0] = (double)s_v[0][s];
-                x[1] = (double)s_v[1][s];
-                x[2] = (double)s_v[2][s];
-            }
-            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
-            seg_round<4>(x, head, tail, r1);
-        }
-        if (own) {
-            double f = 0.0;
-            if (active) {
-                const double Up[3] = {r1[0] / (double)nn, r1[1] / (double)nn, r1[2] / (double)nn};
-                for (int a = 0; a < 3; ++a) c_Up[lane][a] = Up[a];
-                f = -1.0;      // the spread is summed in the next pass
-            }
-            c_f[lane] = f;
-        }
-        team_sync<64>();
-        double r2[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int base = 0; base < np; base += 64) {
-            const int s = base + lane;
-            double x[4] = {0.0, 0.0, 0.0, 0.0};
-            int head = lane;
-            if (s < np) {
-                const int lc = s_lc[s];
-                head = max(c_off[lc] - base, 0);
-                if (c_f[lc] < 0.0) {
-                    const double cx = (double)s_v[0][s] - c_Up[lc][0], cy = (double)s_v[1][s] - c_Up[lc][1],
-                                 cz = (double)s_v[2][s] - c_Up[lc][2];
-                    x[0] = cx * cx + cy * cy + cz * cz;
+        // SP-Shakhov relaxation (Eq. 16-18); the ids of four particles are fetched at once
+        int rel0 = 0, rel1 = 0, rel2 = 0;
+        if (pr > 0.0) {
+            const int64_t *ids = Dd.id + c_start[gc];
+            const uint32_t sd0 = c_seed[gc][0], sd1 = c_seed[gc][1];
+#pragma unroll 1
+            for (int i0 = sub; i0 < nn; i0 += 4 * kk) {
+                int64_t idv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * kk;
+                    idv[u] = i < nn ? ids[i] : 0;
+                }
+#pragma unroll 1
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * kk;
+                    if (i >= nn) break;
+                    const int64_t id = idv[u];
+                    if (!(unid(draw_s(sd0, sd1, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
+                    P Cv[3];
+                    int used = shakhov_draw<P>(sd0, sd1, id, st, par, (P)(1.0 - gas.Pr), Cv);
+                    if (used < 0) {
+                        ++rel2;
+                        used = -used;
+                    }
+                    s_v[0][o + i] = (P)(U[0] + (double)Cv[0]);
+                    s_v[1][o + i] = (P)(U[1] + (double)Cv[1]);
+                    s_v[2][o + i] = (P)(U[2] + (double)Cv[2]);
+                    ++rel0;
+                    rel1 += used;
                 }
             }
-            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
-            seg_round<4>(x, head, tail, r2);
         }
-        if (own) {
-            double f = 0.0;
-            if (active) {
-                const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
-                f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+        cc.relax += rel0;
+        cc.ar += rel1;
+        cc.arcap += rel2;
+
+        // Eq. 19 rescale to the Step (3) U and T
+        double r1[3] = {0.0, 0.0, 0.0};
+        if (active) {
+            for (int i = sub; i < nn; i += kk) {
+                r1[0] = r1[0] + (double)s_v[0][o + i];
+                r1[1] = r1[1] + (double)s_v[1][o + i];
+                r1[2] = r1[2] + (double)s_v[2][o + i];
             }
-            c_f[lane] = f;
         }
-        team_sync<64>();
-        // apply, then Step (5) sums of the final velocities
+        group_sum<3>(r1, kb);
+        double Up[3] = {0.0, 0.0, 0.0};
+        double r2[1] = {0.0};
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Up[a] = r1[a] / (double)nn;
+            for (int i = sub; i < nn; i += kk) {
+                const double cx = (double)s_v[0][o + i] - Up[0], cy = (double)s_v[1][o + i] - Up[1], cz = (double)s_v[2][o + i] - Up[2];
+                r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
+            }
+        }
+        group_sum<1>(r2, kb);
+        double f = 0.0;
+        if (active) {
+            const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
+            f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+        }
+        // apply, write the final velocities, Step (5) sums
+        const bool sampling = work && c_samp[gc] != 0;
+        const bool sums = sampling || (tracing && work);
         double sm[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) sm[j] = 0.0;
-        for (int base = 0; base < np; base += 64) {
-            const int s = base + lane;
-            double x[12];
-#pragma unroll
-            for (int j = 0; j < 12; ++j) x[j] = 0.0;
-            int head = lane;
-            if (s < np) {
-                const int lc = s_lc[s];
-                head = max(c_off[lc] - base, 0);
-                double a = (double)s_v[0][s], b = (double)s_v[1][s], c = (double)s_v[2][s];
-                const double f = c_f[lc];
+        if (f > 0.0 || sums) {
+            for (int i = sub; i < nn; i += kk) {
+                double a = (double)s_v[0][o + i], b = (double)s_v[1][o + i], c = (double)s_v[2][o + i];
                 if (f > 0.0) {
-                    a = c_U[lc][0] + (a - c_Up[lc][0]) * f;
-                    b = c_U[lc][1] + (b - c_Up[lc][1]) * f;
-                    c = c_U[lc][2] + (c - c_Up[lc][2]) * f;
-                    s_v[0][s] = (P)a;
-                    s_v[1][s] = (P)b;
-                    s_v[2][s] = (P)c;
+                    a = U[0] + (a - Up[0]) * f;
+                    b = U[1] + (b - Up[1]) * f;
+                    c = U[2] + (c - Up[2]) * f;
+                    const size_t d = (size_t)c_start[gc] + i;
+                    Dd.vel[0][d] = (P)a;
+                    Dd.vel[1][d] = (P)b;
+                    Dd.vel[2][d] = (P)c;
                 }
-                const double c2 = a * a + b * b + c * c;
-                x[0] = a; x[1] = b; x[2] = c;
-                x[3] = a * a; x[4] = b * b; x[5] = c * c;
-                x[6] = a * b; x[7] = a * c; x[8] = b * c;
-                x[9] = c2 * a; x[10] = c2 * b; x[11] = c2 * c;
+                if (sums) {
+                    const double c2 = a * a + b * b + c * c;
+                    sm[0] += a; sm[1] += b; sm[2] += c;
+                    sm[3] += a * a; sm[4] += b * b; sm[5] += c * c;
+                    sm[6] += a * b; sm[7] += a * c; sm[8] += b * c;
+                    sm[9] += c2 * a; sm[10] += c2 * b; sm[11] += c2 * c;
+                }
             }
-            const int tail = (own && my_e > my_o && my_o < base + 64 && my_e > base) ? min(my_e, base + 64) - 1 - base : -1;
-            seg_round<12>(x, head, tail, sm);
         }
-        if (work) {
-            const CaseDev &cs = C.cases[cid];
-            cc.relax += c_rel[lane][0];
-            cc.ar += c_rel[lane][1];
-            cc.arcap += c_rel[lane][2];
-            if (step >= cs.n_steady) {
-                double *A = &C.acc[13 * (size_t)g];
-                A[0] += (double)nn;
+        if (__any(sums)) group_sum<12>(sm, kb);
+        int nrel[3] = {rel0, rel1, rel2};
+        if (tracing) {
 #pragma unroll
-                for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
+            for (int j = 0; j < 3; ++j) nrel[j] = group_sum_i(nrel[j], kb);
+        }
+        if (lead) {
+            if (sampling) {
+                // one add per cell and step (no other thread touches the cell's sums), so the
+                // result equals a load-add-store; the atomic form needs no return value
+                double *A = &C.acc[13 * (size_t)g];
+                unsafeAtomicAdd(&A[0], (double)nn);
+#pragma unroll
+                for (int j = 0; j < 12; ++j) unsafeAtomicAdd(&A[1 + j], sm[j]);
             }
-            if (tr) {
+            if (tracing) {
+                TraceDev *tr = &C.trace[g];
                 tr->post_sum[0] = sm[0];
                 tr->post_sum[1] = sm[1];
                 tr->post_sum[2] = sm[2];
                 tr->post_sum[3] = sm[3] + sm[4] + sm[5];
-                tr->nrelax = c_rel[lane][0];
-                tr->ar_attempts = c_rel[lane][1];
-                tr->ar_cap = c_rel[lane][2];
+                tr->nrelax = nrel[0];
+                tr->ar_attempts = nrel[1];
+                tr->ar_cap = nrel[2];
             }
-        }
-        // write the velocities of the sorted state
-        for (int s = lane; s < np; s += 64) {
-            const int lc = s_lc[s];
-            const size_t dst = (size_t)c_start[lc] + (s - c_off[lc]);
-            Dd.vel[0][dst] = s_v[0][s];
-            Dd.vel[1][dst] = s_v[1][s];
-            Dd.vel[2][dst] = s_v[2][s];
         }
         team_sync<64>();
     }
-    if (my_case >= 0) flush_counts(C, my_case, cc);
+    wave_flush_counts(C, my_case, cc);
 }
 
 // Sort `a[0..p2)` ascending in LDS with a bitonic network (p2 a power of two).
@@ -1691,7 +1877,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
                 P Cv[3];
-                int used = shakhov_draw<P>(cs, id, st, s_par, (P)(1.0 - C.gas.Pr), Cv);
+                int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, s_par, (P)(1.0 - C.gas.Pr), Cv);
                 if (used < 0) {
                     ++ncap;
                     used = -used;
@@ -1887,6 +2073,11 @@ void Launch::init_finish(const Ctx &c, void *s)
 {
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(256), 0, S_(s), c, (int64_t)0);
 }
+void Launch::tile_table(const Ctx &c, void *s)
+{
+    hipLaunchKernelGGL(k_tile_table, dim3((c.ncells_total + kBlock - 1) / kBlock), dim3(kBlock), 0, S_(s), c);
+}
+
 void Launch::scan_cells(const Ctx &c, void *s, int build_big)
 {
     const int nparts = blocks_for(c.ncells_total, kScanTile);
@@ -1922,16 +2113,22 @@ void Launch::scatter(const Ctx &c, void *s)
 }
 void Launch::collide(const Ctx &c, void *s)
 {
+    // tile kernels loop over tiles with a fixed grid: wide for the streaming gather and
+    // scalar kernels, about the resident capacity for the collision kernel (its per-wave
+    // setup and counter flush are paid once per block)
     const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
-    const int gt = (int)std::max(1ll, std::min(maxtiles, 256ll * 32));
+    const int gw = (int)std::max(1ll, std::min(maxtiles, 256ll * 32));
+    const int gt = (int)std::max(1ll, std::min(maxtiles, 256ll * 8));
     const int gb = std::max(1, std::min(c.ncells_total, 256 * 2));
     if (c.precision == HS_FP64) {
-        hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_phys<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_cell_scalars<double, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_tile<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
         hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
     } else {
-        hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_phys<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_cell_scalars<float, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
+        hipLaunchKernelGGL((k_collide_tile<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
         hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
     }
 }

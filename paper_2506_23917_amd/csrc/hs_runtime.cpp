@@ -24,7 +24,7 @@ struct Layout {
     size_t total = 0;
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
-    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, trace, out;
+    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, cellrec, trace, out;
 };
 
 struct Plan {
@@ -261,6 +261,8 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.facestart = take(4 * (P.faces.size() + 1));
     L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
     L.big = take(4 * nc);
+    L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + 3));
+    L.cellrec = take(8 * 16 * nc);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
     size_t maxcase = 1;
     for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
@@ -431,6 +433,8 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.face_start = (int32_t *)(w + L.facestart);
     c.scan_part = (int32_t *)(w + L.scanpart);
     c.big_list = (int32_t *)(w + L.big);
+    c.tile_cell = (int32_t *)(w + L.tiles);
+    c.cellrec = (double *)(w + L.cellrec);
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
     c.tile_w = tile_width();
     c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
@@ -740,6 +744,9 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     G.next_id[c] = hd.next_id;
     G.n_samples[c] = hd.n_samples;
     HIPCHK(s, hipMemcpy(s->ws + s->lay.globals, &G, sizeof(G), hipMemcpyHostToDevice));
+    Launch::tile_table(s->ctx, s->stream);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipStreamSynchronize(s->stream));
     if (!s->plan.any_spatial) {
         launch_build_big(s->ctx, s->stream);
         HIPCHK(s, hipGetLastError());
