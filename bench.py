@@ -1,20 +1,27 @@
 """Throughput of the hybrid SP-Shakhov / DSMC particle update on one MI355X.
 
-Workload: the 2-D Ma 10 argon flow over a cylinder (Kn 0.01 on D, 800 x 600 cut-cell
-grid, ~14.2M particles, diffuse wall at 500 K, freestream inflow on three sides), run
-from the impulsive start for --warmup steps, then --steps timed steps with sampling on.
-The headline runs the FP32-mixed path; the FP64 path is timed on the same workload for
-the speed-up.  One step = the whole hot path: inflow, transport + walls, counting sort,
-moments, time split, NTC DSMC, Shakhov resampling, conservation rescale, sampling.
+Workload: the 2-D Ma 10 argon flow over a cylinder (Kn 0.01 on D, 800 x 600 cut-cell grid,
+~14.2M particles, diffuse wall at 500 K, freestream inflow on three sides, vacuum outflow),
+run from the impulsive start for --warmup steps, then --steps timed steps with sampling on.
+The headline runs the FP32-mixed path; the FP64 path is timed on the same workload for the
+speed-up.  One step = the whole hot path: inflow, transport + walls, counting sort, moments,
+time split, NTC DSMC, Shakhov resampling, conservation rescale, sampling.  Inputs are
+resident in HBM when the timed region starts (the state never leaves the device).
 
-Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: this build runs on
-one GPU.
+The roofline object is for the dominant kernel (the tile collision kernel), timed with HIP
+events on the simulation's stream inside the timed region.  Its HBM traffic comes from a
+committed rocprofv3 counter summary and is reported only while the kernel sources are the
+ones it was measured on.
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,29 +29,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the collide kernel (FP32-mixed, 2-D): per particle, the source index
-# (4), the gathered source state x, y, vx, vy, vz, cell, id (32) and the written state (32);
-# per cell, cell_start (4), volume (8), (sigma c)_max read + write (16) and, when sampling,
-# the 13 FP64 sums read + written (208).
-COLLIDE_BYTES_PER_PARTICLE = {"fp32": 68, "fp64": 4 + 64 + 64}
-COLLIDE_BYTES_PER_CELL = 4 + 8 + 16 + 208
+# Algorithmic bytes of one launch of the tile collision kernel (FP32-mixed): per particle,
+# its velocity read and written (12 + 12); per cell, cell_start (4), the scalar record
+# U, T, P_relax, (sigma c)_max, N_col, flags (64), (sigma c)_max written (8) and the 13 FP64
+# sampling sums read and written (208).
+TILE_BYTES_PER_PARTICLE = 24
+TILE_BYTES_PER_CELL = 4 + 64 + 8 + 208
+# Whole step, FP32-mixed 2-D: one state read + write for the sort and one for move and
+# collide, plus cell traffic (about 128 B per particle-step).
+STEP_BYTES_PER_PARTICLE = 128
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_traffic.txt")
+KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.hpp", "hs_common.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(prec, case, gas, warmup, steps, graph_check=True):
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2506_23917_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per launch of the tile kernel from the committed counter summary, if it was
+    measured on the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def run_gpu(prec, case, gas, warmup, steps):
     import torch
     from paper_2506_23917_amd.hs import Sim
 
     sim = Sim(gas, case, precision=prec, device="cuda:0")
-    sim.set_timing(True)
     sim.step(warmup)
     sim.sync()
-    warm_ms, warm_n = sim.kernel_timing("collide")
-    sim.clear_timing()
     n0 = sim.num_particles(0)
+    sim.set_timing(["collide"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -52,16 +83,13 @@ def run_gpu(prec, case, gas, warmup, steps, graph_check=True):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n1 = sim.num_particles(0)
-    res = dict(dt=dt, n0=n0, n1=n1)
-    for k in ("inject", "move", "scan", "scatter", "collide", "step"):
-        res[k + "_ms"] = sim.kernel_timing(k)[0]
-    res["collide_ms_all"] = (warm_ms * warm_n + res["collide_ms"] * steps) / max(1, warm_n + steps)
-    sim.clear_timing()
+    tile_ms, launches = sim.kernel_timing("collide")
     sim.set_timing(False)
-    return sim, res
+    sim.clear_timing()
+    return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches)
 
 
-def cpu_baseline(sim, case, gas, nsteps=1):
+def cpu_baseline(sim, case, gas, nsteps):
     """The FP64 oracle, single-threaded, on the GPU's developed state (imported), for
     nsteps steps; particle-steps / s."""
     import numpy as np
@@ -89,58 +117,53 @@ def main():
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=1)
-    ap.add_argument("--traffic", default=None, help="JSON file with rocprof FETCH/WRITE bytes per collide launch")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps of the CPU baseline sample")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import workloads as W
     gas = W.gas()
     case = W.cylinder_2d()
     case["n_steady"] = args.warmup          # the timed steps sample (Step 5 is on)
+    ncells = case["nx"] * case["ny"]
 
     log("[bench] fp32-mixed: warmup %d, timed %d" % (args.warmup, args.steps))
     sim32, r32 = run_gpu("fp32", case, gas, args.warmup, args.steps)
-    psteps = 0.5 * (r32["n0"] + r32["n1"]) * args.steps
-    value = psteps / r32["dt"]
-    ncells = case["nx"] * case["ny"]
     npart = 0.5 * (r32["n0"] + r32["n1"])
-    sampling_cells = ncells
-    coll_bytes = COLLIDE_BYTES_PER_PARTICLE["fp32"] * npart + COLLIDE_BYTES_PER_CELL * sampling_cells
-    achieved = coll_bytes / (r32["collide_ms"] * 1e-3) / 1e9
-    log("[bench] fp32: %.3f ms/step, %.3e particle-steps/s, collide %.3f ms" %
-        (1e3 * r32["dt"] / args.steps, value, r32["collide_ms"]))
-
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            t = json.load(f)
-        traffic = t.get("bytes_per_launch")
+    value = npart * args.steps / r32["dt"]
+    ms_step = 1e3 * r32["dt"] / args.steps
+    tile_bytes = TILE_BYTES_PER_PARTICLE * npart + TILE_BYTES_PER_CELL * ncells
+    achieved = tile_bytes / (r32["tile_ms"] * 1e-3) / 1e9
+    traffic = committed_traffic()
+    log("[bench] fp32: %.3f ms/step, %.3e particle-steps/s, tile kernel %.3f ms" % (ms_step, value, r32["tile_ms"]))
 
     out = {
-        "metric": "particle-steps/s, 2-D Ma10 cylinder: FP32-mixed vs FP64 at <=1e-3 moment error",
+        "metric": "particle-steps/s, 2-D Ma10 cylinder: FP32-mixed vs FP64 at ≤1e-3 moment error",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * r32["dt"] / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 moments, timescales, rescale)",
+        "dtype": "f32/f64-mixed",
         "data": "synthetic",
-        "config": {"workload": "2-D Ma10 argon cylinder, Kn 0.01 on D, 800x600 cut-cell grid, "
-                               "~14.2M particles, FP32-mixed, steady sampling on",
+        "config": {"workload": "2-D Ma10 argon cylinder, Kn 0.01 on D, 800x600 cut-cell grid, ~30 particles "
+                               "per cell, FP32-mixed, developed flow with sampling on",
                    "particles": int(npart), "cells": ncells},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "collide (wave + dense-cell launches)",
-                     "kernel_ms": r32["collide_ms"], "kernel_ms_all_steps": r32["collide_ms_all"]},
-        "kernels_ms": {k: r32[k + "_ms"] for k in ("inject", "move", "scan", "scatter", "collide", "step")},
+                     "kernel": "k_collide_tile<float> (NTC, Shakhov, rescale, sampling on LDS tiles)",
+                     "kernel_ms": r32["tile_ms"], "launches_timed": r32["launches"],
+                     "algorithmic_bytes_per_launch": tile_bytes},
+        "step_roofline": {"bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
+                          "achieved_GBs": STEP_BYTES_PER_PARTICLE * value / 1e9,
+                          "frac": STEP_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_fp64:
         del sim32
@@ -149,8 +172,7 @@ def main():
         log("[bench] fp64: warmup %d, timed %d" % (args.warmup, args.steps))
         sim64, r64 = run_gpu("fp64", case, gas, args.warmup, args.steps)
         v64 = 0.5 * (r64["n0"] + r64["n1"]) * args.steps / r64["dt"]
-        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps,
-                       "collide_ms": r64["collide_ms"]}
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps, "tile_kernel_ms": r64["tile_ms"]}
         out["mixed_speedup_vs_fp64"] = value / v64
         log("[bench] fp64: %.3f ms/step, %.3e particle-steps/s" % (1e3 * r64["dt"] / args.steps, v64))
         base_sim = sim64
@@ -158,7 +180,6 @@ def main():
         base_sim = sim32
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
-        # the oracle takes FP64 state; the FP32 export is widened exactly
         v_cpu, n_cpu, t_cpu = cpu_baseline(base_sim, case, gas, args.cpu_steps)
         out["cpu_baseline"] = {"value": v_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                                "sample": "%d step(s) of the same cylinder workload from the GPU's developed "

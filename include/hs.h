@@ -57,15 +57,18 @@ enum {
     HS_FLAG_GRAPH = 4          /* replay each step as a captured hipGraph                   */
 };
 
-/* Kernel groups of one step, for hs_kernel_timing. */
+/* Kernel groups of one step, for hs_kernel_timing (bit k of the timing mask = group k). */
 enum {
-    HS_KERNEL_INJECT = 0,      /* inflow counts, scan and fill                              */
-    HS_KERNEL_MOVE = 1,        /* free transport + per-cell counts                          */
-    HS_KERNEL_SCAN = 2,        /* exclusive scan of the cell counts                         */
-    HS_KERNEL_SCATTER = 3,     /* stable scatter of particle indices                        */
-    HS_KERNEL_COLLIDE = 4,     /* per-cell gather, moments, collisions, rescale, sampling  */
-    HS_KERNEL_STEP = 5,        /* the whole step                                            */
-    HS_NUM_KERNELS = 6
+    HS_KERNEL_INJECT = 0,      /* inflow counts, scan and fill (Step 2 freestream faces)     */
+    HS_KERNEL_MOVE = 1,        /* free transport, walls, per-cell counts (Step 2)           */
+    HS_KERNEL_SCAN = 2,        /* exclusive scan of the cell counts, tile table             */
+    HS_KERNEL_SCATTER = 3,     /* scatter of particle indices by cell                       */
+    HS_KERNEL_GATHER = 4,      /* stable in-cell order, sorted state written                */
+    HS_KERNEL_SCALARS = 5,     /* Step 3 moments, Eq. 10 / 25-28 split, N_col per cell      */
+    HS_KERNEL_COLLIDE = 6,     /* Step 4-5 on the tiles: NTC, Shakhov, rescale, sampling    */
+    HS_KERNEL_DENSE = 7,       /* Steps 3-5 of the cells too dense for the tiles            */
+    HS_KERNEL_STEP = 8,        /* the whole step                                            */
+    HS_NUM_KERNELS = 9
 };
 
 /* Gas (Sec. 4): molecular mass, VHS reference diameter / temperature / viscosity and
@@ -185,12 +188,13 @@ hs_status hs_counters(hs_sim *sim, int case_id, int64_t *out);
 int64_t hs_num_cells(const hs_sim *sim, int case_id);
 int64_t hs_num_particles(hs_sim *sim, int case_id);
 
-/* Per-kernel timing with HIP events recorded on the sim's stream around each kernel group
- * of every step enqueued while timing is on (steps then run as plain launches, not as a
- * graph).  hs_kernel_timing synchronises and returns the average duration (ms) of kernel
- * group `which` (HS_KERNEL_*) over the timed steps and their number; hs_clear_timing
- * forgets them. */
-hs_status hs_set_timing(hs_sim *sim, int enable);
+/* Per-kernel timing with HIP events recorded on the sim's stream around the kernel groups
+ * selected by `mask` (bit k = HS_KERNEL_k; 0 turns timing off) in every step enqueued while
+ * timing is on (steps then run as plain launches, not as a graph).  hs_kernel_timing
+ * synchronises and returns the average duration (ms) of kernel group `which` over the
+ * timed steps and their number (0 if the group was not selected); hs_clear_timing forgets
+ * them. */
+hs_status hs_set_timing(hs_sim *sim, uint32_t mask);
 hs_status hs_kernel_timing(hs_sim *sim, int which, double *avg_ms, int64_t *launches);
 hs_status hs_clear_timing(hs_sim *sim);
 

@@ -135,7 +135,10 @@ struct Launch {
     static void inject(const Ctx &c, void *stream);
     static void move_count(const Ctx &c, void *stream, int any_body);
     static void scatter(const Ctx &c, void *stream);
+    static void gather(const Ctx &c, void *stream);
+    static void scalars(const Ctx &c, void *stream);
     static void collide(const Ctx &c, void *stream);
+    static void dense(const Ctx &c, void *stream);
     static void finish_step(const Ctx &c, void *stream);
     static void philox(uint64_t seed, uint32_t stream_id, uint64_t e0, uint32_t step,
                        uint32_t draw, int64_t n, uint32_t *out, void *stream);

@@ -2111,26 +2111,37 @@ void Launch::scatter(const Ctx &c, void *s)
     const int grid = std::min(stream_grid(), blocks_for(c.capacity, kBlock));
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, S_(s), c);
 }
+// Tile kernels loop over tiles with a fixed grid: wide for the streaming gather and scalar
+// kernels, about the resident capacity for the collision kernel (its per-wave setup and
+// counter flush are paid once per block).
+static int tile_grid(const Ctx &c, long long cap)
+{
+    const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
+    return (int)std::max(1ll, std::min(maxtiles, cap));
+}
+void Launch::gather(const Ctx &c, void *s)
+{
+    const int g = tile_grid(c, 256ll * 32);
+    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+    else hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+}
+void Launch::scalars(const Ctx &c, void *s)
+{
+    const int g = tile_grid(c, 256ll * 32);
+    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_cell_scalars<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+    else hipLaunchKernelGGL((k_cell_scalars<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+}
 void Launch::collide(const Ctx &c, void *s)
 {
-    // tile kernels loop over tiles with a fixed grid: wide for the streaming gather and
-    // scalar kernels, about the resident capacity for the collision kernel (its per-wave
-    // setup and counter flush are paid once per block)
-    const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
-    const int gw = (int)std::max(1ll, std::min(maxtiles, 256ll * 32));
-    const int gt = (int)std::max(1ll, std::min(maxtiles, 256ll * 8));
+    const int g = tile_grid(c, 256ll * 8);
+    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_collide_tile<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+    else hipLaunchKernelGGL((k_collide_tile<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+}
+void Launch::dense(const Ctx &c, void *s)
+{
     const int gb = std::max(1, std::min(c.ncells_total, 256 * 2));
-    if (c.precision == HS_FP64) {
-        hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_cell_scalars<double, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_tile<double, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
-    } else {
-        hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_cell_scalars<float, kTileW, kCapWave>), dim3(gw), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_tile<float, kTileW, kCapWave>), dim3(gt), dim3(64), 0, S_(s), c);
-        hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
-    }
+    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
+    else hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
 }
 void Launch::finish_step(const Ctx &c, void *s)
 {

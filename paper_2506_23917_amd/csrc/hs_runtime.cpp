@@ -288,8 +288,11 @@ struct hs_sim {
     bool graph_ready = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    bool timing = false;
-    std::vector<hipEvent_t> events;   // HS_NUM_KERNELS+1 per timed step... see enqueue
+    uint32_t timing = 0;                 // mask of timed kernel groups
+    struct StepEvents {
+        hipEvent_t b[HS_NUM_KERNELS], e[HS_NUM_KERNELS];
+    };
+    std::vector<StepEvents> events;      // one record per timed step
     int64_t timed_steps = 0;
 };
 
@@ -341,29 +344,47 @@ void enqueue_step(hs_sim *s, int timed)
 {
     const Ctx &c = s->ctx;
     void *st = (void *)s->stream;
-    hipEvent_t *ev = nullptr;
+    hs_sim::StepEvents *ev = nullptr;
     if (timed) {
-        const size_t base = s->events.size();
-        s->events.resize(base + 6);
-        for (size_t k = base; k < base + 6; ++k) hipEventCreate(&s->events[k]);
-        ev = &s->events[base];
-        hipEventRecord(ev[0], s->stream);
+        s->events.emplace_back();
+        ev = &s->events.back();
+        for (int k = 0; k < HS_NUM_KERNELS; ++k) ev->b[k] = ev->e[k] = nullptr;
     }
+    auto mark = [&](int k, bool begin) {
+        if (!ev || !((s->timing >> k) & 1u)) return;
+        hipEvent_t &e = begin ? ev->b[k] : ev->e[k];
+        if (hipEventCreate(&e) != hipSuccess) { e = nullptr; return; }
+        (void)hipEventRecord(e, s->stream);
+    };
+    mark(HS_KERNEL_STEP, true);
     if (s->plan.any_spatial) {
+        mark(HS_KERNEL_INJECT, true);
         Launch::inject(c, st);
-        if (ev) hipEventRecord(ev[1], s->stream);
+        mark(HS_KERNEL_INJECT, false);
+        mark(HS_KERNEL_MOVE, true);
         Launch::move_count(c, st, s->plan.any_body ? 1 : 0);
-        if (ev) hipEventRecord(ev[2], s->stream);
+        mark(HS_KERNEL_MOVE, false);
+        mark(HS_KERNEL_SCAN, true);
         Launch::scan_cells(c, st, 1);
-        if (ev) hipEventRecord(ev[3], s->stream);
+        mark(HS_KERNEL_SCAN, false);
+        mark(HS_KERNEL_SCATTER, true);
         Launch::scatter(c, st);
-        if (ev) hipEventRecord(ev[4], s->stream);
-    } else if (ev) {
-        for (int k = 1; k <= 4; ++k) hipEventRecord(ev[k], s->stream);
+        mark(HS_KERNEL_SCATTER, false);
     }
+    mark(HS_KERNEL_GATHER, true);
+    Launch::gather(c, st);
+    mark(HS_KERNEL_GATHER, false);
+    mark(HS_KERNEL_SCALARS, true);
+    Launch::scalars(c, st);
+    mark(HS_KERNEL_SCALARS, false);
+    mark(HS_KERNEL_COLLIDE, true);
     Launch::collide(c, st);
-    if (ev) hipEventRecord(ev[5], s->stream);
+    mark(HS_KERNEL_COLLIDE, false);
+    mark(HS_KERNEL_DENSE, true);
+    Launch::dense(c, st);
+    mark(HS_KERNEL_DENSE, false);
     Launch::finish_step(c, st);
+    mark(HS_KERNEL_STEP, false);
 }
 
 }  // namespace
@@ -776,10 +797,10 @@ hs_status hs_counters(hs_sim *s, int c, int64_t *out)
     return HS_OK;
 }
 
-hs_status hs_set_timing(hs_sim *s, int enable)
+hs_status hs_set_timing(hs_sim *s, uint32_t mask)
 {
-    if (!s) return HS_ERR_ARG;
-    s->timing = enable != 0;
+    if (!s || (mask >> HS_NUM_KERNELS) != 0) return HS_ERR_ARG;
+    s->timing = mask;
     return HS_OK;
 }
 
@@ -787,34 +808,35 @@ hs_status hs_kernel_timing(hs_sim *s, int which, double *avg_ms, int64_t *launch
 {
     if (!s || which < 0 || which >= HS_NUM_KERNELS || !avg_ms) return HS_ERR_ARG;
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    const size_t nst = s->events.size() / 6;
     double tot = 0.0;
-    for (size_t k = 0; k < nst; ++k) {
-        hipEvent_t *ev = &s->events[6 * k];
+    int64_t n = 0;
+    for (const auto &ev : s->events) {
+        if (!ev.b[which] || !ev.e[which]) continue;
         float ms = 0.f;
-        hipEvent_t a, b;
-        switch (which) {
-            case HS_KERNEL_INJECT: a = ev[0]; b = ev[1]; break;
-            case HS_KERNEL_MOVE: a = ev[1]; b = ev[2]; break;
-            case HS_KERNEL_SCAN: a = ev[2]; b = ev[3]; break;
-            case HS_KERNEL_SCATTER: a = ev[3]; b = ev[4]; break;
-            case HS_KERNEL_COLLIDE: a = ev[4]; b = ev[5]; break;
-            default: a = ev[0]; b = ev[5]; break;
-        }
-        HIPCHK(s, hipEventElapsedTime(&ms, a, b));
+        HIPCHK(s, hipEventElapsedTime(&ms, ev.b[which], ev.e[which]));
         tot += ms;
+        ++n;
     }
-    *avg_ms = nst ? tot / (double)nst : 0.0;
-    if (launches) *launches = (int64_t)nst;
+    *avg_ms = n ? tot / (double)n : 0.0;
+    if (launches) *launches = n;
     return HS_OK;
+}
+
+static void destroy_events(hs_sim *s)
+{
+    for (auto &ev : s->events)
+        for (int k = 0; k < HS_NUM_KERNELS; ++k) {
+            if (ev.b[k]) (void)hipEventDestroy(ev.b[k]);
+            if (ev.e[k]) (void)hipEventDestroy(ev.e[k]);
+        }
+    s->events.clear();
 }
 
 hs_status hs_clear_timing(hs_sim *s)
 {
     if (!s) return HS_ERR_ARG;
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    for (auto e : s->events) hipEventDestroy(e);
-    s->events.clear();
+    destroy_events(s);
     s->timed_steps = 0;
     return HS_OK;
 }
@@ -828,8 +850,8 @@ const char *hs_error_string(const hs_sim *s)
 void hs_destroy(hs_sim *s)
 {
     if (!s) return;
-    hipStreamSynchronize(s->stream);
-    for (auto e : s->events) hipEventDestroy(e);
+    (void)hipStreamSynchronize(s->stream);
+    destroy_events(s);
     if (s->gexec) hipGraphExecDestroy(s->gexec);
     if (s->graph) hipGraphDestroy(s->graph);
     delete s;

@@ -18,7 +18,8 @@ FP64, FP32_MIXED = 0, 1
 BC = {"outflow": 0, "specular": 1, "inflow": 2}
 BODY = {"none": 0, "cylinder": 1, "sphere": 2}
 FLAG_TRACE, FLAG_NO_PARTICLES, FLAG_GRAPH = 1, 2, 4
-KERNELS = {"inject": 0, "move": 1, "scan": 2, "scatter": 3, "collide": 4, "step": 5}
+KERNELS = {"inject": 0, "move": 1, "scan": 2, "scatter": 3, "gather": 4, "scalars": 5, "collide": 6,
+           "dense": 7, "step": 8}
 COUNTERS = ("injected", "removed", "wall_hits", "candidates", "accepted", "relaxed",
             "ar_attempts", "ar_cap", "bounce_cap", "inject_cap", "skipped_cells")
 STATUS = {0: "ok", 1: "argument", 2: "capacity", 3: "numeric", 4: "device", 5: "state"}
@@ -87,7 +88,7 @@ def lib():
             "hs_counters": ([V, C.c_int, P(C.c_int64)], C.c_int),
             "hs_num_cells": ([V, C.c_int], C.c_int64),
             "hs_num_particles": ([V, C.c_int], C.c_int64),
-            "hs_set_timing": ([V, C.c_int], C.c_int),
+            "hs_set_timing": ([V, C.c_uint32], C.c_int),
             "hs_kernel_timing": ([V, C.c_int, P(C.c_double), P(C.c_int64)], C.c_int),
             "hs_clear_timing": ([V], C.c_int),
             "hs_error_string": ([V], C.c_char_p),
@@ -300,8 +301,18 @@ class Sim:
         self._check(self.L.hs_import_state(self.h, c, buf, len(raw)), "hs_import_state")
 
     # -- timing -------------------------------------------------------------------------
-    def set_timing(self, on: bool):
-        self._check(self.L.hs_set_timing(self.h, int(on)), "hs_set_timing")
+    def set_timing(self, groups=True):
+        """Time kernel groups with HIP events: True = all, False/None = off, or an iterable
+        of names from KERNELS."""
+        if groups is True:
+            mask = (1 << len(KERNELS)) - 1
+        elif not groups:
+            mask = 0
+        else:
+            mask = 0
+            for g in groups:
+                mask |= 1 << KERNELS[g]
+        self._check(self.L.hs_set_timing(self.h, mask), "hs_set_timing")
 
     def kernel_timing(self, which="collide"):
         ms, n = C.c_double(), C.c_int64()

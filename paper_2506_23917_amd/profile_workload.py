@@ -1,0 +1,58 @@
+"""Fixed workloads for hardware-counter runs (rocprofv3 --pmc), which need a short program.
+
+    python -m paper_2506_23917_amd.profile_workload --warmup 2000 --steps 20
+        the bench workload (2-D Ma 10 cylinder, 800 x 600, FP32-mixed): `warmup` steps to
+        develop the flow, then `steps` more with sampling on (filter the counters to the
+        last launches of the kernel of interest)
+    python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
+        a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
+        counters to bytes
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--copy-mib", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copied %d MiB x 3" % args.copy_mib, flush=True)
+        return
+    import workloads as W
+    from paper_2506_23917_amd.hs import Sim
+    case = W.cylinder_2d()
+    case["n_steady"] = args.warmup
+    sim = Sim(W.gas(), case, precision=args.precision, device="cuda:0")
+    done = 0
+    while done < args.warmup:
+        k = min(500, args.warmup - done)
+        sim.step(k)
+        sim.sync()
+        done += k
+        print("warmup %d / %d" % (done, args.warmup), flush=True)
+    sim.step(args.steps)
+    sim.sync()
+    print("timed steps %d, particles %d" % (args.steps, sim.num_particles(0)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
