@@ -1819,17 +1819,21 @@ __device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
     }
 }
 
-// Cells denser than the tile kernel takes: one 256-thread block per cell; the sequential
-// stages run on thread 0, the Shakhov draws on all threads.
+// Cells denser than the tile kernel takes: one 256-thread block per cell.  The stages are
+// those of k_cell_scalars and k_collide_tile with block-wide sums (every thread ends with the
+// same bits and derives the cell's scalars itself) and NTC rounds over the block.
 template <typename P, int CAPB>
 __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
 {
-    __shared__ int32_t s_src[CAPB];
+    constexpr int KC = 2 * kBlock;             // NTC candidates per chunk (two per thread)
+    static_assert(KC <= 1024, "candidate number fits the claim word");
+    __shared__ int32_t s_src[CAPB];            // sources during the gather, then claim words
     __shared__ P s_v[3][CAPB];
+    __shared__ double s_red[(kBlock / 64) * 12];
+    __shared__ unsigned long long s_obs, s_hash;
+    __shared__ int s_nacc, s_left;
     __shared__ int32_t s_rel[3];
-    __shared__ double s_U[3], s_pr, s_T, s_obs;
-    __shared__ int s_act;
-    __shared__ P s_par[7];
+    uint32_t *s_claim = (uint32_t *)s_src;
     Globals *G = C.g;
     if (G->halt) return;
     const int tid = threadIdx.x;
@@ -1839,7 +1843,10 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
     const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
     const bool use_perm = C.perm != nullptr;
     const int nbig = G->n_big;
+    const GasDev &gas = C.gas;
+    const bool tracing = C.trace != nullptr;
     CellCounts cc{0, 0, 0, 0, 0, 0};
+    int my_case = -1;
     for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
         const int g = C.big_list[b];
         const int s0 = C.cstart[g];
@@ -1850,6 +1857,11 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             if (tid == 0) raise_error(G, kErrCellLimit);
             continue;
         }
+        if (tid == 0 && cid != my_case) {
+            if (my_case >= 0) flush_counts(C, my_case, cc);
+            my_case = cid;
+        }
+        // stable order (sort of the source indices), gather, sorted state
         int p2 = 1;
         while (p2 < n) p2 <<= 1;
         for (int k = tid; k < p2; k += kBlock) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
@@ -1865,50 +1877,329 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             s_v[1][k] = S.vel[1][src];
             s_v[2][k] = S.vel[2][src];
         }
-        if (tid < 3) s_rel[tid] = 0;
         __syncthreads();
-        const CellSlot<P> slot{s_U, &s_T, &s_pr, &s_obs, &s_act, s_par};
-        if (tid == 0) cell_stage_a<P>(C, cs, g, st, s_v[0], s_v[1], s_v[2], n, slot, cc);
+        for (int k = tid; k < n; k += kBlock) s_claim[k] = 0u;
+        if (tid == 0) {
+            s_obs = 0ull;
+            s_hash = 0ull;
+            s_nacc = 0;
+            s_rel[0] = s_rel[1] = s_rel[2] = 0;
+        }
+
+        // Eq. 31 moments
+        double s1[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = tid; k < n; k += kBlock) {
+            const double x = (double)s_v[0][k], y = (double)s_v[1][k], z = (double)s_v[2][k];
+            s1[0] = s1[0] + x;
+            s1[1] = s1[1] + y;
+            s1[2] = s1[2] + z;
+            s1[3] = s1[3] + (x * x + y * y + z * z);
+        }
+        team_sum<kBlock, 4>(s1, s_red);
+        double U[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U[a] = s1[a] / (double)n;
+        double s2[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (sizeof(P) == 4) {
+            float uf[3], ud[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                uf[a] = (float)U[a];
+                ud[a] = (float)(U[a] - (double)uf[a]);
+            }
+            for (int k = tid; k < n; k += kBlock) {
+                const float cx = (s_v[0][k] - uf[0]) - ud[0];
+                const float cy = (s_v[1][k] - uf[1]) - ud[1];
+                const float cz = (s_v[2][k] - uf[2]) - ud[2];
+                const float c2 = cx * cx + cy * cy + cz * cz;
+                s2[0] = s2[0] + (double)c2;
+                s2[1] = s2[1] + (double)(c2 * cx);
+                s2[2] = s2[2] + (double)(c2 * cy);
+                s2[3] = s2[3] + (double)(c2 * cz);
+            }
+        } else {
+            for (int k = tid; k < n; k += kBlock) {
+                const double cx = s_v[0][k] - U[0], cy = s_v[1][k] - U[1], cz = s_v[2][k] - U[2];
+                const double c2 = cx * cx + cy * cy + cz * cz;
+                s2[0] = s2[0] + c2;
+                s2[1] = s2[1] + c2 * cx;
+                s2[2] = s2[2] + c2 * cy;
+                s2[3] = s2[3] + c2 * cz;
+            }
+        }
+        team_sum<kBlock, 4>(s2, s_red);
+
+        // Eq. 10 / 25-28 split, N_col, Shakhov parameters (every thread alike)
+        TraceDev *tr = (tid == 0 && tracing) ? &C.trace[g] : nullptr;
+        const double vol = C.vol[g];
+        double T;
+        if constexpr (sizeof(P) == 4)
+            T = gas.m * (s1[3] - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)n) /
+                (3.0 * kKB * (double)(n - 1));
+        else
+            T = gas.m * s2[0] / (3.0 * kKB * (double)(n - 1));
+        double Q[3] = {0.0, 0.0, 0.0};
+        if (vol > 0.0) {
+            const double nd = (double)n * cs.F_N / vol;
+            const double f = nd * (double)n / ((double)(n - 1) * (double)(n - 2));
+            for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * s2[1 + a];
+        }
+        if (tid == 0 && (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2]))) raise_error(G, kErrNumeric);
+        const bool active = T > 0.0 && vol > 0.0;
+        if (tr) {
+            *tr = TraceDev{};
+            tr->n = n;
+            for (int a = 0; a < 4; ++a) tr->pre_sum[a] = s1[a];
+        }
+        double pr = 0.0, scmax = 0.0;
+        long long ncol = 0;
+        P par[7] = {(P)0, (P)0, (P)0, (P)0, (P)0, (P)0, (P)0};
+        if (!active) {
+            if (tid == 0) cc.skipped++;
+        } else {
+            const double nd = (double)n * cs.F_N / vol;
+            const double p = nd * kKB * T;
+            const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
+            const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+            double dtc;
+            if (cs.dim == 0) {
+                dtc = dtG;
+            } else {
+                const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+                dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+            }
+            double dtD, dtS;
+            if (dtc <= tau) {
+                dtD = dtG;
+                dtS = 0.0;
+            } else {
+                dtD = (tau / dtc) * dtG;
+                dtS = dtG - dtD;
+            }
+            pr = -expm1(-dtS / tau);
+            double a_max = 1.0;
+            if (pr > 0.0) {
+                const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+                a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
+                par[0] = (P)Q[0];
+                par[1] = (P)Q[1];
+                par[2] = (P)Q[2];
+                par[3] = (P)p;
+                par[4] = (P)(gas.R * T);
+                par[5] = (P)sqrt(2.0 * gas.R * T);
+                par[6] = (P)a_max;
+            }
+            scmax = C.sigc[g];
+            const double M = 0.5 * (double)n * (double)(n - 1) * cs.F_N * scmax * dtD / vol;
+            const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)(g - cs.cell0), st, 0).x);
+            if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
+            else if (tid == 0) raise_error(G, kErrNumeric);
+            if (tr) {
+                tr->T = T;
+                tr->tau = tau;
+                tr->dt_dsmc = dtD;
+                tr->p_relax = pr;
+                tr->a_max = pr > 0.0 ? a_max : 0.0;
+            }
+        }
         __syncthreads();
-        const double pr = s_pr;
+
+        // NTC (Eq. 5-9) in rounds over the block, as in k_collide_tile
+        const uint32_t lc = (uint32_t)(g - cs.cell0);
+        const P scm = (P)scmax;
+        uint32_t round = 0;
+        for (long long kbase = 0; kbase < ncol; kbase += KC) {
+            const int kn = (int)min((long long)KC, ncol - kbase);
+            int ci[2], cj[2];
+            long long ck[2];
+            P cu[2], om[2][3];
+            bool pend[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int q = tid + kBlock * r;
+                pend[r] = q < kn;
+                ci[r] = cj[r] = 0;
+                ck[r] = 0;
+                cu[r] = om[r][0] = om[r][1] = om[r][2] = (P)0;
+                if (pend[r]) {
+                    const long long kc = kbase + q;
+                    const W4 w = draw(cs, kStreamCell, lc, st, (uint32_t)(1 + 2 * kc));
+                    const uint32_t i = unidx(w.x, (uint32_t)n);
+                    uint32_t j = unidx(w.y, (uint32_t)(n - 1));
+                    if (j >= i) ++j;
+                    ci[r] = (int)i;
+                    cj[r] = (int)j;
+                    ck[r] = kc;
+                    cu[r] = Real<P>::uni(w.z);
+                    const W4 w2 = draw(cs, kStreamCell, lc, st, (uint32_t)(2 + 2 * kc));
+                    const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
+                    const P schi = Real<P>::sq((P)1 - cchi * cchi);
+                    P sth, cth;
+                    Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
+                    om[r][0] = cchi;
+                    om[r][1] = schi * cth;
+                    om[r][2] = schi * sth;
+                }
+            }
+            __syncthreads();                   // every thread has left the previous chunk's rounds
+            if (tid == 0) s_left = kn;
+            __syncthreads();
+            for (;;) {
+                if (round == 0x3fffffu) {      // round counter exhausted: clear the claims
+                    for (int k = tid; k < n; k += kBlock) s_claim[k] = 0u;
+                    round = 0;
+                    __syncthreads();
+                }
+                ++round;
+                uint32_t tag[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    tag[r] = (round << 10) | (uint32_t)(1023 - (tid + kBlock * r));
+                    if (pend[r]) {
+                        atomicMax(&s_claim[ci[r]], tag[r]);
+                        atomicMax(&s_claim[cj[r]], tag[r]);
+                    }
+                }
+                __syncthreads();
+                int done = 0;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    if (!pend[r]) continue;
+                    const int i = ci[r], j = cj[r];
+                    if (s_claim[i] != tag[r] || s_claim[j] != tag[r]) continue;
+                    pend[r] = false;
+                    ++done;
+                    P *vx = s_v[0], *vy = s_v[1], *vz = s_v[2];
+                    const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
+                    const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
+                    P sc;
+                    if constexpr (sizeof(P) == 4)
+                        sc = cr > (P)0 ? (P)gas.K_vhs * __builtin_amdgcn_exp2f((P)gas.vhs_exp * __builtin_amdgcn_logf(cr))
+                                       : (P)0;
+                    else
+                        sc = gas.K_vhs * pow(cr, gas.vhs_exp);
+                    atomicMax(&s_obs, (unsigned long long)__double_as_longlong((double)sc));
+                    if (cu[r] < sc / scm) {
+                        const P sx = vx[i] + vx[j], sy = vy[i] + vy[j], sz = vz[i] + vz[j];
+                        vx[i] = (P)0.5 * (sx - cr * om[r][0]);
+                        vx[j] = (P)0.5 * (sx + cr * om[r][0]);
+                        vy[i] = (P)0.5 * (sy - cr * om[r][1]);
+                        vy[j] = (P)0.5 * (sy + cr * om[r][1]);
+                        vz[i] = (P)0.5 * (sz - cr * om[r][2]);
+                        vz[j] = (P)0.5 * (sz + cr * om[r][2]);
+                        atomicAdd(&s_nacc, 1);
+                        atomicXor(&s_hash, (unsigned long long)(ck[r] + 1) * 0x9E3779B97F4A7C15ull);
+                    }
+                }
+                if (done) atomicSub(&s_left, done);
+                __syncthreads();
+                if (s_left == 0) break;
+            }
+        }
+        if (tid == 0 && active) {
+            const double obs = __longlong_as_double((long long)s_obs);
+            if (obs > scmax) C.sigc[g] = obs;
+            cc.cand += ncol;
+            cc.acc += s_nacc;
+            if (tr) {
+                tr->ncol = ncol;
+                tr->nacc = s_nacc;
+                tr->acc_hash = s_hash;
+            }
+        }
+
+        // SP-Shakhov relaxation (Eq. 16-18)
         if (pr > 0.0) {
             int nrel = 0, nar = 0, ncap = 0;
             for (int k = tid; k < n; k += kBlock) {
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
                 P Cv[3];
-                int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, s_par, (P)(1.0 - C.gas.Pr), Cv);
+                int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, par, (P)(1.0 - gas.Pr), Cv);
                 if (used < 0) {
                     ++ncap;
                     used = -used;
                 }
                 ++nrel;
                 nar += used;
-                s_v[0][k] = (P)(s_U[0] + (double)Cv[0]);
-                s_v[1][k] = (P)(s_U[1] + (double)Cv[1]);
-                s_v[2][k] = (P)(s_U[2] + (double)Cv[2]);
+                s_v[0][k] = (P)(U[0] + (double)Cv[0]);
+                s_v[1][k] = (P)(U[1] + (double)Cv[1]);
+                s_v[2][k] = (P)(U[2] + (double)Cv[2]);
             }
             if (nrel) atomicAdd(&s_rel[0], nrel);
             if (nar) atomicAdd(&s_rel[1], nar);
             if (ncap) atomicAdd(&s_rel[2], ncap);
         }
         __syncthreads();
+
+        // Eq. 19 rescale (each thread rescales the particles it summed), Step (5) sums
+        double r1[3] = {0.0, 0.0, 0.0};
+        for (int k = tid; k < n; k += kBlock) {
+            r1[0] = r1[0] + (double)s_v[0][k];
+            r1[1] = r1[1] + (double)s_v[1][k];
+            r1[2] = r1[2] + (double)s_v[2][k];
+        }
+        team_sum<kBlock, 3>(r1, s_red);
+        const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
+        double r2[1] = {0.0};
+        for (int k = tid; k < n; k += kBlock) {
+            const double cx = (double)s_v[0][k] - Up[0], cy = (double)s_v[1][k] - Up[1], cz = (double)s_v[2][k] - Up[2];
+            r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
+        }
+        team_sum<kBlock, 1>(r2, s_red);
+        double f = 0.0;
+        if (active) {
+            const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(n - 1));
+            f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+        }
+        const bool sampling = step >= cs.n_steady;
+        const bool sums = sampling || tracing;
+        double sm[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) sm[j] = 0.0;
+        for (int k = tid; k < n; k += kBlock) {
+            double a = (double)s_v[0][k], bb = (double)s_v[1][k], c = (double)s_v[2][k];
+            if (f > 0.0) {
+                a = U[0] + (a - Up[0]) * f;
+                bb = U[1] + (bb - Up[1]) * f;
+                c = U[2] + (c - Up[2]) * f;
+            }
+            const size_t dst = (size_t)s0 + k;
+            Dd.vel[0][dst] = (P)a;
+            Dd.vel[1][dst] = (P)bb;
+            Dd.vel[2][dst] = (P)c;
+            if (sums) {
+                const double c2 = a * a + bb * bb + c * c;
+                sm[0] += a; sm[1] += bb; sm[2] += c;
+                sm[3] += a * a; sm[4] += bb * bb; sm[5] += c * c;
+                sm[6] += a * bb; sm[7] += a * c; sm[8] += bb * c;
+                sm[9] += c2 * a; sm[10] += c2 * bb; sm[11] += c2 * c;
+            }
+        }
+        if (sums) team_sum<kBlock, 12>(sm, s_red);
         if (tid == 0) {
             cc.relax += s_rel[0];
             cc.ar += s_rel[1];
             cc.arcap += s_rel[2];
-            cell_stage_c<P>(C, g, step >= cs.n_steady, s_v[0], s_v[1], s_v[2], n, slot, s_rel);
-            flush_counts(C, cid, cc);
-        }
-        __syncthreads();
-        for (int k = tid; k < n; k += kBlock) {
-            const size_t dst = (size_t)s0 + k;
-            Dd.vel[0][dst] = s_v[0][k];
-            Dd.vel[1][dst] = s_v[1][k];
-            Dd.vel[2][dst] = s_v[2][k];
+            if (sampling) {
+                double *A = &C.acc[13 * (size_t)g];
+                A[0] += (double)n;
+#pragma unroll
+                for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
+            }
+            if (tr) {
+                tr->post_sum[0] = sm[0];
+                tr->post_sum[1] = sm[1];
+                tr->post_sum[2] = sm[2];
+                tr->post_sum[3] = sm[3] + sm[4] + sm[5];
+                tr->nrelax = s_rel[0];
+                tr->ar_attempts = s_rel[1];
+                tr->ar_cap = s_rel[2];
+            }
         }
         __syncthreads();
     }
+    if (tid == 0 && my_case >= 0) flush_counts(C, my_case, cc);
 }
 
 // Dense-cell list of a batch whose cells never re-sort (only 0-D cases): built once.
