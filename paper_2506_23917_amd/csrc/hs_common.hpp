@@ -120,7 +120,7 @@ struct Ctx {
     TraceDev *trace;              // nullptr unless tracing
     Globals *g;
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
-    int32_t cap_block, precision, tile_w, pad;
+    int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension
     int64_t capacity;             // total particle capacity of the batch
 };
 

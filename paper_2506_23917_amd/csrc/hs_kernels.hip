@@ -13,6 +13,8 @@
 //   finish_step    live count, step counter, sample counters
 #include "hs_device.hpp"
 
+#include <type_traits>
+
 namespace hsk {
 
 // ------------------------------------------------------------------------------------
@@ -548,15 +550,19 @@ __global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
         int nc = -1, cid = 0;
         bool to_body = false;
         if (valid) {
+            // state loads first (guarded by the batch's largest dimension, not the case's),
+            // so they overlap the case lookup
             const int g = S.cell[i];
+            P xr[3] = {(P)0, (P)0, (P)0}, v[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
             cid = case_of(C, g);
             const CaseDev &cs = C.cases[cid];
             if (cs.dim == 0) {
                 nc = g;
             } else {
-                P xr[3], v[3];
-                for (int a = 0; a < 3; ++a) if (a < cs.dim) xr[a] = S.pos[a][i];
-                for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
                 const bool full = i < n_live;
                 double t = cs.dt_G;
                 if (!full) t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
@@ -1389,7 +1395,7 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
 // groups as in k_cell_scalars; after the NTC every lane reads and writes only its own
 // particles.
 template <typename P, int TW, int D>
-__global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
+__device__ __forceinline__ void collide_tile_body(const Ctx &C)
 {
     constexpr int MAXC = TW / 4;
     constexpr int MAXP = TW + D;
@@ -1401,7 +1407,10 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
     __shared__ P s_v[3][MAXP];
     __shared__ int32_t c_start[MAXC], c_off[MAXC + 1], c_kb[MAXC + 1];
     __shared__ P c_scm[MAXC];
-    __shared__ unsigned long long c_obs[MAXC], c_hash[MAXC];
+    // largest sigma c seen (bits of a non-negative P: integer order = value order) and the
+    // XOR hash of the accepted candidates (its low 32 bits in FP32-mixed)
+    using UWord = std::conditional_t<sizeof(P) == 8, unsigned long long, unsigned int>;
+    __shared__ UWord c_obs[MAXC], c_hash[MAXC];
     __shared__ int32_t c_nacc[MAXC];
     __shared__ uint8_t c_case[MAXC], c_samp[MAXC];
     __shared__ uint32_t c_seed[MAXC][2], c_lcid[MAXC];
@@ -1556,8 +1565,8 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
         if (sub == 0 && own) {
             c_kb[gc] = kincl - nc_l;
             c_scm[gc] = (P)scmax;
-            c_obs[gc] = 0ull;
-            c_hash[gc] = 0ull;
+            c_obs[gc] = 0;
+            c_hash[gc] = 0;
             c_nacc[gc] = 0;
         }
         if (lane == 0) c_kb[ncl] = kall;
@@ -1645,7 +1654,10 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
                         sc = cr > (P)0 ? K_vhs * __builtin_amdgcn_exp2f(ex_vhs * __builtin_amdgcn_logf(cr)) : (P)0;
                     else
                         sc = gas.K_vhs * pow(cr, gas.vhs_exp);
-                    atomicMax(&c_obs[lc], (unsigned long long)__double_as_longlong((double)sc));
+                    if constexpr (sizeof(P) == 8)
+                        atomicMax(&c_obs[lc], (unsigned long long)__double_as_longlong(sc));
+                    else
+                        atomicMax(&c_obs[lc], __float_as_uint(sc));
                     if (cu[r] < sc / c_scm[lc]) {
                         const P sx = vx[i] + vx[j], sy = vy[i] + vy[j], sz = vz[i] + vz[j];
                         vx[i] = (P)0.5 * (sx - cr * om[r][0]);
@@ -1655,7 +1667,7 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
                         vz[i] = (P)0.5 * (sz - cr * om[r][2]);
                         vz[j] = (P)0.5 * (sz + cr * om[r][2]);
                         atomicAdd(&c_nacc[lc], 1);
-                        atomicXor(&c_hash[lc], (unsigned long long)(ck[r] + 1) * 0x9E3779B97F4A7C15ull);
+                        atomicXor(&c_hash[lc], (UWord)((unsigned long long)(ck[r] + 1) * 0x9E3779B97F4A7C15ull));
                     }
                 }
                 team_sync<64>();
@@ -1663,14 +1675,16 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
         }
         team_sync<64>();
         if (lead && active) {
-            const double obs = __longlong_as_double((long long)c_obs[gc]);
+            double obs;
+            if constexpr (sizeof(P) == 8) obs = __longlong_as_double((long long)c_obs[gc]);
+            else obs = (double)__uint_as_float(c_obs[gc]);
             if (obs > scmax) C.sigc[g] = obs;
             cc.cand += ncol;
             cc.acc += c_nacc[gc];
             if (tr) {
                 tr->ncol = ncol;
                 tr->nacc = c_nacc[gc];
-                tr->acc_hash = c_hash[gc];
+                tr->acc_hash = (unsigned long long)c_hash[gc];
             }
         }
 
@@ -1796,6 +1810,19 @@ __global__ __launch_bounds__(64) void k_collide_tile(Ctx C)
         team_sync<64>();
     }
     wave_flush_counts(C, my_case, cc);
+}
+
+constexpr int kCapWave = 192;       // densest cell of the tile kernel
+constexpr int kTileW = 256;         // tile weight: particles + 4 per cell
+
+// FP32-mixed: registers capped for four waves per SIMD (the LDS tile allows four).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_collide_tile_f32(Ctx C)
+{
+    collide_tile_body<float, kTileW, kCapWave>(C);
+}
+__global__ __launch_bounds__(64) void k_collide_tile_f64(Ctx C)
+{
+    collide_tile_body<double, kTileW, kCapWave>(C);
 }
 
 // Sort `a[0..p2)` ascending in LDS with a bitonic network (p2 a power of two).
@@ -2336,8 +2363,6 @@ __global__ void k_philox(uint64_t seed, uint32_t stream, uint64_t e0, uint32_t s
 // launchers
 // ------------------------------------------------------------------------------------
 
-constexpr int kCapWave = 192;       // densest cell of the tile kernel
-constexpr int kTileW = 256;         // tile weight: particles + 4 per cell
 constexpr int kCapBlock64 = 2048;   // powers of two: the bitonic sort pads to one
 constexpr int kCapBlock32 = 2048;
 
@@ -2388,7 +2413,7 @@ void Launch::inject(const Ctx &c, void *s)
 }
 void Launch::move_count(const Ctx &c, void *s, int any_body)
 {
-    const int grid = std::min(stream_grid(), blocks_for(c.capacity, kBlock));
+    const int grid = std::min(4 * stream_grid(), blocks_for(c.capacity, kBlock));
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
         if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
@@ -2424,9 +2449,8 @@ void Launch::scalars(const Ctx &c, void *s)
 }
 void Launch::collide(const Ctx &c, void *s)
 {
-    const int g = tile_grid(c, 256ll * 8);
-    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_collide_tile<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
-    else hipLaunchKernelGGL((k_collide_tile<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
+    if (c.precision == HS_FP64) hipLaunchKernelGGL(k_collide_tile_f64, dim3(tile_grid(c, 256ll * 4)), dim3(64), 0, S_(s), c);
+    else hipLaunchKernelGGL(k_collide_tile_f32, dim3(tile_grid(c, 256ll * 16)), dim3(64), 0, S_(s), c);
 }
 void Launch::dense(const Ctx &c, void *s)
 {

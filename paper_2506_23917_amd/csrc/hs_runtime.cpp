@@ -458,6 +458,7 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.cellrec = (double *)(w + L.cellrec);
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
     c.tile_w = tile_width();
+    c.dim_max = s->plan.dim_max;
     c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
     c.g = (Globals *)(w + L.globals);
     c.n_cases = n_cases;
