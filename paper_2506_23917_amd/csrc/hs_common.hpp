@@ -76,6 +76,7 @@ struct Globals {
     int32_t n_work;          // particles routed to the body-reflection kernel
     int32_t n_tiles;         // tiles of the collide kernel this step
     int32_t pad;
+    int32_t case_tile0[kMaxCases + 1];   // first tile of each case (tiles never span cases)
     int64_t next_id[kMaxCases];
     int64_t inj_id_base[kMaxCases];
     int64_t n_samples[kMaxCases];

@@ -347,23 +347,53 @@ __global__ void k_scan_parts(Ctx C, int nparts)
     if (threadIdx.x == 0) C.scan_part[nparts] = carry;
 }
 
-// Collide tiles: tile t covers the cells c with t TW <= w(c) < (t+1) TW, w(c) = cstart[c] + 4 c
-// (strictly increasing).  Cell g with weight w0 and successor weight w1 writes g + 1 as the
-// first cell of every tile t with w0 < t TW <= w1; tile 0 starts at cell 0, and the entry
-// after the last tile is ncells.
-__device__ __forceinline__ void tile_marks(const Ctx &C, int g, long long w0, long long w1)
+// Collide tiles never span two cases, so a case is tiled exactly as it would be alone (its
+// cell sums then run in the same order in any batch).  Tile t of case k covers the cells c
+// of the case whose local weight w(c) = (cstart[c] - cstart[cell0]) + 4 (c - cell0), which
+// strictly increases, lies in [t TW, (t+1) TW); tile_cell[] holds the first cell of every
+// tile of the batch and, after the last, ncells.
+__global__ void k_case_tiles(Ctx C)
 {
+    if (C.g->halt) return;
+    __shared__ int lds[16];
+    Globals *G = C.g;
     const long long tw = C.tile_w;
-    for (long long t = w0 / tw + 1; t <= w1 / tw; ++t) C.tile_cell[t] = g + 1;
-    if (g == 0) C.tile_cell[0] = 0;
-    if (g == C.ncells_total - 1 && w1 % tw != 0) C.tile_cell[w1 / tw + 1] = g + 1;
+    int carry = 0;
+    for (int base = 0; base < C.n_cases; base += blockDim.x) {
+        const int k = base + threadIdx.x;
+        int v = 0;
+        if (k < C.n_cases) {
+            const CaseDev &cs = C.cases[k];
+            const long long W = (long long)(C.cstart[cs.cell0 + cs.ncells] - C.cstart[cs.cell0]) + 4ll * cs.ncells;
+            v = (int)((W + tw - 1) / tw);
+        }
+        int total;
+        const int ex = block_excl_scan(v, lds, total);
+        __syncthreads();
+        if (k < C.n_cases) G->case_tile0[k] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        G->case_tile0[C.n_cases] = carry;
+        G->n_tiles = carry;
+        C.tile_cell[carry] = C.ncells_total;
+    }
 }
 
 __global__ void k_tile_table(Ctx C)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= C.ncells_total) return;
-    tile_marks(C, g, (long long)C.cstart[g] + 4ll * g, (long long)C.cstart[g + 1] + 4ll * (g + 1));
+    if (g >= C.ncells_total || C.g->halt) return;
+    const int k = case_of(C, g);
+    const CaseDev &cs = C.cases[k];
+    const long long tw = C.tile_w;
+    const long long c0 = C.cstart[cs.cell0];
+    const long long w0 = (C.cstart[g] - c0) + 4ll * (g - cs.cell0);
+    const long long w1 = (C.cstart[g + 1] - c0) + 4ll * (g + 1 - cs.cell0);
+    int32_t *tc = C.tile_cell + C.g->case_tile0[k];
+    for (long long t = w0 / tw + 1; t <= w1 / tw; ++t) tc[t] = g + 1;
+    if (g == cs.cell0) tc[0] = g;
+    if (g == cs.cell0 + cs.ncells - 1 && w1 % tw != 0) tc[w1 / tw + 1] = g + 1;
 }
 
 __global__ void k_scan_final(Ctx C, int build_big, int nparts)
@@ -391,7 +421,6 @@ __global__ void k_scan_final(Ctx C, int build_big, int nparts)
                 const int slot = atomicAdd(&C.g->n_big, 1);
                 C.big_list[slot] = g;
             }
-            tile_marks(C, g, (long long)run + 4ll * g, (long long)(run + v[k]) + 4ll * (g + 1));
         }
         run += v[k];
     }
@@ -399,7 +428,6 @@ __global__ void k_scan_final(Ctx C, int build_big, int nparts)
         const int all = C.scan_part[nparts];
         C.cstart[C.ncells_total] = all;
         C.g->n_new = all;
-        C.g->n_tiles = (int)(((long long)all + 4ll * C.ncells_total + C.tile_w - 1) / C.tile_w);
     }
 }
 
@@ -2391,6 +2419,7 @@ void Launch::init_finish(const Ctx &c, void *s)
 }
 void Launch::tile_table(const Ctx &c, void *s)
 {
+    hipLaunchKernelGGL(k_case_tiles, dim3(1), dim3(kBlock), 0, S_(s), c);
     hipLaunchKernelGGL(k_tile_table, dim3((c.ncells_total + kBlock - 1) / kBlock), dim3(kBlock), 0, S_(s), c);
 }
 
@@ -2400,6 +2429,7 @@ void Launch::scan_cells(const Ctx &c, void *s, int build_big)
     hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, S_(s), c);
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, S_(s), c, nparts);
     hipLaunchKernelGGL(k_scan_final, dim3(nparts), dim3(kBlock), 0, S_(s), c, build_big, nparts);
+    tile_table(c, s);
 }
 void Launch::inject(const Ctx &c, void *s)
 {

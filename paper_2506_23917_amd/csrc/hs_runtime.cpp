@@ -261,7 +261,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.facestart = take(4 * (P.faces.size() + 1));
     L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
     L.big = take(4 * nc);
-    L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + 3));
+    L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.cellrec = take(8 * 16 * nc);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
     size_t maxcase = 1;

@@ -192,7 +192,10 @@ class Sim:
         self.ws_bytes = nb.value
         with torch.cuda.device(self.device):
             self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream(self.device)
+            # a stream of its own (default priority): graph capture is not allowed on the
+            # legacy default stream
+            self.stream = torch.cuda.Stream(device=self.device)
+            torch.cuda.current_stream(self.device).synchronize()
         h = C.c_void_p()
         rc = self.L.hs_init_particles(C.byref(self._gas), self._cs.arr, self._cs.n, self.prec, self.flags,
                                       C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
