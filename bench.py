@@ -74,6 +74,9 @@ def run_gpu(prec, case, gas, warmup, steps):
     sim = Sim(gas, case, precision=prec, device="cuda:0")
     sim.step(warmup)
     sim.sync()
+    # launch shapes (blocks per grid of each kernel group) picked by the autotuner on the
+    # developed flow; its trial steps are further warmup steps
+    tune = sim.autotune(steps_per_trial=10)
     n0 = sim.num_particles(0)
     sim.set_timing(["collide"])
     torch.cuda.synchronize()
@@ -86,7 +89,7 @@ def run_gpu(prec, case, gas, warmup, steps):
     tile_ms, launches = sim.kernel_timing("collide")
     sim.set_timing(False)
     sim.clear_timing()
-    return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches)
+    return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches, tune=tune)
 
 
 def cpu_baseline(sim, case, gas, nsteps):
@@ -155,7 +158,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2-D Ma10 argon cylinder, Kn 0.01 on D, 800x600 cut-cell grid, ~30 particles "
                                "per cell, FP32-mixed, developed flow with sampling on",
-                   "particles": int(npart), "cells": ncells},
+                   "particles": int(npart), "cells": ncells,
+                   "launch_grids": {k: v[0] for k, v in r32["tune"]["grids"].items()},
+                   "tuning_steps": r32["tune"]["steps"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_collide_tile<float> (NTC, Shakhov, rescale, sampling on LDS tiles)",

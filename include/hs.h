@@ -198,6 +198,26 @@ hs_status hs_set_timing(hs_sim *sim, uint32_t mask);
 hs_status hs_kernel_timing(hs_sim *sim, int which, double *avg_ms, int64_t *launches);
 hs_status hs_clear_timing(hs_sim *sim);
 
+/* Launch-shape autotuner.  For each tunable kernel group (collide, gather, scalars, dense,
+ * move, scatter) it runs `steps_per_trial` steps with each candidate grid size (blocks per
+ * launch), timed with HIP events, and keeps the fastest; `report` (may be NULL) receives
+ * the chosen grids, their average durations (ms) and the number of steps taken.  Grid
+ * sizes do not change results -- every tile, cell and particle is processed the same way
+ * whichever block takes it -- so the tuning steps are ordinary steps of the run: the
+ * simulation advances by `report->steps`.  Synchronises; forgets timing records; a
+ * captured step graph is dropped and captured again with the new shapes.  Errors: as
+ * hs_step plus the device checks of hs_sync. */
+typedef struct {
+    int32_t grid[HS_NUM_KERNELS];   /* chosen blocks per launch (0: group not tuned)    */
+    double ms[HS_NUM_KERNELS];      /* average duration of the chosen shape, ms         */
+    int64_t steps;                  /* steps the tuning advanced the simulation         */
+} hs_tune_report;
+hs_status hs_autotune(hs_sim *sim, int steps_per_trial, hs_tune_report *report);
+
+/* Set the grid size (blocks per launch) of kernel group `which` by hand; 0 restores the
+ * built-in default.  Results do not depend on it.  Drops a captured step graph. */
+hs_status hs_set_grid(hs_sim *sim, int which, int32_t blocks);
+
 /* Human-readable description of the last error (never NULL). */
 const char *hs_error_string(const hs_sim *sim);
 

@@ -123,6 +123,8 @@ struct Ctx {
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
     int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension
     int64_t capacity;             // total particle capacity of the batch
+    // launch shapes (blocks per grid; 0 = the built-in default), chosen by the autotuner
+    int32_t grid[HS_NUM_KERNELS];
 };
 
 // Launchers (defined in hs_kernels.hip).

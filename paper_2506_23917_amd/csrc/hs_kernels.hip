@@ -1189,12 +1189,48 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     }
 }
 
-// Butterfly sum over each aligned group of 2^kb lanes.  Every lane of a group ends with
-// the same bits: at each level the two partners add the same two values.
+// Value held by the partner lane under a DPP lane pattern (every lane active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_partner_i(int x)
+{
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+}
+// DPP lane patterns: the other lane of a pair, the other pair of a quad (quad_perm), the other
+// quad of an 8-lane half row (half-row mirror), the other half of a 16-lane row (row mirror).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// Butterfly sum over each aligned group of 2^kb lanes (kb uniform in the wave).  Every lane
+// of a group ends with the same bits: at each level the two partners add the same two values
+// (partial sums of complementary halves).  Levels within a 16-lane row move data with DPP,
+// the two wider ones with cross-lane shuffles.
 template <int K>
 __device__ __forceinline__ void group_sum(double (&x)[K], int kb)
 {
-    for (int m = 1; m < (1 << kb); m <<= 1) {
+    if (kb >= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = x[k] + dpp_partner<kDppXor1>(x[k]);
+    }
+    if (kb >= 2) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = x[k] + dpp_partner<kDppXor2>(x[k]);
+    }
+    if (kb >= 3) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = x[k] + dpp_partner<kDppHalfMirror>(x[k]);
+    }
+    if (kb >= 4) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = x[k] + dpp_partner<kDppMirror>(x[k]);
+    }
+    for (int m = 16; m < (1 << kb); m <<= 1) {
 #pragma unroll
         for (int k = 0; k < K; ++k) x[k] = x[k] + __shfl_xor(x[k], m, 64);
     }
@@ -1202,7 +1238,11 @@ __device__ __forceinline__ void group_sum(double (&x)[K], int kb)
 
 __device__ __forceinline__ int group_sum_i(int x, int kb)
 {
-    for (int m = 1; m < (1 << kb); m <<= 1) x += __shfl_xor(x, m, 64);
+    if (kb >= 1) x += dpp_partner_i<kDppXor1>(x);
+    if (kb >= 2) x += dpp_partner_i<kDppXor2>(x);
+    if (kb >= 3) x += dpp_partner_i<kDppHalfMirror>(x);
+    if (kb >= 4) x += dpp_partner_i<kDppMirror>(x);
+    for (int m = 16; m < (1 << kb); m <<= 1) x += __shfl_xor(x, m, 64);
     return x;
 }
 
@@ -2443,7 +2483,8 @@ void Launch::inject(const Ctx &c, void *s)
 }
 void Launch::move_count(const Ctx &c, void *s, int any_body)
 {
-    const int grid = std::min(4 * stream_grid(), blocks_for(c.capacity, kBlock));
+    const int grid = c.grid[HS_KERNEL_MOVE] > 0 ? c.grid[HS_KERNEL_MOVE]
+                                                : std::min(4 * stream_grid(), blocks_for(c.capacity, kBlock));
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
         if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
@@ -2454,37 +2495,41 @@ void Launch::move_count(const Ctx &c, void *s, int any_body)
 }
 void Launch::scatter(const Ctx &c, void *s)
 {
-    const int grid = std::min(stream_grid(), blocks_for(c.capacity, kBlock));
+    const int grid = c.grid[HS_KERNEL_SCATTER] > 0 ? c.grid[HS_KERNEL_SCATTER]
+                                                   : std::min(stream_grid(), blocks_for(c.capacity, kBlock));
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, S_(s), c);
 }
 // Tile kernels loop over tiles with a fixed grid: wide for the streaming gather and scalar
 // kernels, about the resident capacity for the collision kernel (its per-wave setup and
 // counter flush are paid once per block).
-static int tile_grid(const Ctx &c, long long cap)
+static int tile_grid(const Ctx &c, int which, long long cap)
 {
+    if (c.grid[which] > 0) return c.grid[which];
     const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
     return (int)std::max(1ll, std::min(maxtiles, cap));
 }
 void Launch::gather(const Ctx &c, void *s)
 {
-    const int g = tile_grid(c, 256ll * 32);
+    const int g = tile_grid(c, HS_KERNEL_GATHER, 256ll * 32);
     if (c.precision == HS_FP64) hipLaunchKernelGGL((k_sort_gather<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
     else hipLaunchKernelGGL((k_sort_gather<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
 }
 void Launch::scalars(const Ctx &c, void *s)
 {
-    const int g = tile_grid(c, 256ll * 32);
+    const int g = tile_grid(c, HS_KERNEL_SCALARS, 256ll * 32);
     if (c.precision == HS_FP64) hipLaunchKernelGGL((k_cell_scalars<double, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
     else hipLaunchKernelGGL((k_cell_scalars<float, kTileW, kCapWave>), dim3(g), dim3(64), 0, S_(s), c);
 }
 void Launch::collide(const Ctx &c, void *s)
 {
-    if (c.precision == HS_FP64) hipLaunchKernelGGL(k_collide_tile_f64, dim3(tile_grid(c, 256ll * 4)), dim3(64), 0, S_(s), c);
-    else hipLaunchKernelGGL(k_collide_tile_f32, dim3(tile_grid(c, 256ll * 16)), dim3(64), 0, S_(s), c);
+    if (c.precision == HS_FP64)
+        hipLaunchKernelGGL(k_collide_tile_f64, dim3(tile_grid(c, HS_KERNEL_COLLIDE, 256ll * 4)), dim3(64), 0, S_(s), c);
+    else
+        hipLaunchKernelGGL(k_collide_tile_f32, dim3(tile_grid(c, HS_KERNEL_COLLIDE, 256ll * 16)), dim3(64), 0, S_(s), c);
 }
 void Launch::dense(const Ctx &c, void *s)
 {
-    const int gb = std::max(1, std::min(c.ncells_total, 256 * 2));
+    const int gb = c.grid[HS_KERNEL_DENSE] > 0 ? c.grid[HS_KERNEL_DENSE] : std::max(1, std::min(c.ncells_total, 256 * 2));
     if (c.precision == HS_FP64) hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
     else hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
 }

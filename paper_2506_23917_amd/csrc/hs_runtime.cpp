@@ -842,6 +842,94 @@ hs_status hs_clear_timing(hs_sim *s)
     return HS_OK;
 }
 
+hs_status hs_autotune(hs_sim *s, int steps_per_trial, hs_tune_report *rep)
+{
+    if (!s || steps_per_trial < 1) return HS_ERR_ARG;
+    if (s->failed) return HS_ERR_STATE;
+    hs_status st = check_device(s);
+    if (st) return st;
+    // candidate blocks per grid of each tunable kernel group
+    struct Cand {
+        int which;
+        std::vector<int> grids;
+    };
+    const std::vector<Cand> cands = {
+        {HS_KERNEL_COLLIDE, {1024, 2048, 3072, 4096, 6144, 8192}},
+        {HS_KERNEL_GATHER, {2048, 4096, 8192, 16384}},
+        {HS_KERNEL_SCALARS, {2048, 4096, 8192, 16384}},
+        {HS_KERNEL_DENSE, {128, 256, 512}},
+        {HS_KERNEL_MOVE, {4096, 8192, 16384, 32768}},
+        {HS_KERNEL_SCATTER, {2048, 4096, 8192, 16384}},
+    };
+    if (s->graph_ready) {                       // shapes change: capture again later
+        (void)hipGraphExecDestroy(s->gexec);
+        (void)hipGraphDestroy(s->graph);
+        s->gexec = nullptr;
+        s->graph = nullptr;
+        s->graph_ready = false;
+    }
+    const uint32_t saved = s->timing;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    destroy_events(s);
+    hs_tune_report r;
+    std::memset(&r, 0, sizeof(r));
+    for (const Cand &c : cands) {
+        if (!s->plan.any_spatial && (c.which == HS_KERNEL_MOVE || c.which == HS_KERNEL_SCATTER)) continue;
+        int best = 0;
+        double best_ms = 0.0;
+        for (int g : c.grids) {
+            s->ctx.grid[c.which] = g;
+            s->timing = 1u << c.which;
+            for (int k = 0; k < steps_per_trial; ++k) enqueue_step(s, 1);
+            r.steps += steps_per_trial;
+            HIPCHK(s, hipStreamSynchronize(s->stream));
+            st = check_device(s);
+            if (st) {
+                s->timing = saved;
+                destroy_events(s);
+                return st;
+            }
+            double tot = 0.0;
+            int n = 0;
+            for (const auto &ev : s->events) {
+                float ms = 0.f;
+                if (ev.b[c.which] && ev.e[c.which] && hipEventElapsedTime(&ms, ev.b[c.which], ev.e[c.which]) == hipSuccess) {
+                    tot += ms;
+                    ++n;
+                }
+            }
+            destroy_events(s);
+            const double avg = n ? tot / n : 0.0;
+            if (best == 0 || avg < best_ms) {
+                best = g;
+                best_ms = avg;
+            }
+        }
+        s->ctx.grid[c.which] = best;
+        r.grid[c.which] = best;
+        r.ms[c.which] = best_ms;
+    }
+    s->timing = saved;
+    s->timed_steps = 0;
+    if (rep) *rep = r;
+    return HS_OK;
+}
+
+hs_status hs_set_grid(hs_sim *s, int which, int32_t blocks)
+{
+    if (!s || which < 0 || which >= HS_NUM_KERNELS || blocks < 0) return HS_ERR_ARG;
+    if (s->graph_ready) {
+        (void)hipGraphExecDestroy(s->gexec);
+        (void)hipGraphDestroy(s->graph);
+        s->gexec = nullptr;
+        s->graph = nullptr;
+        s->graph_ready = false;
+    }
+    s->ctx.grid[which] = blocks;
+    return HS_OK;
+}
+
+
 const char *hs_error_string(const hs_sim *s)
 {
     if (!s) return "no sim";

@@ -20,6 +20,10 @@ BODY = {"none": 0, "cylinder": 1, "sphere": 2}
 FLAG_TRACE, FLAG_NO_PARTICLES, FLAG_GRAPH = 1, 2, 4
 KERNELS = {"inject": 0, "move": 1, "scan": 2, "scatter": 3, "gather": 4, "scalars": 5, "collide": 6,
            "dense": 7, "step": 8}
+
+
+class HsTuneReport(C.Structure):
+    _fields_ = [("grid", C.c_int32 * len(KERNELS)), ("ms", C.c_double * len(KERNELS)), ("steps", C.c_int64)]
 COUNTERS = ("injected", "removed", "wall_hits", "candidates", "accepted", "relaxed",
             "ar_attempts", "ar_cap", "bounce_cap", "inject_cap", "skipped_cells")
 STATUS = {0: "ok", 1: "argument", 2: "capacity", 3: "numeric", 4: "device", 5: "state"}
@@ -91,6 +95,8 @@ def lib():
             "hs_set_timing": ([V, C.c_uint32], C.c_int),
             "hs_kernel_timing": ([V, C.c_int, P(C.c_double), P(C.c_int64)], C.c_int),
             "hs_clear_timing": ([V], C.c_int),
+            "hs_autotune": ([V, C.c_int, P(HsTuneReport)], C.c_int),
+            "hs_set_grid": ([V, C.c_int, C.c_int32], C.c_int),
             "hs_error_string": ([V], C.c_char_p),
             "hs_destroy": ([V], None),
             "hs_debug_philox": ([C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, V, V], C.c_int),
@@ -106,7 +112,7 @@ def lib():
 def exported_symbols():
     return ["hs_plan", "hs_init_particles", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
             "hs_export_state", "hs_import_state", "hs_last_trace", "hs_counters", "hs_num_cells",
-            "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing",
+            "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
             "hs_error_string", "hs_destroy", "hs_debug_philox"]
 
 
@@ -324,6 +330,18 @@ class Sim:
 
     def clear_timing(self):
         self._check(self.L.hs_clear_timing(self.h), "hs_clear_timing")
+
+    # -- launch shapes --------------------------------------------------------------------
+    def autotune(self, steps_per_trial=10) -> dict:
+        """Pick the grid size of each tunable kernel group by timing candidates on the live
+        run (the simulation advances by the returned `steps`; results do not depend on it)."""
+        r = HsTuneReport()
+        self._check(self.L.hs_autotune(self.h, int(steps_per_trial), C.byref(r)), "hs_autotune")
+        out = {k: (int(r.grid[i]), float(r.ms[i])) for k, i in KERNELS.items() if r.grid[i] > 0}
+        return dict(grids=out, steps=int(r.steps))
+
+    def set_grid(self, which, blocks):
+        self._check(self.L.hs_set_grid(self.h, KERNELS[which], int(blocks)), "hs_set_grid")
 
 
 def debug_philox(seed, stream, first, step, draw, n, device="cuda:0") -> np.ndarray:

@@ -4,6 +4,7 @@
 * batching: a case gives the same bits alone or inside a ragged batch (case-local RNG keys);
 * graph replay (HS_FLAG_GRAPH) equals eager launches, replay after replay;
 * checkpoint: export, import into a fresh sim and continue == never stopping;
+* the launch-shape autotuner changes no result;
 * FP32-mixed against FP64 from the same state: relative L2 of the cell moments n, u, T, q
   <= 1e-3 after one step (paired); over 300 sampled steps no further from FP64 than a second
   FP64 run with another seed; the FP32-mixed Sod ensemble against the exact Riemann solution;
@@ -93,6 +94,24 @@ def test_export_import_resume_is_exact(gas, prec):
     c.import_state(0, st)
     c.step(3)
     _same(a.export_state(0), c.export_state(0), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_is_result_neutral(gas, prec):
+    """Launch shapes chosen by the autotuner change no result: a tuned run equals an untuned
+    run of the same number of steps."""
+    case = _cyl()
+    a = _sim(gas, case, precision=prec)
+    rep = a.autotune(steps_per_trial=2)
+    assert rep["steps"] > 0 and "collide" in rep["grids"] and "move" in rep["grids"]
+    a.step(3)
+    b = _sim(gas, case, precision=prec)
+    b.step(rep["steps"] + 3)
+    _same(a.export_state(0), b.export_state(0), prec)
+    a.set_grid("collide", 0)            # back to the built-in shape
+    a.step(1)
+    b.step(1)
+    _same(a.export_state(0), b.export_state(0), prec)
 
 
 def _rel_l2(a, b):
