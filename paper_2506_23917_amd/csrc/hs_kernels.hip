@@ -1246,6 +1246,44 @@ __device__ __forceinline__ int group_sum_i(int x, int kb)
     return x;
 }
 
+// The same with a group size per lane (groups of several sizes in one wave, each aligned to
+// its size): every level up to the wave's largest group runs, and a lane adds its partner's
+// value only at the levels inside its own group.
+template <int K>
+__device__ __forceinline__ void group_sum_v(double (&x)[K], int kb, int kbmax)
+{
+    if (kbmax >= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { const double y = dpp_partner<kDppXor1>(x[k]); if (kb >= 1) x[k] = x[k] + y; }
+    }
+    if (kbmax >= 2) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { const double y = dpp_partner<kDppXor2>(x[k]); if (kb >= 2) x[k] = x[k] + y; }
+    }
+    if (kbmax >= 3) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { const double y = dpp_partner<kDppHalfMirror>(x[k]); if (kb >= 3) x[k] = x[k] + y; }
+    }
+    if (kbmax >= 4) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { const double y = dpp_partner<kDppMirror>(x[k]); if (kb >= 4) x[k] = x[k] + y; }
+    }
+    for (int l = 4; l < kbmax; ++l) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { const double y = __shfl_xor(x[k], 1 << l, 64); if (kb > l) x[k] = x[k] + y; }
+    }
+}
+
+__device__ __forceinline__ int group_sum_iv(int x, int kb, int kbmax)
+{
+    if (kbmax >= 1) { const int y = dpp_partner_i<kDppXor1>(x); if (kb >= 1) x += y; }
+    if (kbmax >= 2) { const int y = dpp_partner_i<kDppXor2>(x); if (kb >= 2) x += y; }
+    if (kbmax >= 3) { const int y = dpp_partner_i<kDppHalfMirror>(x); if (kb >= 3) x += y; }
+    if (kbmax >= 4) { const int y = dpp_partner_i<kDppMirror>(x); if (kb >= 4) x += y; }
+    for (int l = 4; l < kbmax; ++l) { const int y = __shfl_xor(x, 1 << l, 64); if (kb > l) x += y; }
+    return x;
+}
+
 // Per-cell record written by k_cell_scalars for the tile kernel (16 doubles per cell):
 // U[3], T, P_relax, (sigma c)_max, N_col, active, Shakhov parameters Q[3], p, RT,
 // sqrt(2RT), A_max.
@@ -1480,7 +1518,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
     using UWord = std::conditional_t<sizeof(P) == 8, unsigned long long, unsigned int>;
     __shared__ UWord c_obs[MAXC], c_hash[MAXC];
     __shared__ int32_t c_nacc[MAXC];
-    __shared__ uint8_t c_case[MAXC], c_samp[MAXC];
+    __shared__ uint8_t c_case[MAXC], c_samp[MAXC], c_goff[MAXC], c_gkb[MAXC];
+    __shared__ uint8_t s_gcell[64];       // tile-local cell of each lane's group (0xFF: none)
     __shared__ uint32_t c_seed[MAXC][2], c_lcid[MAXC];
     Globals *G = C.g;
     if (G->halt) return;
@@ -1505,12 +1544,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             return;
         }
         if (ncl == 0) continue;          // a tile inside one dense cell
-        // lane groups: 2^kb lanes per cell; the group's cell scalars
-        const int kb = ncl == 1 ? 6 : 6 - (32 - __clz(ncl - 1));
-        const int kk = 1 << kb;
-        const int gc = lane >> kb, sub = lane & (kk - 1);
-        const bool own = gc < ncl;
-        const int g = cb + gc;
         // cell table: lane = local cell
         int nn0 = 0, n_lane = 0;
         if (lane < ncl) {
@@ -1592,6 +1625,52 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             }
         }
         team_sync<64>();
+        // ---- lane groups sized to the work: a cell with nn particles of the tile's np gets an
+        // aligned group of 2^kb ~ 64 nn / np lanes (one at least if nn > 0, none for an empty
+        // or dense cell); groups are laid out largest first, which aligns each to its size
+        int gsz = 0;
+        if (lane < ncl) {
+            const int nnc = c_off[lane + 1] - c_off[lane];
+            if (nnc > 0) gsz = 1 << (31 - __clz(max(1, (64 * nnc) / np)));
+        }
+        for (;;) {                        // fit into 64 lanes: halve the largest group
+            int tot = gsz, mx = gsz;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                tot += __shfl_xor(tot, off, 64);
+                mx = max(mx, __shfl_xor(mx, off, 64));
+            }
+            if (tot <= 64) break;
+            const unsigned long long m = __ballot(gsz == mx);
+            if (lane == __ffsll((long long)m) - 1) gsz >>= 1;
+        }
+        {
+            int goff = 0, gbase = 0;
+            for (int sz = 64; sz >= 1; sz >>= 1) {
+                const unsigned long long m = __ballot(gsz == sz);
+                if (gsz == sz) goff = gbase + __popcll(m & ((1ull << lane) - 1ull)) * sz;
+                gbase += __popcll(m) * sz;
+            }
+            s_gcell[lane] = 0xFF;
+            team_sync<64>();
+            for (int j = 0; j < gsz; ++j) s_gcell[goff + j] = (uint8_t)lane;
+            if (lane < ncl) {
+                c_goff[lane] = (uint8_t)goff;
+                c_gkb[lane] = (uint8_t)(gsz > 0 ? 31 - __clz(gsz) : 0);
+                c_kb[lane] = 0;
+            }
+            team_sync<64>();
+        }
+        const int gcell = s_gcell[lane];
+        const bool own = gcell != 0xFF;
+        const int gc = own ? gcell : 0;
+        const int kb = own ? (int)c_gkb[gc] : 0;
+        const int kk = 1 << kb;
+        const int sub = own ? lane - (int)c_goff[gc] : 0;
+        const int g = cb + gc;
+        int kbmax = kb;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) kbmax = max(kbmax, __shfl_xor(kbmax, off, 64));
         double scmax = 0.0, U[3] = {0.0, 0.0, 0.0}, T = 0.0, pr = 0.0;
         P par[7] = {(P)0, (P)0, (P)0, (P)0, (P)0, (P)0, (P)0};
         long long ncol = 0;
@@ -1626,17 +1705,20 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             my_case = cid;
         }
 
-        // candidate ranges of the cells
-        const int nc_l = lead ? (int)ncol : 0;
+        // candidate ranges of the cells, in cell order
+        if (lead) c_kb[gc] = (int)ncol;
+        if (lane < ncl) {
+            c_obs[lane] = 0;
+            c_hash[lane] = 0;
+            c_nacc[lane] = 0;
+        }
+        if (sub == 0 && own) c_scm[gc] = (P)scmax;
+        team_sync<64>();
+        const int nc_l = lane < ncl ? c_kb[lane] : 0;
         const int kincl = wave_incl_scan(nc_l);
         const int kall = __shfl(kincl, 63, 64);
-        if (sub == 0 && own) {
-            c_kb[gc] = kincl - nc_l;
-            c_scm[gc] = (P)scmax;
-            c_obs[gc] = 0;
-            c_hash[gc] = 0;
-            c_nacc[gc] = 0;
-        }
+        team_sync<64>();
+        if (lane < ncl) c_kb[lane] = kincl - nc_l;
         if (lane == 0) c_kb[ncl] = kall;
         team_sync<64>();
 
@@ -1759,25 +1841,38 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         const int o = work ? c_off[gc] : 0;
         const int nn = work ? c_off[gc + 1] - o : 0;
 
-        // SP-Shakhov relaxation (Eq. 16-18); the ids of four particles are fetched at once
+        // SP-Shakhov relaxation (Eq. 16-18).  First the Bernoulli decisions of the lane's
+        // particles (ids fetched four at a time) into a bit mask, then the acceptance-rejection
+        // draws of the relaxing ones only, so a wave runs as many draw sequences as its
+        // busiest lane has relaxing particles.
         int rel0 = 0, rel1 = 0, rel2 = 0;
         if (pr > 0.0) {
             const int64_t *ids = Dd.id + c_start[gc];
             const uint32_t sd0 = c_seed[gc][0], sd1 = c_seed[gc][1];
 #pragma unroll 1
-            for (int i0 = sub; i0 < nn; i0 += 4 * kk) {
-                int64_t idv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + u * kk;
-                    idv[u] = i < nn ? ids[i] : 0;
-                }
+            for (int base = sub; base < nn; base += 64 * kk) {
+                const int lim = min(nn, base + 64 * kk);
+                unsigned long long mask = 0ull;
 #pragma unroll 1
-                for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + u * kk;
-                    if (i >= nn) break;
-                    const int64_t id = idv[u];
-                    if (!(unid(draw_s(sd0, sd1, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
+                for (int i0 = base; i0 < lim; i0 += 4 * kk) {
+                    int64_t idv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u * kk;
+                        idv[u] = i < lim ? ids[i] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u * kk;
+                        if (i < lim && unid(draw_s(sd0, sd1, kStreamParticle, (uint64_t)idv[u], st, kDrawRelax).x) < pr)
+                            mask |= 1ull << ((i - base) / kk);
+                    }
+                }
+                while (mask) {
+                    const int bit = __ffsll((long long)mask) - 1;
+                    mask &= mask - 1ull;
+                    const int i = base + bit * kk;
+                    const int64_t id = ids[i];
                     P Cv[3];
                     int used = shakhov_draw<P>(sd0, sd1, id, st, par, (P)(1.0 - gas.Pr), Cv);
                     if (used < 0) {
@@ -1805,7 +1900,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 r1[2] = r1[2] + (double)s_v[2][o + i];
             }
         }
-        group_sum<3>(r1, kb);
+        group_sum_v<3>(r1, kb, kbmax);
         double Up[3] = {0.0, 0.0, 0.0};
         double r2[1] = {0.0};
         if (active) {
@@ -1816,7 +1911,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
             }
         }
-        group_sum<1>(r2, kb);
+        group_sum_v<1>(r2, kb, kbmax);
         double f = 0.0;
         if (active) {
             const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
@@ -1849,11 +1944,11 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 }
             }
         }
-        if (__any(sums)) group_sum<12>(sm, kb);
+        if (__any(sums)) group_sum_v<12>(sm, kb, kbmax);
         int nrel[3] = {rel0, rel1, rel2};
         if (tracing) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) nrel[j] = group_sum_i(nrel[j], kb);
+            for (int j = 0; j < 3; ++j) nrel[j] = group_sum_iv(nrel[j], kb, kbmax);
         }
         if (lead) {
             if (sampling) {
@@ -2206,9 +2301,18 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
         // SP-Shakhov relaxation (Eq. 16-18)
         if (pr > 0.0) {
             int nrel = 0, nar = 0, ncap = 0;
-            for (int k = tid; k < n; k += kBlock) {
+            // decisions first (at most CAPB / kBlock particles per thread), then the draws
+            static_assert(CAPB / kBlock <= 32, "decision mask");
+            uint32_t mask = 0u;
+            for (int k = tid, j = 0; k < n; k += kBlock, ++j) {
                 const int64_t id = Dd.id[(size_t)s0 + k];
-                if (!(unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr)) continue;
+                if (unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr) mask |= 1u << j;
+            }
+            while (mask) {
+                const int j = __ffs((int)mask) - 1;
+                mask &= mask - 1u;
+                const int k = tid + kBlock * j;
+                const int64_t id = Dd.id[(size_t)s0 + k];
                 P Cv[3];
                 int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, par, (P)(1.0 - gas.Pr), Cv);
                 if (used < 0) {
