@@ -1065,6 +1065,21 @@ __device__ __forceinline__ void seg_round(double (&x)[K], int head, int tail, do
     }
 }
 
+// XCD-aware order of the tiles.  Workgroups are dealt to the chip's 8 XCDs in turn (block b
+// runs on XCD b mod 8), and each XCD has its own L2.  Neighbouring tiles read the same source
+// cache lines (a cell's particles come from the cells around it, which belong to tiles a row
+// apart), so each XCD takes whole chunks of kTileChunk consecutive tiles, chunk c going to
+// XCD c mod 8, and its blocks sweep them in order.  The grid is a multiple of 8.
+constexpr int kXcds = 8;
+constexpr int kTileChunk = 256;
+
+// Tile of the p-th position in this block's XCD sequence (increasing in p).
+__device__ __forceinline__ int xcd_tile(int p, int xcd)
+{
+    const int chunk = p / kTileChunk;
+    return (chunk * kXcds + xcd) * kTileChunk + (p - chunk * kTileChunk);
+}
+
 // Tiles of the collision stage: a 64-thread block takes the cells whose weight
 // w(c) = cell_start[c] + 4 c falls in [t TW, (t+1) TW): at most TW/4 = 64 cells and TW + D
 // particles; cells denser than D go to k_collide_dense.  This kernel restores the stable
@@ -1074,7 +1089,8 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
 {
     constexpr int MAXC = TW / 4;
     constexpr int MAXP = TW + D;
-    __shared__ int32_t s_src[MAXP];
+    __shared__ int32_t s_src[MAXP];       // source of each scatter slot
+    __shared__ int32_t s_dsrc[MAXP];      // source of each destination slot
     __shared__ uint8_t s_lc[MAXP];
     __shared__ int32_t c_start[MAXC], c_off[MAXC + 1];
     __shared__ uint8_t c_case[MAXC], c_dim[MAXC];
@@ -1089,7 +1105,10 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     const int ntiles = G->n_tiles;
     const int NC = C.ncells_total;
 
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
+    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
+        const int t = xcd_tile(pos, xcd);
+        if (t >= ntiles) break;
         const int cb = C.tile_cell[t];
         const int ncl = C.tile_cell[t + 1] - cb;
         if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
@@ -1144,43 +1163,54 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
                 if (pidx[r] >= 0) s_src[lane + 64 * r] = pidx[r];
         }
         team_sync<64>();
-        // stable order inside each cell, gather (all loads first), write position / cell / id
-        {
-            P gv[R][3], gp[R][3];
-            int64_t gid[R];
+        // stable order inside each cell: a source's rank among its cell's sources is its
+        // place (sources are distinct); the slots then hold sources in destination order
+        for (int s = lane; s < np; s += 64) {
+            const int lc = s_lc[s];
+            const int o = c_off[lc], e = c_off[lc + 1];
+            const int src = s_src[s];
+            int rk = 0;
+            for (int u = o; u < e; ++u) rk += s_src[u] < src;
+            s_dsrc[o + rk] = src;
+        }
+        team_sync<64>();
+        // gather by destination slot (neighbouring lanes write neighbouring particles and,
+        // sources being in increasing order, mostly read neighbouring ones); the loads of a
+        // group of rows are in flight together
+        constexpr int RG = 4;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = lane + 64 * r;
-                if (s < np) {
-                    const int src = s_src[s];
-                    const int dim = c_dim[s_lc[s]];
-                    gv[r][0] = S.vel[0][src];
-                    gv[r][1] = S.vel[1][src];
-                    gv[r][2] = S.vel[2][src];
-                    gid[r] = S.id[src];
+        for (int r0 = 0; r0 < R; r0 += RG) {
+            P gv[RG][3], gp[RG][3];
+            int64_t gid[RG];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) gp[r][a] = a < dim ? S.pos[a][src] : (P)0;
+            for (int q = 0; q < RG; ++q) {
+                const int d = lane + 64 * (r0 + q);
+                if (r0 + q < R && d < np) {
+                    const uint32_t src = (uint32_t)s_dsrc[d];
+                    const int dim = c_dim[s_lc[d]];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gv[q][c] = ld_off(S.vel[c], src * (uint32_t)sizeof(P));
+                    gid[q] = ld_off(S.id, src * 8u);
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; ++a2)
+                        gp[q][a2] = a2 < dim ? ld_off(S.pos[a2], src * (uint32_t)sizeof(P)) : (P)0;
                 }
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = lane + 64 * r;
-                if (s < np) {
-                    const int lc = s_lc[s];
-                    const int o = c_off[lc], e = c_off[lc + 1];
-                    const int src = s_src[s];
-                    int rk = 0;
-                    for (int u = o; u < e; ++u) rk += s_src[u] < src;
-                    const size_t dst = (size_t)c_start[lc] + rk;
+            for (int q = 0; q < RG; ++q) {
+                const int d = lane + 64 * (r0 + q);
+                if (r0 + q < R && d < np) {
+                    const int lc = s_lc[d];
+                    const size_t dst = (size_t)c_start[lc] + (d - c_off[lc]);
                     const int dim = c_dim[lc];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        if (a < dim) Dd.pos[a][dst] = gp[r][a];
+                    for (int a2 = 0; a2 < 3; ++a2)
+                        if (a2 < dim) Dd.pos[a2][dst] = gp[q][a2];
                     Dd.cell[dst] = cb + lc;
-                    Dd.id[dst] = gid[r];
-                    Dd.vel[0][dst] = gv[r][0];
-                    Dd.vel[1][dst] = gv[r][1];
-                    Dd.vel[2][dst] = gv[r][2];
+                    Dd.id[dst] = gid[q];
+                    Dd.vel[0][dst] = gv[q][0];
+                    Dd.vel[1][dst] = gv[q][1];
+                    Dd.vel[2][dst] = gv[q][2];
                 }
             }
         }
@@ -1314,7 +1344,10 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
     long long skipped = 0;
     int my_case = -1;
 
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
+    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
+        const int t = xcd_tile(pos, xcd);
+        if (t >= ntiles) break;
         const int cb = C.tile_cell[t];
         const int ncl = C.tile_cell[t + 1] - cb;
         if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
@@ -1536,7 +1569,10 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
     CellCounts cc{0, 0, 0, 0, 0, 0};
     int my_case = -1;
 
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
+    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
+        const int t = xcd_tile(pos, xcd);
+        if (t >= ntiles) break;
         const int cb = C.tile_cell[t];
         const int ncl = C.tile_cell[t + 1] - cb;
         if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
@@ -2608,9 +2644,12 @@ void Launch::scatter(const Ctx &c, void *s)
 // counter flush are paid once per block).
 static int tile_grid(const Ctx &c, int which, long long cap)
 {
-    if (c.grid[which] > 0) return c.grid[which];
-    const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
-    return (int)std::max(1ll, std::min(maxtiles, cap));
+    long long g = c.grid[which];
+    if (g <= 0) {
+        const long long maxtiles = ((long long)c.capacity + 4ll * c.ncells_total) / kTileW + 1;
+        g = std::max(1ll, std::min(maxtiles, cap));
+    }
+    return (int)((g + kXcds - 1) / kXcds * kXcds);     // whole blocks per XCD
 }
 void Launch::gather(const Ctx &c, void *s)
 {
