@@ -117,6 +117,7 @@ struct Ctx {
     int32_t *scan_part;
     int32_t *big_list;
     int32_t *tile_cell;           // first cell of each collide tile (n_tiles + 1 entries)
+    int32_t *tile_case;           // case of each tile (tiles never span cases)
     int32_t *work;                // body worklist (particle indices)
     TraceDev *trace;              // nullptr unless tracing
     Globals *g;

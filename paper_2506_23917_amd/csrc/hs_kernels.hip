@@ -390,9 +390,17 @@ __global__ void k_tile_table(Ctx C)
     const long long c0 = C.cstart[cs.cell0];
     const long long w0 = (C.cstart[g] - c0) + 4ll * (g - cs.cell0);
     const long long w1 = (C.cstart[g + 1] - c0) + 4ll * (g + 1 - cs.cell0);
-    int32_t *tc = C.tile_cell + C.g->case_tile0[k];
-    for (long long t = w0 / tw + 1; t <= w1 / tw; ++t) tc[t] = g + 1;
-    if (g == cs.cell0) tc[0] = g;
+    const int t0 = C.g->case_tile0[k], ntk = C.g->case_tile0[k + 1] - t0;
+    int32_t *tc = C.tile_cell + t0;
+    int32_t *tk = C.tile_case + t0;
+    for (long long t = w0 / tw + 1; t <= w1 / tw; ++t) {
+        tc[t] = g + 1;
+        if (t < ntk) tk[t] = k;
+    }
+    if (g == cs.cell0) {
+        tc[0] = g;
+        tk[0] = k;
+    }
     if (g == cs.cell0 + cs.ncells - 1 && w1 % tw != 0) tc[w1 / tw + 1] = g + 1;
 }
 
@@ -1080,6 +1088,80 @@ __device__ __forceinline__ int xcd_tile(int p, int xcd)
     return (chunk * kXcds + xcd) * kTileChunk + (p - chunk * kTileChunk);
 }
 
+// Table entries of a tile: first cell, end cell, case.  The tile kernels load those of the
+// next tile while they work on the current one (uniform loads, through the scalar cache).
+struct TileRef {
+    int cb, ce, ci;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const Ctx &C, int t, int ntiles)
+{
+    TileRef r{0, 0, 0};
+    if (t < ntiles) {
+        r.cb = C.tile_cell[t];
+        r.ce = C.tile_cell[t + 1];
+        r.ci = C.tile_case[t];
+    }
+    return r;
+}
+
+// Counter sums of one wave by case.  Lane l holds counter base + (l & 7) of slot l >> 3
+// (eight cases at a time).  Lanes count privately; when the wave moves to a tile of another
+// case their counts are summed over the wave into that case's slot, and the flush adds each
+// slot with one atomic per lane, so no address takes an atomic per lane or per tile.
+struct CaseTally {
+    long long val;
+    int slot_case;
+    int nslot;                          // uniform over the wave
+};
+
+template <int K>
+__device__ __forceinline__ void tally_flush(const Ctx &C, CaseTally &T, int base)
+{
+    const int k = threadIdx.x & 7;
+    if (T.slot_case >= 0 && k < K && T.val != 0)
+        atomicAdd((unsigned long long *)&C.g->counters[T.slot_case][base + k], (unsigned long long)T.val);
+    T.val = 0;
+    T.slot_case = -1;
+    T.nslot = 0;
+}
+
+// Adds the wave's sums of v[] to case cid (every lane of the wave calls it).
+template <int K>
+__device__ __forceinline__ void tally_add(const Ctx &C, CaseTally &T, int cid, int base, const long long (&v)[K])
+{
+    static_assert(K <= 8, "eight counters per slot");
+    long long tot[K];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        long long x = v[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        tot[j] = x;
+        any = any || x != 0;
+    }
+    if (!any || cid < 0) return;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long hit = __ballot(T.slot_case == cid);
+    int slot;
+    if (hit) {
+        slot = (__ffsll((long long)hit) - 1) >> 3;
+    } else {
+        if (T.nslot == 8) tally_flush<K>(C, T, base);
+        slot = T.nslot++;
+        if ((lane >> 3) == slot) T.slot_case = cid;
+    }
+    if ((lane >> 3) == slot) {
+        const int k = lane & 7;
+        long long a = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j == k) a = tot[j];
+        T.val += a;
+    }
+}
+
 // Tiles of the collision stage: a 64-thread block takes the cells whose weight
 // w(c) = cell_start[c] + 4 c falls in [t TW, (t+1) TW): at most TW/4 = 64 cells and TW + D
 // particles; cells denser than D go to k_collide_dense.  This kernel restores the stable
@@ -1093,7 +1175,6 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     __shared__ int32_t s_dsrc[MAXP];      // source of each destination slot
     __shared__ uint8_t s_lc[MAXP];
     __shared__ int32_t c_start[MAXC], c_off[MAXC + 1];
-    __shared__ uint8_t c_case[MAXC], c_dim[MAXC];
     Globals *G = C.g;
     if (G->halt) return;
     const int lane = threadIdx.x;
@@ -1106,28 +1187,31 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     const int NC = C.ncells_total;
 
     const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
-    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
-        const int t = xcd_tile(pos, xcd);
-        if (t >= ntiles) break;
-        const int cb = C.tile_cell[t];
-        const int ncl = C.tile_cell[t + 1] - cb;
-        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+    int pos = blockIdx.x / kXcds;
+    int t = xcd_tile(pos, xcd);
+    TileRef nx = tile_ref(C, t, ntiles);
+    while (t < ntiles) {
+        const TileRef cur = nx;
+        pos += nbx;
+        t = xcd_tile(pos, xcd);
+        nx = tile_ref(C, t, ntiles);
+        const int cb = cur.cb;
+        const int ncl = cur.ce - cb;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC || cur.ci < 0 || cur.ci >= C.n_cases) {
             if (lane == 0) raise_error(G, kErrState);
             return;
         }
+        const int dim = C.cases[cur.ci].dim;
         // owner lane = local cell
         const bool own = lane < ncl;
         const int g = cb + lane;
-        int n = 0, start = 0, cid = 0;
+        int n = 0, start = 0;
         bool dense = false;
         if (own) {
             start = C.cstart[g];
             n = C.cstart[g + 1] - start;
             dense = n > D;
-            cid = case_of(C, g);
             c_start[lane] = start;
-            c_case[lane] = (uint8_t)cid;
-            c_dim[lane] = (uint8_t)C.cases[cid].dim;
         }
         const int nn = (own && !dense) ? n : 0;
         const int incl = wave_incl_scan(nn);
@@ -1187,7 +1271,6 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
                 const int d = lane + 64 * (r0 + q);
                 if (r0 + q < R && d < np) {
                     const uint32_t src = (uint32_t)s_dsrc[d];
-                    const int dim = c_dim[s_lc[d]];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) gv[q][c] = ld_off(S.vel[c], src * (uint32_t)sizeof(P));
                     gid[q] = ld_off(S.id, src * 8u);
@@ -1202,7 +1285,6 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
                 if (r0 + q < R && d < np) {
                     const int lc = s_lc[d];
                     const size_t dst = (size_t)c_start[lc] + (d - c_off[lc]);
-                    const int dim = c_dim[lc];
 #pragma unroll
                     for (int a2 = 0; a2 < 3; ++a2)
                         if (a2 < dim) Dd.pos[a2][dst] = gp[q][a2];
@@ -1341,31 +1423,43 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
     const int NC = C.ncells_total;
     const GasDev &gas = C.gas;
     const bool tracing = C.trace != nullptr;
-    long long skipped = 0;
+    long long skipped[1] = {0};
+    CaseTally tally{0, -1, 0};
     int my_case = -1;
 
     const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
-    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
-        const int t = xcd_tile(pos, xcd);
-        if (t >= ntiles) break;
-        const int cb = C.tile_cell[t];
-        const int ncl = C.tile_cell[t + 1] - cb;
-        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+    int pos = blockIdx.x / kXcds;
+    int t = xcd_tile(pos, xcd);
+    TileRef nx = tile_ref(C, t, ntiles);
+    while (t < ntiles) {
+        const TileRef cur = nx;
+        pos += nbx;
+        t = xcd_tile(pos, xcd);
+        nx = tile_ref(C, t, ntiles);
+        const int cb = cur.cb;
+        const int ncl = cur.ce - cb;
+        const int cid = cur.ci;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC || cid < 0 || cid >= C.n_cases) {
             if (lane == 0) raise_error(G, kErrState);
             return;
         }
         if (ncl == 0) continue;
+        if (cid != my_case) {
+            tally_add<1>(C, tally, my_case, HS_CNT_SKIPPED_CELLS, skipped);
+            skipped[0] = 0;
+            my_case = cid;
+        }
+        const CaseDev &cs = C.cases[cid];
         const int kb = ncl == 1 ? 6 : 6 - (32 - __clz(ncl - 1));
         const int kk = 1 << kb;
         const int gc = lane >> kb, sub = lane & (kk - 1);
         const bool own = gc < ncl;
         const int g = cb + gc;
-        int start = 0, n = 0, cid = 0;
+        int start = 0, n = 0;
         double vol = 0.0, scm = 0.0;
         if (own) {
             start = C.cstart[g];
             n = C.cstart[g + 1] - start;
-            cid = case_of(C, g);
             vol = C.vol[g];
             scm = C.sigc[g];
         }
@@ -1428,13 +1522,6 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
         if constexpr (sizeof(P) == 8) peculiar(nn >= 2);
 
         TraceDev *tr = (lead && tracing) ? &C.trace[g] : nullptr;
-        if (work && cid != my_case) {
-            if (my_case >= 0 && skipped)
-                atomicAdd((unsigned long long *)&G->counters[my_case][HS_CNT_SKIPPED_CELLS], (unsigned long long)skipped);
-            skipped = 0;
-            my_case = cid;
-        }
-        const CaseDev &cs = C.cases[cid];
         double T = 0.0, pr = 0.0, p = 0.0, tau = 0.0, dtD = 0.0;
         bool active = false;
         if (work && nn >= 2) {
@@ -1445,7 +1532,7 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
                 T = gas.m * s2[0] / (3.0 * kKB * (double)(nn - 1));
             if (!isfinite(T)) raise_error(G, kErrNumeric);
             active = T > 0.0 && vol > 0.0;
-            if (!active && lead) ++skipped;
+            if (!active && lead) ++skipped[0];
         }
         if (active) {
             const double nd = (double)nn * cs.F_N / vol;
@@ -1525,7 +1612,8 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
             }
         }
     }
-    wave_add(&G->counters[0][0], HS_NUM_COUNTERS, my_case, HS_CNT_SKIPPED_CELLS, skipped, my_case >= 0);
+    tally_add<1>(C, tally, my_case, HS_CNT_SKIPPED_CELLS, skipped);
+    tally_flush<1>(C, tally, HS_CNT_SKIPPED_CELLS);
 }
 
 // Steps (4)-(5) of the tiles' cells on the sorted state: NTC, SP-Shakhov resampling, Eq. 19
@@ -1551,9 +1639,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
     using UWord = std::conditional_t<sizeof(P) == 8, unsigned long long, unsigned int>;
     __shared__ UWord c_obs[MAXC], c_hash[MAXC];
     __shared__ int32_t c_nacc[MAXC];
-    __shared__ uint8_t c_case[MAXC], c_samp[MAXC], c_goff[MAXC], c_gkb[MAXC];
+    __shared__ uint8_t c_goff[MAXC], c_gkb[MAXC];
     __shared__ uint8_t s_gcell[64];       // tile-local cell of each lane's group (0xFF: none)
-    __shared__ uint32_t c_seed[MAXC][2], c_lcid[MAXC];
     Globals *G = C.g;
     if (G->halt) return;
     const int lane = threadIdx.x;
@@ -1566,20 +1653,39 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
     const int NC = C.ncells_total;
     const GasDev &gas = C.gas;
     const bool tracing = C.trace != nullptr;
-    CellCounts cc{0, 0, 0, 0, 0, 0};
+    // counts of this wave: candidates, accepted, relaxed, AR attempts, AR cap hits
+    long long cnt[5] = {0, 0, 0, 0, 0};
+    CaseTally tally{0, -1, 0};
     int my_case = -1;
 
     const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
-    for (int pos = blockIdx.x / kXcds;; pos += nbx) {
-        const int t = xcd_tile(pos, xcd);
-        if (t >= ntiles) break;
-        const int cb = C.tile_cell[t];
-        const int ncl = C.tile_cell[t + 1] - cb;
-        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC) {
+    int pos = blockIdx.x / kXcds;
+    int t = xcd_tile(pos, xcd);
+    TileRef nx = tile_ref(C, t, ntiles);
+    while (t < ntiles) {
+        const TileRef cur = nx;
+        pos += nbx;
+        t = xcd_tile(pos, xcd);
+        nx = tile_ref(C, t, ntiles);
+        const int cb = cur.cb;
+        const int ncl = cur.ce - cb;
+        const int cid = cur.ci;
+        if (ncl < 0 || ncl > MAXC || cb < 0 || cb + ncl > NC || cid < 0 || cid >= C.n_cases) {
             if (lane == 0) raise_error(G, kErrState);
             return;
         }
         if (ncl == 0) continue;          // a tile inside one dense cell
+        if (cid != my_case) {
+            tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, cnt);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) cnt[j] = 0;
+            my_case = cid;
+        }
+        // the tile's case (uniform): RNG key, first cell, sampling on or off
+        const CaseDev &cs = C.cases[cid];
+        const uint32_t sd0 = cs.seed_lo, sd1 = cs.seed_hi;
+        const int lc0 = cb - cs.cell0;
+        const bool samp_on = step >= cs.n_steady;
         // cell table: lane = local cell
         int nn0 = 0, n_lane = 0;
         if (lane < ncl) {
@@ -1587,13 +1693,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             const int start = C.cstart[g0];
             n_lane = C.cstart[g0 + 1] - start;
             c_start[lane] = start;
-            const int ci = case_of(C, g0);
-            const CaseDev &cs = C.cases[ci];
-            c_case[lane] = (uint8_t)ci;
-            c_seed[lane][0] = cs.seed_lo;
-            c_seed[lane][1] = cs.seed_hi;
-            c_lcid[lane] = (uint32_t)(g0 - cs.cell0);
-            c_samp[lane] = step >= cs.n_steady ? 1 : 0;
             nn0 = n_lane > D ? 0 : n_lane;
         }
         const int incl = wave_incl_scan(nn0);
@@ -1624,7 +1723,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                                                              4, 0, 0);
                     }
                 }
-                __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): the LDS words have landed
             } else {
                 uint32_t boff[R];
 #pragma unroll
@@ -1660,7 +1758,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 }
             }
         }
-        team_sync<64>();
         // ---- lane groups sized to the work: a cell with nn particles of the tile's np gets an
         // aligned group of 2^kb ~ 64 nn / np lanes (one at least if nn > 0, none for an empty
         // or dense cell); groups are laid out largest first, which aligns each to its size
@@ -1721,11 +1818,17 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             U[2] = R[kRecU + 2];
             T = R[kRecT];
             pr = R[kRecPr];
-            if (pr > 0.0) {
+            // the Shakhov parameters hold only where pr > 0 (same cache lines as the rest)
 #pragma unroll
-                for (int j = 0; j < 7; ++j) par[j] = (P)R[kRecPar + j];
+            for (int j = 0; j < 7; ++j) par[j] = (P)R[kRecPar + j];
+            if (!(pr > 0.0)) {
+#pragma unroll
+                for (int j = 0; j < 7; ++j) par[j] = (P)0;
             }
         }
+        // the velocities (FP32: still landing in LDS) and the records have arrived
+        if constexpr (sizeof(P) == 4) __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0)
+        team_sync<64>();
         const int cn = __shfl(n_lane, gc & 63, 64);
         const bool work = own && cn <= D;
         if (!work) {
@@ -1733,13 +1836,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             ncol = 0;
             pr = 0.0;
         }
-        const int cid = own ? c_case[gc] : 0;
         const bool lead = work && sub == 0;
         TraceDev *tr = (lead && tracing) ? &C.trace[g] : nullptr;
-        if (work && cid != my_case) {
-            if (my_case >= 0) flush_counts(C, my_case, cc);
-            my_case = cid;
-        }
 
         // candidate ranges of the cells, in cell order
         if (lead) c_kb[gc] = (int)ncol;
@@ -1786,7 +1884,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                     }
                     const int kc = x - c_kb[a];
                     const int o2 = c_off[a], cn = c_off[a + 1] - o2;
-                    const uint32_t sd0 = c_seed[a][0], sd1 = c_seed[a][1], lcid = c_lcid[a];
+                    const uint32_t lcid = (uint32_t)(lc0 + a);
                     const W4 w = draw_s(sd0, sd1, kStreamCell, lcid, st, (uint32_t)(1 + 2 * kc));
                     const uint32_t i = unidx(w.x, (uint32_t)cn);
                     uint32_t j = unidx(w.y, (uint32_t)(cn - 1));
@@ -1865,8 +1963,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             if constexpr (sizeof(P) == 8) obs = __longlong_as_double((long long)c_obs[gc]);
             else obs = (double)__uint_as_float(c_obs[gc]);
             if (obs > scmax) C.sigc[g] = obs;
-            cc.cand += ncol;
-            cc.acc += c_nacc[gc];
+            cnt[0] += ncol;
+            cnt[1] += c_nacc[gc];
             if (tr) {
                 tr->ncol = ncol;
                 tr->nacc = c_nacc[gc];
@@ -1884,7 +1982,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         int rel0 = 0, rel1 = 0, rel2 = 0;
         if (pr > 0.0) {
             const int64_t *ids = Dd.id + c_start[gc];
-            const uint32_t sd0 = c_seed[gc][0], sd1 = c_seed[gc][1];
 #pragma unroll 1
             for (int base = sub; base < nn; base += 64 * kk) {
                 const int lim = min(nn, base + 64 * kk);
@@ -1923,9 +2020,9 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 }
             }
         }
-        cc.relax += rel0;
-        cc.ar += rel1;
-        cc.arcap += rel2;
+        cnt[2] += rel0;
+        cnt[3] += rel1;
+        cnt[4] += rel2;
 
         // Eq. 19 rescale to the Step (3) U and T
         double r1[3] = {0.0, 0.0, 0.0};
@@ -1954,7 +2051,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
         }
         // apply, write the final velocities, Step (5) sums
-        const bool sampling = work && c_samp[gc] != 0;
+        const bool sampling = work && samp_on;
         const bool sums = sampling || (tracing && work);
         double sm[12];
 #pragma unroll
@@ -2008,7 +2105,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         }
         team_sync<64>();
     }
-    wave_flush_counts(C, my_case, cc);
+    tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, cnt);
+    tally_flush<5>(C, tally, HS_CNT_CANDIDATES);
 }
 
 constexpr int kCapWave = 192;       // densest cell of the tile kernel

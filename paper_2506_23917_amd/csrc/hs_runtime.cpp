@@ -24,7 +24,7 @@ struct Layout {
     size_t total = 0;
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
-    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, cellrec, trace, out;
+    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, trace, out;
 };
 
 struct Plan {
@@ -262,6 +262,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
     L.big = take(4 * nc);
     L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
+    L.tilecase = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.cellrec = take(8 * 16 * nc);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
     size_t maxcase = 1;
@@ -455,6 +456,7 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.scan_part = (int32_t *)(w + L.scanpart);
     c.big_list = (int32_t *)(w + L.big);
     c.tile_cell = (int32_t *)(w + L.tiles);
+    c.tile_case = (int32_t *)(w + L.tilecase);
     c.cellrec = (double *)(w + L.cellrec);
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
     c.tile_w = tile_width();
