@@ -94,12 +94,27 @@ template <> struct Real<float> {
 };
 
 // Case of a global cell: binary search over the cases' first cells.
+// Reads through the constant address space, for tables that no kernel writes while another
+// reads them (the case table; the tile table, written by an earlier launch): wave-uniform
+// reads then become scalar loads.
+template <typename T>
+__device__ __forceinline__ T const_read(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+__device__ __forceinline__ const CaseDev &case_const(const Ctx &C, int ci)
+{
+    using ConstCase = const __attribute__((address_space(4))) CaseDev;
+    return *(const CaseDev *)((ConstCase *)C.cases + ci);
+}
+
 __device__ __forceinline__ int case_of(const Ctx &C, int g)
 {
     int lo = 0, hi = C.n_cases - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (C.cases[mid].cell0 <= g) lo = mid;
+        if (case_const(C, mid).cell0 <= g) lo = mid;
         else hi = mid - 1;
     }
     return lo;

@@ -568,8 +568,33 @@ __device__ __forceinline__ int wave_slot(int32_t *count, int nc, bool want)
     return old + rank;
 }
 
-// Every particle: straight flight with specular / open walls, the moved position written
-// back in place (velocity too when a wall changed it), new cell and slot recorded.
+// Straight flight of particle i of case cs (state already loaded): the moved position
+// written back in place (velocity too when a wall changed it), the new cell returned in nc
+// (-1: left the domain); to_body when the path may meet the body.
+template <typename P>
+__device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> &S, int i, int g, P (&xr)[3],
+                                              P (&v)[3], uint32_t st, int n_live, int &nc, bool &to_body)
+{
+    if (cs.dim == 0) {
+        nc = g;
+        return;
+    }
+    const bool full = i < n_live;
+    double t = cs.dt_G;
+    if (!full) t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
+    bool vchg = false;
+    const int nl = flight<P>(cs, g - cs.cell0, xr, v, t, full, vchg);
+    if (nl == -2) {
+        to_body = true;
+    } else if (nl >= 0) {
+        nc = cs.cell0 + nl;
+        for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
+        if (vchg)
+            for (int a = 0; a < 3; ++a) if (a < cs.dim) S.vel[a][i] = v[a];
+    }
+}
+
+// Every particle: straight flight with specular / open walls, new cell and slot recorded.
 // Particles whose path may meet the body go to a worklist for k_move_body.
 template <typename P>
 __global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
@@ -582,37 +607,30 @@ __global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < n_total; base += stride) {
         const int i = base + threadIdx.x;
-        const bool valid = i < n_total;
-        int nc = -1, cid = 0;
-        bool to_body = false;
+        const bool valid = i < n_total;       // the valid lanes of a wave are a prefix
+        int g = 0;
+        P xr[3] = {(P)0, (P)0, (P)0}, v[3] = {(P)0, (P)0, (P)0};
         if (valid) {
-            // state loads first (guarded by the batch's largest dimension, not the case's),
-            // so they overlap the case lookup
-            const int g = S.cell[i];
-            P xr[3] = {(P)0, (P)0, (P)0}, v[3];
+            // state loads first (guarded by the batch's largest dimension, not the case's)
+            g = S.cell[i];
 #pragma unroll
             for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
 #pragma unroll
             for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+        }
+        // Cases are contiguous in the particle array (the sorted live part, then the injected
+        // particles case by case), so a wave nearly always lies in the case of its first
+        // particle: that case is then found once, with uniform loads, for the whole wave.
+        const int cu = case_of(C, __builtin_amdgcn_readfirstlane(g));
+        const CaseDev &csu = case_const(C, cu);
+        const bool one = __all(!valid || (g >= csu.cell0 && g < csu.cell0 + csu.ncells));
+        int nc = -1, cid = cu;
+        bool to_body = false;
+        if (one) {
+            if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, nc, to_body);
+        } else if (valid) {
             cid = case_of(C, g);
-            const CaseDev &cs = C.cases[cid];
-            if (cs.dim == 0) {
-                nc = g;
-            } else {
-                const bool full = i < n_live;
-                double t = cs.dt_G;
-                if (!full) t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
-                bool vchg = false;
-                const int nl = flight<P>(cs, g - cs.cell0, xr, v, t, full, vchg);
-                if (nl == -2) {
-                    to_body = true;
-                } else if (nl >= 0) {
-                    nc = cs.cell0 + nl;
-                    for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
-                    if (vchg)
-                        for (int a = 0; a < 3; ++a) if (a < cs.dim) S.vel[a][i] = v[a];
-                }
-            }
+            move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, nc, to_body);
         }
         // worklist of body candidates
         {
@@ -1098,9 +1116,9 @@ __device__ __forceinline__ TileRef tile_ref(const Ctx &C, int t, int ntiles)
 {
     TileRef r{0, 0, 0};
     if (t < ntiles) {
-        r.cb = C.tile_cell[t];
-        r.ce = C.tile_cell[t + 1];
-        r.ci = C.tile_case[t];
+        r.cb = const_read(C.tile_cell + t);
+        r.ce = const_read(C.tile_cell + t + 1);
+        r.ci = const_read(C.tile_case + t);
     }
     return r;
 }
@@ -1201,7 +1219,7 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
             if (lane == 0) raise_error(G, kErrState);
             return;
         }
-        const int dim = C.cases[cur.ci].dim;
+        const int dim = case_const(C, cur.ci).dim;
         // owner lane = local cell
         const bool own = lane < ncl;
         const int g = cb + lane;
@@ -1449,7 +1467,7 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
             skipped[0] = 0;
             my_case = cid;
         }
-        const CaseDev &cs = C.cases[cid];
+        const CaseDev &cs = case_const(C, cid);
         const int kb = ncl == 1 ? 6 : 6 - (32 - __clz(ncl - 1));
         const int kk = 1 << kb;
         const int gc = lane >> kb, sub = lane & (kk - 1);
@@ -1682,7 +1700,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             my_case = cid;
         }
         // the tile's case (uniform): RNG key, first cell, sampling on or off
-        const CaseDev &cs = C.cases[cid];
+        const CaseDev &cs = case_const(C, cid);
         const uint32_t sd0 = cs.seed_lo, sd1 = cs.seed_hi;
         const int lc0 = cb - cs.cell0;
         const bool samp_on = step >= cs.n_steady;
@@ -2083,15 +2101,21 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
 #pragma unroll
             for (int j = 0; j < 3; ++j) nrel[j] = group_sum_iv(nrel[j], kb, kbmax);
         }
-        if (lead) {
-            if (sampling) {
-                // one add per cell and step (no other thread touches the cell's sums), so the
-                // result equals a load-add-store; the atomic form needs no return value
-                double *A = &C.acc[13 * (size_t)g];
-                unsafeAtomicAdd(&A[0], (double)nn);
+        if (sampling) {
+            // one add per cell and step (no other thread touches the cell's sums), so the
+            // result equals a load-add-store; the atomic form needs no return value.  Every
+            // lane of the group holds the same sums: lane j adds sum j, so a cell's 13 adds
+            // leave in one vector instruction when the group has 16 lanes or more
+            double *A = &C.acc[13 * (size_t)g];
+            for (int j = sub; j < 13; j += kk) {
+                double v = (double)nn;
 #pragma unroll
-                for (int j = 0; j < 12; ++j) unsafeAtomicAdd(&A[1 + j], sm[j]);
+                for (int q = 0; q < 12; ++q)
+                    if (j == q + 1) v = sm[q];
+                unsafeAtomicAdd(&A[j], v);
             }
+        }
+        if (lead) {
             if (tracing) {
                 TraceDev *tr = &C.trace[g];
                 tr->post_sum[0] = sm[0];
