@@ -17,8 +17,12 @@
  *    outlive the sim.  The sim handle owns host metadata only.
  *  - Streams: all GPU work of a sim is enqueued on the hipStream_t given at init
  *    (passed as void*; NULL = the default stream).  hs_step() does not synchronise.
- *    Calls that return data (hs_sample_moments, hs_export_state, hs_last_trace,
- *    hs_counters, hs_sync) synchronise that stream.
+ *    Within a step the dense-cell kernel runs on a second stream that the sim creates
+ *    (default priority, non-blocking) and destroys: it is forked from the given stream
+ *    after the scatter and joined back into it before the step ends, so work queued later on
+ *    the given stream, or a graph captured from it, sees the whole step.  Calls that
+ *    return data (hs_sample_moments, hs_export_state, hs_last_trace, hs_counters, hs_sync)
+ *    synchronise the given stream.
  *  - Errors: every call returns an hs_status.  Argument errors return at once and
  *    change nothing.  Faults found on the device (capacity overflow, a cell denser than
  *    the per-cell limit, a non-finite moment, inconsistent state) are latched in a

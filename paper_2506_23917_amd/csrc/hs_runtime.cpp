@@ -278,6 +278,10 @@ struct hs_sim {
     hs_precision prec;
     uint32_t flags;
     hipStream_t stream;
+    // second stream of the step: the dense-cell kernel runs on it beside the scalar and tile
+    // kernels, forked from and joined back into `stream` by the two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char *ws;
     size_t ws_bytes;
     Plan plan;
@@ -351,41 +355,49 @@ void enqueue_step(hs_sim *s, int timed)
         ev = &s->events.back();
         for (int k = 0; k < HS_NUM_KERNELS; ++k) ev->b[k] = ev->e[k] = nullptr;
     }
-    auto mark = [&](int k, bool begin) {
+    auto mark = [&](int k, bool begin, hipStream_t on) {
         if (!ev || !((s->timing >> k) & 1u)) return;
         hipEvent_t &e = begin ? ev->b[k] : ev->e[k];
         if (hipEventCreate(&e) != hipSuccess) { e = nullptr; return; }
-        (void)hipEventRecord(e, s->stream);
+        (void)hipEventRecord(e, on);
     };
-    mark(HS_KERNEL_STEP, true);
+    const hipStream_t ms = s->stream;
+    mark(HS_KERNEL_STEP, true, ms);
     if (s->plan.any_spatial) {
-        mark(HS_KERNEL_INJECT, true);
+        mark(HS_KERNEL_INJECT, true, ms);
         Launch::inject(c, st);
-        mark(HS_KERNEL_INJECT, false);
-        mark(HS_KERNEL_MOVE, true);
+        mark(HS_KERNEL_INJECT, false, ms);
+        mark(HS_KERNEL_MOVE, true, ms);
         Launch::move_count(c, st, s->plan.any_body ? 1 : 0);
-        mark(HS_KERNEL_MOVE, false);
-        mark(HS_KERNEL_SCAN, true);
+        mark(HS_KERNEL_MOVE, false, ms);
+        mark(HS_KERNEL_SCAN, true, ms);
         Launch::scan_cells(c, st, 1);
-        mark(HS_KERNEL_SCAN, false);
-        mark(HS_KERNEL_SCATTER, true);
+        mark(HS_KERNEL_SCAN, false, ms);
+        mark(HS_KERNEL_SCATTER, true, ms);
         Launch::scatter(c, st);
-        mark(HS_KERNEL_SCATTER, false);
+        mark(HS_KERNEL_SCATTER, false, ms);
     }
-    mark(HS_KERNEL_GATHER, true);
+    // cells denser than the tile limit: their kernel sorts, gathers and collides its cells
+    // alone (from the scatter's permutation), sharing no cell with the gather, scalar and
+    // tile kernels, so it runs on the side stream while they run
+    (void)hipEventRecord(s->ev_fork, ms);
+    (void)hipStreamWaitEvent(s->side, s->ev_fork, 0);
+    mark(HS_KERNEL_DENSE, true, s->side);
+    Launch::dense(c, (void *)s->side);
+    mark(HS_KERNEL_DENSE, false, s->side);
+    (void)hipEventRecord(s->ev_join, s->side);
+    mark(HS_KERNEL_GATHER, true, ms);
     Launch::gather(c, st);
-    mark(HS_KERNEL_GATHER, false);
-    mark(HS_KERNEL_SCALARS, true);
+    mark(HS_KERNEL_GATHER, false, ms);
+    mark(HS_KERNEL_SCALARS, true, ms);
     Launch::scalars(c, st);
-    mark(HS_KERNEL_SCALARS, false);
-    mark(HS_KERNEL_COLLIDE, true);
+    mark(HS_KERNEL_SCALARS, false, ms);
+    mark(HS_KERNEL_COLLIDE, true, ms);
     Launch::collide(c, st);
-    mark(HS_KERNEL_COLLIDE, false);
-    mark(HS_KERNEL_DENSE, true);
-    Launch::dense(c, st);
-    mark(HS_KERNEL_DENSE, false);
+    mark(HS_KERNEL_COLLIDE, false, ms);
+    (void)hipStreamWaitEvent(ms, s->ev_join, 0);
     Launch::finish_step(c, st);
-    mark(HS_KERNEL_STEP, false);
+    mark(HS_KERNEL_STEP, false, ms);
 }
 
 }  // namespace
@@ -498,7 +510,12 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     if (!s->plan.any_spatial) launch_build_big(ci, s->stream);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+        if (s->side) (void)hipStreamDestroy(s->side);
         delete s;
         return HS_ERR_DEVICE;
     }
@@ -942,9 +959,13 @@ void hs_destroy(hs_sim *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    if (s->side) (void)hipStreamSynchronize(s->side);
     destroy_events(s);
     if (s->gexec) hipGraphExecDestroy(s->gexec);
     if (s->graph) hipGraphDestroy(s->graph);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->side) (void)hipStreamDestroy(s->side);
     delete s;
 }
 
