@@ -1483,17 +1483,41 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
         }
         const bool work = own && n <= D;
         const int nn = work ? n : 0;
+        // nothing to do in a tile without particles of its own (unless trace records are kept)
+        if (!tracing && !__any(nn > 0)) continue;
         const bool lead = work && sub == 0;
         const P *vx = Dd.vel[0] + start, *vy = Dd.vel[1] + start, *vz = Dd.vel[2] + start;
 
+        // A lane's particles are i = sub, sub + kk, ...; they are read kU at a time with all
+        // loads in flight before the first is used, and summed in that order.
+        constexpr int kU = 2;
+        auto load_u = [&](int i0, P (&bx)[kU], P (&by)[kU], P (&bz)[kU]) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * kk;
+                bx[u] = by[u] = bz[u] = (P)0;
+                if (i < nn) {
+                    bx[u] = vx[i];
+                    by[u] = vy[i];
+                    bz[u] = vz[i];
+                }
+            }
+        };
         // Eq. 31: sums of c and |c|^2
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int i = sub; i < nn; i += kk) {
-            const double x = (double)vx[i], y = (double)vy[i], z = (double)vz[i];
-            s1[0] = s1[0] + x;
-            s1[1] = s1[1] + y;
-            s1[2] = s1[2] + z;
-            s1[3] = s1[3] + (x * x + y * y + z * z);
+        for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+            P bx[kU], by[kU], bz[kU];
+            load_u(i0, bx, by, bz);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (i0 + u * kk < nn) {
+                    const double x = (double)bx[u], y = (double)by[u], z = (double)bz[u];
+                    s1[0] = s1[0] + x;
+                    s1[1] = s1[1] + y;
+                    s1[2] = s1[2] + z;
+                    s1[3] = s1[3] + (x * x + y * y + z * z);
+                }
+            }
         }
         group_sum<4>(s1, kb);
         double U[3] = {0.0, 0.0, 0.0};
@@ -1514,24 +1538,38 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
                         uf[a] = (float)U[a];
                         ud[a] = (float)(U[a] - (double)uf[a]);
                     }
-                    for (int i = sub; i < nn; i += kk) {
-                        const float cx = (vx[i] - uf[0]) - ud[0];
-                        const float cy = (vy[i] - uf[1]) - ud[1];
-                        const float cz = (vz[i] - uf[2]) - ud[2];
-                        const float c2 = cx * cx + cy * cy + cz * cz;
-                        s2[0] = s2[0] + (double)c2;
-                        s2[1] = s2[1] + (double)(c2 * cx);
-                        s2[2] = s2[2] + (double)(c2 * cy);
-                        s2[3] = s2[3] + (double)(c2 * cz);
+                    for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+                        P bx[kU], by[kU], bz[kU];
+                        load_u(i0, bx, by, bz);
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            if (i0 + u * kk < nn) {
+                                const float cx = (bx[u] - uf[0]) - ud[0];
+                                const float cy = (by[u] - uf[1]) - ud[1];
+                                const float cz = (bz[u] - uf[2]) - ud[2];
+                                const float c2 = cx * cx + cy * cy + cz * cz;
+                                s2[0] = s2[0] + (double)c2;
+                                s2[1] = s2[1] + (double)(c2 * cx);
+                                s2[2] = s2[2] + (double)(c2 * cy);
+                                s2[3] = s2[3] + (double)(c2 * cz);
+                            }
+                        }
                     }
                 } else {
-                    for (int i = sub; i < nn; i += kk) {
-                        const double cx = vx[i] - U[0], cy = vy[i] - U[1], cz = vz[i] - U[2];
-                        const double c2 = cx * cx + cy * cy + cz * cz;
-                        s2[0] = s2[0] + c2;
-                        s2[1] = s2[1] + c2 * cx;
-                        s2[2] = s2[2] + c2 * cy;
-                        s2[3] = s2[3] + c2 * cz;
+                    for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+                        P bx[kU], by[kU], bz[kU];
+                        load_u(i0, bx, by, bz);
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            if (i0 + u * kk < nn) {
+                                const double cx = bx[u] - U[0], cy = by[u] - U[1], cz = bz[u] - U[2];
+                                const double c2 = cx * cx + cy * cy + cz * cz;
+                                s2[0] = s2[0] + c2;
+                                s2[1] = s2[1] + c2 * cx;
+                                s2[2] = s2[2] + c2 * cy;
+                                s2[3] = s2[3] + c2 * cz;
+                            }
+                        }
                     }
                 }
             }
@@ -1598,23 +1636,25 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
             else raise_error(G, kErrNumeric);
         }
         if (lead) {
-            double *R = C.cellrec + (size_t)kRecLen * g;
-            R[kRecU + 0] = U[0];
-            R[kRecU + 1] = U[1];
-            R[kRecU + 2] = U[2];
-            R[kRecT] = T;
-            R[kRecPr] = pr;
-            R[kRecScm] = scm;
-            R[kRecNcol] = (double)ncol;
-            R[kRecAct] = active ? 1.0 : 0.0;
-            if (pr > 0.0) {
-                R[kRecPar + 0] = Q[0];
-                R[kRecPar + 1] = Q[1];
-                R[kRecPar + 2] = Q[2];
-                R[kRecPar + 3] = p;
-                R[kRecPar + 4] = gas.R * T;
-                R[kRecPar + 5] = sqrt(2.0 * gas.R * T);
-                R[kRecPar + 6] = a_max;
+            if (nn > 0) {                 // the tile kernel reads no record of an empty cell
+                double *R = C.cellrec + (size_t)kRecLen * g;
+                R[kRecU + 0] = U[0];
+                R[kRecU + 1] = U[1];
+                R[kRecU + 2] = U[2];
+                R[kRecT] = T;
+                R[kRecPr] = pr;
+                R[kRecScm] = scm;
+                R[kRecNcol] = (double)ncol;
+                R[kRecAct] = active ? 1.0 : 0.0;
+                if (pr > 0.0) {
+                    R[kRecPar + 0] = Q[0];
+                    R[kRecPar + 1] = Q[1];
+                    R[kRecPar + 2] = Q[2];
+                    R[kRecPar + 3] = p;
+                    R[kRecPar + 4] = gas.R * T;
+                    R[kRecPar + 5] = sqrt(2.0 * gas.R * T);
+                    R[kRecPar + 6] = a_max;
+                }
             }
             if (tr) {
                 *tr = TraceDev{};
@@ -1715,6 +1755,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         }
         const int incl = wave_incl_scan(nn0);
         const int np = __shfl(incl, 63, 64);
+        if (np == 0) continue;           // empty cells only (or dense ones, served elsewhere)
         if (lane < ncl) c_off[lane] = incl - nn0;
         if (lane == 0) c_off[ncl] = np;
         team_sync<64>();

@@ -4,6 +4,10 @@
         the bench workload (2-D Ma 10 cylinder, 800 x 600, FP32-mixed): `warmup` steps to
         develop the flow, then `steps` more with sampling on (filter the counters to the
         last launches of the kernel of interest)
+    python -m paper_2506_23917_amd.profile_workload --workload jets --warmup 2000 --steps 200
+        the ragged batch of 32 planar jets (one launch per kernel for the whole batch, the
+        step replayed from a captured graph); `--workload sphere` the 3-D Ma 10 sphere
+        (240 x 160 x 160).  Both print particle-steps/s of the timed steps.
     python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
         a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
         counters to bytes
@@ -25,6 +29,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere"])
     args = ap.parse_args()
     import torch
     if args.copy_mib:
@@ -37,11 +42,18 @@ def main():
         torch.cuda.synchronize()
         print("copied %d MiB x 3" % args.copy_mib, flush=True)
         return
+    import time
     import workloads as W
     from paper_2506_23917_amd.hs import Sim
-    case = W.cylinder_2d()
-    case["n_steady"] = args.warmup
-    sim = Sim(W.gas(), case, precision=args.precision, device="cuda:0")
+    if args.workload == "jets":
+        cases = W.jets_2d()
+        sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0", graph=True)
+    else:
+        case = W.cylinder_2d() if args.workload == "cylinder" else W.sphere_3d()
+        case["n_steady"] = args.warmup
+        cases = [case]
+        sim = Sim(W.gas(), case, precision=args.precision, device="cuda:0")
+    nc = len(cases)
     done = 0
     while done < args.warmup:
         k = min(500, args.warmup - done)
@@ -49,9 +61,16 @@ def main():
         sim.sync()
         done += k
         print("warmup %d / %d" % (done, args.warmup), flush=True)
+    n0 = sum(sim.num_particles(c) for c in range(nc))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     sim.step(args.steps)
     sim.sync()
-    print("timed steps %d, particles %d" % (args.steps, sim.num_particles(0)), flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n1 = sum(sim.num_particles(c) for c in range(nc))
+    print("timed steps %d, particles %d, %.4f ms/step, %.4e particle-steps/s" %
+          (args.steps, n1, 1e3 * dt / max(args.steps, 1), 0.5 * (n0 + n1) * args.steps / dt), flush=True)
 
 
 if __name__ == "__main__":
