@@ -43,6 +43,7 @@ typedef struct {
     double *dt_over_tau;
     int64_t ncells;
     double *vol, *sigc_max, *acc, *dt_cell;
+    double *surf;                 /* 7 sums per body surface element */
     int64_t n_samples;
     int64_t np, cap;
     double *x, *v;
@@ -366,7 +367,7 @@ static void free_case(ocase *c)
     free(c->vol); free(c->sigc_max); free(c->acc); free(c->dt_cell);
     free(c->x); free(c->v); free(c->cell); free(c->id);
     free(c->x2); free(c->v2); free(c->cell2); free(c->id2); free(c->count);
-    free(c->faces); free(c->trace);
+    free(c->faces); free(c->trace); free(c->surf);
 }
 
 static int alloc_particles(ocase *c, int64_t cap)
@@ -474,6 +475,11 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         oc->trace = calloc((size_t)nc, sizeof(hso_trace));
         if (!oc->vol || !oc->sigc_max || !oc->acc || !oc->dt_cell || !oc->count || !oc->trace)
             e = HSO_ECAP;
+        if (c->n_surf < 0 || (c->n_surf > 0 && c->body == HSO_BODY_NONE)) e = HSO_EARG;
+        if (!e && c->n_surf > 0) {
+            oc->surf = calloc((size_t)c->n_surf * 7, sizeof(double));
+            if (!oc->surf) e = HSO_ECAP;
+        }
         if (!e) e = alloc_particles(oc, c->capacity);
         if (!e) e = build_faces(gas, oc);
         if (e) { hso_destroy(s); return e; }
@@ -540,6 +546,7 @@ static int init_case(const hso_gas *g, ocase *oc)
     oc->n_samples = 0;
     memset(&oc->cnt, 0, sizeof(oc->cnt));
     memset(oc->acc, 0, sizeof(double) * 13 * (size_t)oc->ncells);
+    if (oc->surf) memset(oc->surf, 0, sizeof(double) * 7 * (size_t)c->n_surf);
     for (int64_t k = 0; k < oc->ncells; ++k) {
         const hso_state *st = region_of(c, k);
         if (!st || oc->vol[k] <= 0.0 || st->n <= 0.0) continue;
@@ -718,6 +725,51 @@ static void diffuse_reflect(const hso_case *c, double R, const double xh[3], con
     for (int k = 0; k < 3; ++k) v[k] = cn * nrm[k] + cs * t1[k] + ct * t2[k];
 }
 
+/* Outward unit normal of the body at wall point xh, polar angle th from the upstream
+ * stagnation direction s = -x, and the unit tangent of growing th,
+ * t = (n cos th - s) / sin th (zero at the poles). */
+static void body_frame(const hso_case *c, const double xh[3], double nrm[3], double *th, double tan[3])
+{
+    int na = body_axes(c);
+    double len = 0.0;
+    for (int k = 0; k < 3; ++k) nrm[k] = 0.0;
+    for (int k = 0; k < na; ++k) { nrm[k] = xh[k] - c->body_c[k]; len = len + nrm[k] * nrm[k]; }
+    len = sqrt(len);
+    for (int k = 0; k < na; ++k) nrm[k] = nrm[k] / len;
+    double ct = -nrm[0];
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    *th = acos(ct);
+    double st = sin(*th);
+    double sdir[3] = { -1.0, 0.0, 0.0 };
+    for (int k = 0; k < 3; ++k) tan[k] = st > 0.0 ? (nrm[k] * ct - sdir[k]) / st : 0.0;
+}
+
+/* Step (5) on the wall: the momentum and energy one diffuse reflection gives the body,
+ * added to the surface element of the hit point (sampled steps only). */
+static void surface_hit(const hso_gas *g, ocase *oc, const double xh[3], const double vin[3],
+                        const double vout[3])
+{
+    const hso_case *c = &oc->p;
+    double nrm[3], tan[3], th;
+    body_frame(c, xh, nrm, &th, tan);
+    int k = (int)floor(th / PI * (double)c->n_surf);
+    if (k < 0) k = 0;
+    if (k > c->n_surf - 1) k = c->n_surf - 1;
+    double w = g->m * c->F_N, dP[3], e_in = 0.0, e_out = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        dP[a] = w * (vin[a] - vout[a]);
+        e_in = e_in + vin[a] * vin[a];
+        e_out = e_out + vout[a] * vout[a];
+    }
+    double *S = &oc->surf[7 * k];
+    S[0] = S[0] + 1.0;
+    S[1] = S[1] + (dP[0] * nrm[0] + dP[1] * nrm[1] + dP[2] * nrm[2]);
+    S[2] = S[2] + (dP[0] * tan[0] + dP[1] * tan[1] + dP[2] * tan[2]);
+    S[3] = S[3] + 0.5 * w * (e_in - e_out);
+    for (int a = 0; a < 3; ++a) S[4 + a] = S[4 + a] + dP[a];
+}
+
 /* Free transport, Eq. 4: x <- x + c t, with the body's diffuse wall, specular domain
  * walls, and removal through open faces (Step (2)).  Returns the new case-local cell, or
  * -1 when the particle has left the domain. */
@@ -737,7 +789,9 @@ static int32_t move_particle(const hso_gas *g, ocase *oc, double *x, double *v, 
             if (b == MAX_BOUNCE) { oc->cnt.bounce_cap++; t = 0.0; break; }
             uint32_t w[4];
             hso_draw(c->seed, ST_PARTICLE, (uint64_t)id, st, (uint32_t)(DRAW_BOUNCE + b), w);
+            double vin[3] = { v[0], v[1], v[2] };
             diffuse_reflect(c, R, x, w, v);
+            if (oc->surf && oc->step >= c->n_steady) surface_hit(g, oc, x, vin, v);
         }
     }
     for (int k = 0; k < c->dim; ++k) x[k] = x[k] + v[k] * t;
@@ -1221,5 +1275,89 @@ int hso_get_counters(const hso_sim *s, int c, hso_counters *out)
 {
     if (!s || c < 0 || c >= s->n_cases) return HSO_EARG;
     *out = s->cases[c].cnt;
+    return HSO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Body surface sampling: raw sums and Eq. 35-36 time averages                           */
+/* ------------------------------------------------------------------------------------ */
+
+int hso_get_surface(const hso_sim *s, int ci, double *sums7)
+{
+    if (!s || ci < 0 || ci >= s->n_cases || !sums7) return HSO_EARG;
+    const ocase *oc = &s->cases[ci];
+    if (!oc->surf) return HSO_EARG;
+    memcpy(sums7, oc->surf, sizeof(double) * 7 * (size_t)oc->p.n_surf);
+    return HSO_OK;
+}
+
+int hso_set_surface(hso_sim *s, int ci, const double *sums7)
+{
+    if (!s || ci < 0 || ci >= s->n_cases || !sums7) return HSO_EARG;
+    ocase *oc = &s->cases[ci];
+    if (!oc->surf) return HSO_EARG;
+    memcpy(oc->surf, sums7, sizeof(double) * 7 * (size_t)oc->p.n_surf);
+    return HSO_OK;
+}
+
+/* Element k spans polar angles [th_k, th_k+1), th_k = k pi / n_surf.  Its area: a
+ * cylinder's two strips 2 R (th_k+1 - th_k) times the axial length (the unit depth h_z of a
+ * 2-D case, nz h_z in 3-D); a sphere's zone 2 pi R^2 (cos th_k - cos th_k+1).  Over S
+ * sampled steps of dt_G: p = -sum dP.n / (A S dt), tau = sum dP.t / (A S dt),
+ * q = sum dE / (A S dt), force = sum dP / (S dt).  Eq. 35: C_p = (p - p_inf) / (rho U^2 / 2),
+ * C_h = q / (rho U^3 / 2) (and C_f = tau / (rho U^2 / 2)); Eq. 36: C_D, C_L = force along
+ * the freestream direction u / |u| and along (-u_y, u_x, 0) / |u|, over rho U^2 A_ref / 2 with
+ * A_ref = 2 R times the axial length (cylinder) or pi R^2 (sphere). */
+int hso_surface_sample(const hso_sim *s, int ci, double *elem8, double *body5, int64_t *n_samples)
+{
+    if (!s || ci < 0 || ci >= s->n_cases) return HSO_EARG;
+    const ocase *oc = &s->cases[ci];
+    const hso_case *c = &oc->p;
+    if (!oc->surf) return HSO_EARG;
+    if (n_samples) *n_samples = oc->n_samples;
+    int ns = c->n_surf;
+    double R = c->body_r;
+    double len = c->dim == 3 ? (double)c->nz * c->h[2] : c->h[2];
+    double time = (double)oc->n_samples * c->dt_G;
+    const hso_state *f = &c->inflow;
+    double U = sqrt(f->u[0] * f->u[0] + f->u[1] * f->u[1] + f->u[2] * f->u[2]);
+    double rho = f->n * s->gas.m, pinf = f->n * KB * f->T;
+    double qd = 0.5 * rho * U * U;
+    double aref = c->body == HSO_BODY_CYLINDER ? 2.0 * R * len : PI * R * R;
+    double F[3] = { 0.0, 0.0, 0.0 };
+    for (int k = 0; k < ns; ++k) {
+        const double *S = &oc->surf[7 * k];
+        double t0 = PI * (double)k / (double)ns, t1 = PI * (double)(k + 1) / (double)ns;
+        double area = c->body == HSO_BODY_CYLINDER ? 2.0 * R * (t1 - t0) * len
+                                                  : 2.0 * PI * R * R * (cos(t0) - cos(t1));
+        double p = 0.0, tau = 0.0, q = 0.0;
+        if (time > 0.0) {
+            p = -S[1] / (area * time);
+            tau = S[2] / (area * time);
+            q = S[3] / (area * time);
+            for (int a = 0; a < 3; ++a) F[a] = F[a] + S[4 + a] / time;
+        }
+        if (elem8) {
+            double *E = &elem8[8 * k];
+            E[0] = 0.5 * (t0 + t1);
+            E[1] = area;
+            E[2] = p;
+            E[3] = tau;
+            E[4] = q;
+            E[5] = qd > 0.0 ? (p - pinf) / qd : 0.0;
+            E[6] = qd > 0.0 ? tau / qd : 0.0;
+            E[7] = qd > 0.0 ? q / (qd * U) : 0.0;
+        }
+    }
+    if (body5) {
+        for (int a = 0; a < 3; ++a) body5[a] = F[a];
+        double drag = 0.0, lift = 0.0;
+        if (U > 0.0) {
+            drag = (F[0] * f->u[0] + F[1] * f->u[1] + F[2] * f->u[2]) / U;
+            lift = (-F[0] * f->u[1] + F[1] * f->u[0]) / U;
+        }
+        body5[3] = qd > 0.0 ? drag / (qd * aref) : 0.0;
+        body5[4] = qd > 0.0 ? lift / (qd * aref) : 0.0;
+    }
     return HSO_OK;
 }

@@ -50,6 +50,7 @@ typedef struct {
     const double *dt_over_tau;       /* dim 0 only: per-cell dt_G / tau_0              */
     uint64_t seed;
     int64_t n_steady, capacity;
+    int32_t n_surf;                  /* body surface elements sampled (0: none)        */
 } hso_case;
 
 typedef struct hso_sim hso_sim;
@@ -89,6 +90,19 @@ int  hso_get_cells(const hso_sim *s, int c, double *vol, double *sigc_max, doubl
 int  hso_set_cells(hso_sim *s, int c, const double *sigc_max, const double *acc13,
                    int64_t n_samples);
 int  hso_get_trace(const hso_sim *s, int c, hso_trace *out);
+/* Body surface sampling (Step (5) on the wall; the quantities of Eq. 35-36).  Element k
+ * of the n_surf elements holds the wall points whose polar angle from the upstream
+ * stagnation direction -x lies in [k, k+1) pi / n_surf (a cylinder's upper and lower
+ * halves together).  Raw sums per element, 7 doubles, over the sampled steps: reflections,
+ * sum dP.n, sum dP.t, sum dE, sum dP (x, y, z); dP = m F_N (c_in - c_out) is the momentum
+ * a reflection gives the wall, dE = m F_N (|c_in|^2 - |c_out|^2) / 2 its energy, n the
+ * outward normal and t the unit tangent of growing polar angle at the hit point.
+ * hso_surface_sample turns them into time averages: per element 8 doubles (mid angle,
+ * area, p, tau, q, C_p, C_f, C_h) and per case 5 (force x, y, z per unit time, C_D, C_L),
+ * with the inflow state as freestream (coefficients 0 when it has no speed). */
+int  hso_get_surface(const hso_sim *s, int c, double *sums7);
+int  hso_set_surface(hso_sim *s, int c, const double *sums7);
+int  hso_surface_sample(const hso_sim *s, int c, double *elem8, double *body5, int64_t *n_samples);
 int  hso_get_counters(const hso_sim *s, int c, hso_counters *out);
 int64_t hso_num_cells(const hso_sim *s, int c);
 int64_t hso_num_faces(const hso_sim *s, int c);

@@ -56,7 +56,7 @@ class Case(C.Structure):
                 ("region_box", C.POINTER(C.c_double)), ("region_state", C.POINTER(State)),
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
-                ("n_steady", C.c_int64), ("capacity", C.c_int64)]
+                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32)]
 
 
 class Trace(C.Structure):
@@ -98,6 +98,9 @@ def lib():
         L.hso_step.argtypes = [C.c_void_p, C.c_int64]
         L.hso_sample_moments.argtypes = [C.c_void_p, C.c_int, C.c_int, P(C.c_double), P(C.c_double),
                                          P(C.c_double), P(C.c_double), P(C.c_int64)]
+        L.hso_get_surface.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
+        L.hso_set_surface.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
+        L.hso_surface_sample.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int64)]
         L.hso_num_particles.argtypes = [C.c_void_p, C.c_int]
         L.hso_num_particles.restype = C.c_int64
         L.hso_num_cells.argtypes = [C.c_void_p, C.c_int]
@@ -180,6 +183,7 @@ class _CaseHolder:
         c.seed = int(d["seed"])
         c.n_steady = int(d["n_steady"])
         c.capacity = int(d["capacity"])
+        c.n_surf = int(d.get("n_surf", 0))
         self.c = c
 
 
@@ -278,6 +282,27 @@ class Oracle:
             acc = np.ascontiguousarray(acc, dtype=np.float64)
             ap = _dp(acc)
         _check(self.L.hso_set_cells(self.h, c, sp, ap, int(n_samples)), "set_cells")
+
+    def surface_sums(self, c=0) -> np.ndarray:
+        """Raw wall sums, (n_surf, 7): reflections, sum dP.n, sum dP.t, sum dE, sum dP."""
+        out = np.zeros((int(self.case_dicts[c].get("n_surf", 0)), 7))
+        _check(self.L.hso_get_surface(self.h, c, _dp(out)), "get_surface")
+        return out
+
+    def set_surface_sums(self, c, sums):
+        sums = np.ascontiguousarray(sums, dtype=np.float64)
+        _check(self.L.hso_set_surface(self.h, c, _dp(sums)), "set_surface")
+
+    def surface_sample(self, c=0) -> dict:
+        """Eq. 35-36 time averages of the wall sums: per element theta (mid), area, p, tau,
+        q, Cp, Cf, Ch; per case the force per unit time and CD, CL."""
+        ns = int(self.case_dicts[c].get("n_surf", 0))
+        e, b = np.zeros((ns, 8)), np.zeros(5)
+        k = C.c_int64()
+        _check(self.L.hso_surface_sample(self.h, c, _dp(e), _dp(b), C.byref(k)), "surface_sample")
+        out = {n: e[:, i].copy() for i, n in enumerate(("theta", "area", "p", "tau", "q", "Cp", "Cf", "Ch"))}
+        out.update(force=b[:3].copy(), CD=float(b[3]), CL=float(b[4]), n_samples=k.value)
+        return out
 
     def trace(self, c=0) -> np.ndarray:
         out = np.zeros(self.num_cells(c), dtype=TRACE_DTYPE)

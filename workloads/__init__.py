@@ -55,7 +55,7 @@ def _case(**kw):
                 slot_lo=(0.0, 0.0, 0.0), slot_hi=(0.0, 0.0, 0.0),
                 body="none", body_c=(0.0, 0.0, 0.0), body_r=0.0, body_T=0.0,
                 regions=[], F_N=1.0, dt_G=0.0, T_sigma=273.0, dt_over_tau=None,
-                seed=1, n_steady=1 << 40, capacity=0)
+                seed=1, n_steady=1 << 40, capacity=0, n_surf=0)
     base.update(kw)
     return base
 
@@ -115,9 +115,10 @@ def relax_0d_state(case, ppc=1000, tx_over_t=1.5, skew=0.05, state_seed=11):
     return v.reshape(-1, 3).copy(), cell, ids
 
 
-def cylinder_2d(nx=800, ny=600, ppc=30, seed=1, n_steady=10000, cap_factor=1.6):
+def cylinder_2d(nx=800, ny=600, ppc=30, seed=1, n_steady=10000, cap_factor=1.6, n_surf=90):
     """Ma 10 argon flow over a cylinder of diameter D = 1 m at (2.5, 3) in an 8 x 6 m box;
-    diffuse wall at 500 K; freestream inflow on -x, -y, +y; vacuum outflow on +x."""
+    diffuse wall at 500 K; freestream inflow on -x, -y, +y; vacuum outflow on +x; the wall
+    sampled in n_surf elements of polar angle (2 degrees each by default)."""
     h = 8.0 / nx
     assert abs(6.0 / ny - h) < 1e-12
     fn = N_INF * h * h / ppc
@@ -127,12 +128,13 @@ def cylinder_2d(nx=800, ny=600, ppc=30, seed=1, n_steady=10000, cap_factor=1.6):
                  inflow=st, body="cylinder", body_c=(2.5, 3.0, 0.0), body_r=0.5, body_T=500.0,
                  regions=[((0.0, 0.0, 0.0, 8.0, 6.0, 1.0), st)], F_N=fn,
                  dt_G=h / U_PLUS_A_INF, T_sigma=T_STAG, seed=seed, n_steady=n_steady,
-                 capacity=int(nx * ny * ppc * cap_factor) + 4096)
+                 capacity=int(nx * ny * ppc * cap_factor) + 4096, n_surf=n_surf)
 
 
-def sphere_3d(nx=240, ny=160, nz=160, ppc=15, seed=1, n_steady=5000, cap_factor=1.6):
+def sphere_3d(nx=240, ny=160, nz=160, ppc=15, seed=1, n_steady=5000, cap_factor=1.6, n_surf=45):
     """Ma 10 argon flow over a sphere of diameter D = 1 m at (2, 2, 2) in a 6 x 4 x 4 m
-    box; diffuse wall at 500 K; inflow on -x and the four lateral faces; outflow +x."""
+    box; diffuse wall at 500 K; inflow on -x and the four lateral faces; outflow +x; the
+    wall sampled in n_surf zones of polar angle (4 degrees each by default)."""
     h = 6.0 / nx
     assert abs(4.0 / ny - h) < 1e-12 and abs(4.0 / nz - h) < 1e-12
     fn = N_INF * h ** 3 / ppc
@@ -142,7 +144,29 @@ def sphere_3d(nx=240, ny=160, nz=160, ppc=15, seed=1, n_steady=5000, cap_factor=
                  inflow=st, body="sphere", body_c=(2.0, 2.0, 2.0), body_r=0.5, body_T=500.0,
                  regions=[((0.0, 0.0, 0.0, 6.0, 4.0, 4.0), st)], F_N=fn,
                  dt_G=h / U_PLUS_A_INF, T_sigma=T_STAG, seed=seed, n_steady=n_steady,
-                 capacity=int(nx * ny * nz * ppc * cap_factor) + 4096)
+                 capacity=int(nx * ny * nz * ppc * cap_factor) + 4096, n_surf=n_surf)
+
+
+def free_molecular_body(body="cylinder", s=1.0, T=300.0, T_w=500.0, n=1.0e13, cells=40, ppc=20,
+                        R=0.3, n_surf=12, seed=7):
+    """A drifting argon stream past a diffuse body at T_w with (practically) no collisions:
+    at n = 1e13 m^-3 the mean free path is ~130 m against a 2 m box, so the wall sees the
+    undisturbed freestream (free-molecular flow).  Box [0,2]^dim with `cells` cells per
+    axis, body of radius R at the centre, stream along +x with speed ratio
+    s = U / sqrt(2 k T / m); every face is a freestream face (it injects the stream's
+    one-way flux and removes leaving particles), so the box holds the undisturbed stream
+    everywhere; the box starts at the freestream state and every step is sampled."""
+    dim = 2 if body == "cylinder" else 3
+    h = 2.0 / cells
+    U = s * math.sqrt(2.0 * R_ARGON * T)
+    st = dict(n=n, u=(U, 0.0, 0.0), T=T)
+    vol = h ** dim
+    bc = ("inflow",) * 4 + (("inflow", "inflow") if dim == 3 else ("outflow", "outflow"))
+    return _case(dim=dim, nx=cells, ny=cells, nz=cells if dim == 3 else 1, h=(h, h, h if dim == 3 else 1.0),
+                 bc=bc, inflow=st, body=body, body_c=(1.0, 1.0, 1.0 if dim == 3 else 0.0), body_r=R,
+                 body_T=T_w, regions=[((0.0, 0.0, 0.0, 2.0, 2.0, 2.0 if dim == 3 else 1.0), st)],
+                 F_N=n * vol / ppc, dt_G=0.5 * h / (U + 3.0 * math.sqrt(R_ARGON * T)), T_sigma=T,
+                 seed=seed, n_steady=0, capacity=int(cells ** dim * ppc * 2) + 4096, n_surf=n_surf)
 
 
 def jets_2d(n_jets=32, grids=((200, 100), (400, 200), (800, 400)), batch_seed=2026,
