@@ -103,7 +103,9 @@ typedef struct {
  *  F_N: real molecules per particle; dt_G: global time step (fixed; Eq. 26 evaluated by
  *    the caller); T_sigma: temperature setting the initial (sigma_T c_r)_max at
  *    c* = 10 sqrt(k T_sigma / m); n_steady: first sampled step (Step 5); capacity: the
- *    largest number of particles the case may hold.  Arrays are copied at init. */
+ *    largest number of particles the case may hold.  Arrays are copied at init.
+ *  n_surf: number of body surface elements sampled from step n_steady on (0: none; needs
+ *    a body; at most 65536); see hs_surface_sample. */
 typedef struct {
     int32_t dim, nx, ny, nz;
     double lo[3], h[3];
@@ -119,6 +121,7 @@ typedef struct {
     const double *dt_over_tau;
     uint64_t seed;
     int64_t n_steady, capacity;
+    int32_t n_surf;
 } hs_case;
 
 typedef struct hs_sim hs_sim;
@@ -221,6 +224,33 @@ hs_status hs_autotune(hs_sim *sim, int steps_per_trial, hs_tune_report *report);
 /* Set the grid size (blocks per launch) of kernel group `which` by hand; 0 restores the
  * built-in default.  Results do not depend on it.  Drops a captured step graph. */
 hs_status hs_set_grid(hs_sim *sim, int which, int32_t blocks);
+
+/* Body surface sampling: the wall counterpart of Step (5), giving the quantities of Eq. 35
+ * (surface pressure and heat flux, with the shear stress the paper's surface plots show)
+ * and Eq. 36 (drag and lift coefficients).  Element k of the case's n_surf elements holds
+ * the wall points whose polar angle from the upstream stagnation direction -x lies in
+ * [k, k+1) pi / n_surf (a cylinder's upper and lower halves together).  Every diffuse
+ * reflection at the body during a sampled step (step >= n_steady) adds to its element:
+ * 1, dP.n, dP.t, dE and dP (x, y, z), with dP = m F_N (c_in - c_out) the momentum given to
+ * the wall, dE = m F_N (|c_in|^2 - |c_out|^2) / 2 the energy, n the outward normal and t
+ * the unit tangent of growing polar angle at the hit point.
+ *
+ * hs_surface_sums copies these raw sums of case_id, n_surf x 7 doubles, into host memory.
+ * hs_surface_sample gives their time averages over the S sampled steps of length dt_G:
+ * per element 8 doubles (mid angle, area A, p = -sum dP.n / (A S dt_G),
+ * tau = sum dP.t / (A S dt_G), q = sum dE / (A S dt_G), C_p = (p - p_inf) / (rho U^2 / 2),
+ * C_f = tau / (rho U^2 / 2), C_h = q / (rho U^3 / 2)), and 5 doubles for the body (force
+ * x, y, z = sum dP / (S dt_G); C_D and C_L = the force along u / |u| and along
+ * (-u_y, u_x, 0) / |u| over rho U^2 A_ref / 2).  The freestream is the case's inflow
+ * state (rho = n m, U = |u|, p_inf = n k T); coefficients are 0 when it has no speed.
+ * Areas: a cylinder's element is its two strips, 2 R dtheta times the axial length (h_z in
+ * 2-D, nz h_z in 3-D), with A_ref = 2 R times that length; a sphere's element is the zone
+ * 2 pi R^2 (cos theta_k - cos theta_k+1), A_ref = pi R^2.  Outputs are caller-owned host
+ * arrays (n_samples may be NULL).  Both synchronise the sim's stream.  Errors: HS_ERR_ARG
+ * for a bad case_id, a case without surface elements or a NULL array; device errors as
+ * hs_sync. */
+hs_status hs_surface_sums(hs_sim *sim, int case_id, double *sums7);
+hs_status hs_surface_sample(hs_sim *sim, int case_id, double *elem8, double *body5, int64_t *n_samples);
 
 /* Human-readable description of the last error (never NULL). */
 const char *hs_error_string(const hs_sim *sim);

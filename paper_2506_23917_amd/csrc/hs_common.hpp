@@ -50,6 +50,7 @@ struct CaseDev {
     double F_N, dt_G, L_cell, sigc0, tau0;
     double in_n, in_u[3], in_T;
     int32_t bb_lo[3], bb_hi[3];     // cell-index box around the body (1-cell margin)
+    int32_t surf0, n_surf;          // body surface elements: first of the batch, count
 };
 
 struct FaceDev {
@@ -113,6 +114,7 @@ struct Ctx {
     int32_t *count, *cstart;      // per cell; cstart has ncells_total + 1 entries
     double *sigc, *acc, *vol;     // (sigma c)_max, 13 sums per cell, fluid volume
     double *cellrec;              // 16 doubles per cell: scalars of the collision stage
+    double *surf;                 // 7 sums per body surface element (all cases)
     int32_t *face_cnt, *face_start;
     int32_t *scan_part;
     int32_t *big_list;
@@ -151,6 +153,7 @@ struct Launch {
 void launch_moments_now(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
 void launch_build_big(const Ctx &c, void *stream);
 void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
+void launch_surface_finalize(const Ctx &c, void *stream, int case_id, double *out);
 int cap_wave();
 int tile_width();
 int cap_block(int precision);

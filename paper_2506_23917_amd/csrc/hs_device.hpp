@@ -259,10 +259,51 @@ struct MoveStats {
 // flight in cell units in the storage precision, specular walls by mirroring, removal
 // through open faces.  Returns the new case-local cell or -1.
 // `id` is the particle id, or -1 to load it from *idsrc on the first body reflection.
+// Step (5) on the wall: the momentum dP = m F_N (c_in - c_out) and the energy
+// dE = m F_N (|c_in|^2 - |c_out|^2) / 2 one diffuse reflection gives the body, added to the
+// surface element of the hit point X.  Elements are bands of the polar angle th from the
+// upstream stagnation direction -x; dP is split on the outward normal n and on the unit
+// tangent of growing th, t = (n cos th + x) / sin th (zero at the poles).
+__device__ inline void surface_hit(const GasDev &gas, const CaseDev &cs, const double X[3], const double Vin[3],
+                                   const double Vout[3], double *surf)
+{
+    const int na = body_axes(cs);
+    double nr[3] = {0.0, 0.0, 0.0};
+    double len = 0.0;
+    for (int k = 0; k < 3; ++k) if (k < na) {
+        nr[k] = X[k] - cs.body_c[k];
+        len = len + nr[k] * nr[k];
+    }
+    len = sqrt(len);
+    for (int k = 0; k < 3; ++k) if (k < na) nr[k] = nr[k] / len;
+    double ct = -nr[0];
+    ct = ct > 1.0 ? 1.0 : (ct < -1.0 ? -1.0 : ct);
+    const double th = acos(ct);
+    const double st = sin(th);
+    const double sdir[3] = {-1.0, 0.0, 0.0};
+    double tg[3];
+    for (int k = 0; k < 3; ++k) tg[k] = st > 0.0 ? (nr[k] * ct - sdir[k]) / st : 0.0;
+    int e = (int)floor(th / kPi * (double)cs.n_surf);
+    e = e < 0 ? 0 : (e > cs.n_surf - 1 ? cs.n_surf - 1 : e);
+    const double w = gas.m * cs.F_N;
+    double dP[3], ein = 0.0, eout = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        dP[a] = w * (Vin[a] - Vout[a]);
+        ein = ein + Vin[a] * Vin[a];
+        eout = eout + Vout[a] * Vout[a];
+    }
+    double *S = surf + 7 * (size_t)(cs.surf0 + e);
+    unsafeAtomicAdd(&S[0], 1.0);
+    unsafeAtomicAdd(&S[1], dP[0] * nr[0] + dP[1] * nr[1] + dP[2] * nr[2]);
+    unsafeAtomicAdd(&S[2], dP[0] * tg[0] + dP[1] * tg[1] + dP[2] * tg[2]);
+    unsafeAtomicAdd(&S[3], 0.5 * w * (ein - eout));
+    for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&S[4 + a], dP[a]);
+}
+
 template <typename P>
 __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int local, P xr[3], P v[3],
                                     int64_t &id, const int64_t *idsrc, double t, bool full_step,
-                                    uint32_t step, MoveStats &ms)
+                                    uint32_t step, MoveStats &ms, double *surf)
 {
     const int dim = cs.dim;
     int ijk[3];
@@ -285,7 +326,9 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
                 break;
             }
             if (id < 0) id = *idsrc;
+            const double Vin[3] = {V[0], V[1], V[2]};
             diffuse_reflect(gas, cs, X, draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + b), V);
+            if (surf) surface_hit(gas, cs, X, Vin, V, surf);
         }
         if (bounced) {
             for (int a = 0; a < 3; ++a) if (a < dim) {

@@ -682,7 +682,9 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
                 id = S.id[i];
                 t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
             }
-            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms);
+            // wall sums of the body (Step (5) on the surface) in sampled steps
+            double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady) ? C.surf : nullptr;
+            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
             if (nl >= 0) {
                 nc = cs.cell0 + nl;
                 for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
@@ -2861,6 +2863,67 @@ void launch_moments_now(const Ctx &c, void *s, int case_id, int ncells, double *
 void launch_build_big(const Ctx &c, void *s)
 {
     hipLaunchKernelGGL(k_build_big, dim3(blocks_for(c.ncells_total, 256)), dim3(256), 0, S_(s), c);
+}
+
+// Time averages of one case's body wall sums: per element the mid angle, area, p, tau, q
+// and the Eq. 35 coefficients (with C_f for the shear), then the body force and the Eq. 36
+// C_D, C_L (freestream = the case's inflow state).  One block; out holds 8 n_surf + 5.
+__global__ void k_surface_finalize(Ctx C, int case_id, double *out)
+{
+    __shared__ double red[3][256];
+    const CaseDev &cs = C.cases[case_id];
+    const int ns = cs.n_surf;
+    const double R = cs.body_r;
+    const double len = cs.dim == 3 ? (double)cs.n[2] * cs.h[2] : cs.h[2];
+    const double time = (double)C.g->n_samples[case_id] * cs.dt_G;
+    const double U = sqrt(cs.in_u[0] * cs.in_u[0] + cs.in_u[1] * cs.in_u[1] + cs.in_u[2] * cs.in_u[2]);
+    const double rho = cs.in_n * C.gas.m, pinf = cs.in_n * kKB * cs.in_T;
+    const double qd = 0.5 * rho * U * U;
+    const bool cyl = cs.body == HS_BODY_CYLINDER;
+    const double aref = cyl ? 2.0 * R * len : kPi * R * R;
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+        const double *S = C.surf + 7 * (size_t)(cs.surf0 + k);
+        const double t0 = kPi * (double)k / (double)ns, t1 = kPi * (double)(k + 1) / (double)ns;
+        const double area = cyl ? 2.0 * R * (t1 - t0) * len : 2.0 * kPi * R * R * (cos(t0) - cos(t1));
+        double p = 0.0, tau = 0.0, q = 0.0;
+        if (time > 0.0) {
+            p = -S[1] / (area * time);
+            tau = S[2] / (area * time);
+            q = S[3] / (area * time);
+            for (int a = 0; a < 3; ++a) F[a] = F[a] + S[4 + a] / time;
+        }
+        double *E = out + 8 * (size_t)k;
+        E[0] = 0.5 * (t0 + t1);
+        E[1] = area;
+        E[2] = p;
+        E[3] = tau;
+        E[4] = q;
+        E[5] = qd > 0.0 ? (p - pinf) / qd : 0.0;
+        E[6] = qd > 0.0 ? tau / qd : 0.0;
+        E[7] = qd > 0.0 ? q / (qd * U) : 0.0;
+    }
+    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = F[a];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double Ft[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < (int)blockDim.x; ++j)
+            for (int a = 0; a < 3; ++a) Ft[a] = Ft[a] + red[a][j];
+        double *B = out + 8 * (size_t)ns;
+        double drag = 0.0, lift = 0.0;
+        if (U > 0.0) {
+            drag = (Ft[0] * cs.in_u[0] + Ft[1] * cs.in_u[1] + Ft[2] * cs.in_u[2]) / U;
+            lift = (-Ft[0] * cs.in_u[1] + Ft[1] * cs.in_u[0]) / U;
+        }
+        for (int a = 0; a < 3; ++a) B[a] = Ft[a];
+        B[3] = qd > 0.0 ? drag / (qd * aref) : 0.0;
+        B[4] = qd > 0.0 ? lift / (qd * aref) : 0.0;
+    }
+}
+
+void launch_surface_finalize(const Ctx &c, void *s, int case_id, double *out)
+{
+    hipLaunchKernelGGL(k_surface_finalize, dim3(1), dim3(256), 0, S_(s), c, case_id, out);
 }
 
 void launch_finalize(const Ctx &c, void *s, int case_id, int ncells, double *out)

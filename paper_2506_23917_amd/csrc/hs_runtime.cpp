@@ -24,7 +24,8 @@ struct Layout {
     size_t total = 0;
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
-    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, trace, out;
+    size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, surf, trace, out;
+    size_t surf_bytes = 0;
 };
 
 struct Plan {
@@ -80,6 +81,10 @@ hs_status validate(const hs_gas *g, const hs_case *cs, int n, std::string &why)
                     why = "body must lie strictly inside the domain";
                     return HS_ERR_ARG;
                 }
+        }
+        if (c.n_surf < 0 || c.n_surf > 65536 || (c.n_surf > 0 && c.body == HS_BODY_NONE)) {
+            why = "n_surf (0..65536, needs a body)";
+            return HS_ERR_ARG;
         }
         for (int j = 0; j < i; ++j)
             if (cs[j].seed == c.seed) { why = "cases need distinct seeds"; return HS_ERR_ARG; }
@@ -140,6 +145,8 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         d.seed_hi = (uint32_t)(c.seed >> 32);
         d.n_steady = c.n_steady;
         d.capacity = c.capacity;
+        d.surf0 = P.cases.empty() ? 0 : P.cases.back().surf0 + P.cases.back().n_surf;
+        d.n_surf = c.n_surf;
         for (int a = 0; a < 3; ++a) {
             d.lo[a] = c.lo[a];
             d.h[a] = c.h[a];
@@ -264,10 +271,16 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.tilecase = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.cellrec = take(8 * 16 * nc);
+    size_t nsurf = 0;
+    for (const auto &c : P.cases) nsurf += (size_t)c.n_surf;
+    L.surf_bytes = 8 * 7 * std::max<size_t>(nsurf, 1);
+    L.surf = take(L.surf_bytes);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
     size_t maxcase = 1;
     for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
-    L.out = take(8 * 8 * maxcase);
+    size_t maxsurf = 0;
+    for (const auto &c : P.cases) maxsurf = std::max<size_t>(maxsurf, (size_t)c.n_surf);
+    L.out = take(8 * std::max<size_t>(8 * maxcase, 8 * maxsurf + 5));
     L.total = o;
     return L;
 }
@@ -470,6 +483,7 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.tile_cell = (int32_t *)(w + L.tiles);
     c.tile_case = (int32_t *)(w + L.tilecase);
     c.cellrec = (double *)(w + L.cellrec);
+    c.surf = (double *)(w + L.surf);
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
     c.tile_w = tile_width();
     c.dim_max = s->plan.dim_max;
@@ -494,6 +508,7 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     e = e ? e : up(L.rstate, s->plan.rstate.data(), sizeof(StateDev) * s->plan.rstate.size());
     if (s->plan.any_0d) e = e ? e : up(L.dtcell, s->plan.dtcell.data(), sizeof(double) * s->plan.dtcell.size());
     e = e ? e : hipMemsetAsync(w + L.globals, 0, sizeof(Globals), s->stream);
+    e = e ? e : hipMemsetAsync(w + L.surf, 0, L.surf_bytes, s->stream);
     if (e != hipSuccess) {
         std::string m = hipGetErrorString(e);
         delete s;
@@ -545,6 +560,40 @@ hs_status hs_step(hs_sim *s, int64_t n)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(s, HS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return HS_OK;
+}
+
+hs_status hs_surface_sums(hs_sim *s, int c, double *sums7)
+{
+    if (!s || !sums7 || c < 0 || c >= (int)s->plan.cases.size() || s->plan.cases[c].n_surf <= 0) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const CaseDev &cs = s->plan.cases[c];
+    HIPCHK(s, hipMemcpyAsync(sums7, s->ctx.surf + 7 * (size_t)cs.surf0, 8 * 7 * (size_t)cs.n_surf,
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return HS_OK;
+}
+
+hs_status hs_surface_sample(hs_sim *s, int c, double *elem8, double *body5, int64_t *n_samples)
+{
+    if (!s || !elem8 || !body5 || c < 0 || c >= (int)s->plan.cases.size() || s->plan.cases[c].n_surf <= 0)
+        return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const int ns = s->plan.cases[c].n_surf;
+    double *out = (double *)(s->ws + s->lay.out);
+    launch_surface_finalize(s->ctx, s->stream, c, out);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(elem8, out, 8 * 8 * (size_t)ns, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(body5, out + 8 * (size_t)ns, 8 * 5, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (n_samples) {
+        Globals G;
+        st = read_globals(s, G);
+        if (st) return st;
+        *n_samples = G.n_samples[c];
+    }
     return HS_OK;
 }
 

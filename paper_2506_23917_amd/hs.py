@@ -53,7 +53,7 @@ class HsCase(C.Structure):
                 ("region_box", C.POINTER(C.c_double)), ("region_state", C.POINTER(HsState)),
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
-                ("n_steady", C.c_int64), ("capacity", C.c_int64)]
+                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32)]
 
 
 class HsStateHeader(C.Structure):
@@ -97,6 +97,8 @@ def lib():
             "hs_clear_timing": ([V], C.c_int),
             "hs_autotune": ([V, C.c_int, P(HsTuneReport)], C.c_int),
             "hs_set_grid": ([V, C.c_int, C.c_int32], C.c_int),
+            "hs_surface_sums": ([V, C.c_int, P(C.c_double)], C.c_int),
+            "hs_surface_sample": ([V, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int64)], C.c_int),
             "hs_error_string": ([V], C.c_char_p),
             "hs_destroy": ([V], None),
             "hs_debug_philox": ([C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, V, V], C.c_int),
@@ -113,7 +115,7 @@ def exported_symbols():
     return ["hs_plan", "hs_init_particles", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
             "hs_export_state", "hs_import_state", "hs_last_trace", "hs_counters", "hs_num_cells",
             "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
-            "hs_error_string", "hs_destroy", "hs_debug_philox"]
+            "hs_surface_sums", "hs_surface_sample", "hs_error_string", "hs_destroy", "hs_debug_philox"]
 
 
 def make_gas(g: dict) -> HsGas:
@@ -158,6 +160,7 @@ class _Cases:
             c.seed = int(d["seed"])
             c.n_steady = int(d["n_steady"])
             c.capacity = int(d["capacity"])
+            c.n_surf = int(d.get("n_surf", 0))
         self.arr = arr
         self.n = len(cases)
 
@@ -256,6 +259,28 @@ class Sim:
         self._check(self.L.hs_sample_moments(self.h, c, mode, dp(n), dp(u), dp(T), dp(q), C.byref(ns)),
                     "hs_sample_moments")
         return dict(n=n, u=u, T=T, q=q, n_samples=ns.value)
+
+    def _n_surf(self, c):
+        return int(self.cases[c].get("n_surf", 0))
+
+    def surface_sums(self, c=0) -> np.ndarray:
+        """Raw body wall sums of case c, (n_surf, 7): reflections, sum dP.n, sum dP.t, sum dE,
+        sum dP (x, y, z)."""
+        out = np.zeros((self._n_surf(c), 7))
+        self._check(self.L.hs_surface_sums(self.h, c, out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "hs_surface_sums")
+        return out
+
+    def surface_sample(self, c=0) -> dict:
+        """Time-averaged wall quantities (Eq. 35-36): per element theta (mid), area, p, tau, q,
+        Cp, Cf, Ch; for the body the force per unit time and CD, CL."""
+        e, b = np.zeros((self._n_surf(c), 8)), np.zeros(5)
+        k = C.c_int64()
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.L.hs_surface_sample(self.h, c, dp(e), dp(b), C.byref(k)), "hs_surface_sample")
+        out = {n: e[:, i].copy() for i, n in enumerate(("theta", "area", "p", "tau", "q", "Cp", "Cf", "Ch"))}
+        out.update(force=b[:3].copy(), CD=float(b[3]), CL=float(b[4]), n_samples=k.value)
+        return out
 
     def trace(self, c=0) -> np.ndarray:
         out = np.zeros(self.num_cells(c), dtype=TRACE_DTYPE)

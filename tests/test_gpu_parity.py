@@ -175,3 +175,36 @@ def test_error_paths(gas):
     with pytest.raises(HsError) as e:
         sim.sync()
     assert e.value.code == 2
+
+
+@pytest.mark.parametrize("name", ["fm_cylinder", "fm_sphere", "cylinder"])
+def test_fp64_surface_sums_match_oracle(gas, name):
+    """Body wall sums (reflections exact per element, momentum and energy sums to 1e-11)
+    and their Eq. 35-36 time averages, FP64 path against the oracle from the same start."""
+    if name == "fm_cylinder":
+        case, steps = W.free_molecular_body("cylinder", s=1.0, cells=20, ppc=10, R=0.3, n_surf=8), 30
+    elif name == "fm_sphere":
+        case, steps = W.free_molecular_body("sphere", s=1.0, cells=12, ppc=8, R=0.35, n_surf=6), 20
+    else:
+        case = dict(small_cases()["cylinder"][0])
+        case.update(n_steady=0, n_surf=16)       # collisions on, the Ma 10 stream
+        steps = 4
+    sim = _sim(gas, [case], precision="fp64")
+    ora = Oracle(gas, [case])
+    ora.init_particles()
+    sim.step(steps)
+    ora.step(steps)
+    _compare(gas, case, sim.export_state(0), ora.get_state(0), label="surface " + name)
+    sg, so = sim.surface_sums(0), ora.surface_sums(0)
+    assert so[:, 0].sum() > 50, so[:, 0]
+    assert np.array_equal(sg[:, 0], so[:, 0]), (name, sg[:, 0], so[:, 0])
+    scale = np.abs(so[:, 1:]).max(axis=0)
+    assert np.allclose(sg[:, 1:], so[:, 1:], rtol=1e-11, atol=1e-12 * scale), name
+    rg, ro = sim.surface_sample(0), ora.surface_sample(0)
+    assert rg["n_samples"] == ro["n_samples"] == steps
+    for k in ("theta", "area", "p", "tau", "q", "Cp", "Cf", "Ch"):
+        s = np.abs(ro[k]).max()
+        assert np.allclose(rg[k], ro[k], rtol=1e-11, atol=1e-12 * s), (name, k)
+    assert np.allclose(rg["force"], ro["force"], rtol=1e-11, atol=1e-12 * np.abs(ro["force"]).max())
+    for k in ("CD", "CL"):
+        assert abs(rg[k] - ro[k]) <= 1e-11 * max(abs(ro["CD"]), 1e-300), (name, k)

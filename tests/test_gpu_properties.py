@@ -396,3 +396,31 @@ def test_bench_workload_full_size(gas):
 def test_smoke_entry_point():
     import __graft_entry__ as ge
     ge.smoke()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_free_molecular_cylinder_drag(gas, precision):
+    """Both precisions against the closed-form free-molecular cylinder drag (Bird 1994,
+    Ch. 7) at speed ratio 1, T_w / T = 5/3, by batch means over 2000 sampled steps."""
+    import math
+    from scipy import special
+    T, Tw, s = 300.0, 500.0, 1.0
+    case = W.free_molecular_body("cylinder", s=s, T=T, T_w=Tw, cells=40, ppc=20, R=0.3, n_surf=6)
+    sim = _sim(gas, [case], precision=precision)
+    U, n = case["inflow"]["u"][0], case["inflow"]["n"]
+    qd = 0.5 * n * W.ARGON["m"] * U * U
+    cds, prev = [], 0.0
+    for b in range(10):
+        sim.step(200)
+        fx = sim.surface_sums(0)[:, 4].sum()
+        cds.append((fx - prev) / (200 * case["dt_G"]) / (qd * 2 * case["body_r"]))
+        prev = fx
+    z = s * s / 2
+    ref = (math.sqrt(math.pi) * math.exp(-z) / s * ((s * s + 1.5) * special.i0(z) + (s * s + 0.5) * special.i1(z))
+           + math.pi ** 1.5 / (4 * s) * math.sqrt(Tw / T))
+    cds = np.array(cds)
+    se = cds.std(ddof=1) / math.sqrt(len(cds))
+    assert abs(cds.mean() - ref) < 5 * se, (precision, cds.mean(), ref, se)
+    assert se < 0.02 * ref
+    r = sim.surface_sample(0)
+    assert abs(r["CD"] - cds.mean()) < 1e-6 * ref
