@@ -44,6 +44,8 @@ typedef struct {
     int64_t ncells;
     double *vol, *sigc_max, *acc, *dt_cell;
     double *surf;                 /* 7 sums per body surface element */
+    double dt_cur, dt_next;       /* global step of the coming step; Eq. 26 minimum so far */
+    double t_sampled;             /* sum of the global steps of the sampled steps */
     int64_t n_samples;
     int64_t np, cap;
     double *x, *v;
@@ -484,6 +486,8 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         if (!e) e = build_faces(gas, oc);
         if (e) { hso_destroy(s); return e; }
         oc->cap = c->capacity;
+        oc->dt_cur = c->dt_G;
+        oc->dt_next = INFINITY;
         /* initial (sigma_T c_r)_max: the VHS value at c* = 10 sqrt(k T_sigma / m) */
         double sc0 = hso_sigma_c(gas, 10.0 * sqrt(KB * c->T_sigma / gas->m));
         for (int64_t k = 0; k < nc; ++k) {
@@ -544,6 +548,9 @@ static int init_case(const hso_gas *g, ocase *oc)
     oc->next_id = 0;
     oc->step = 0;
     oc->n_samples = 0;
+    oc->dt_cur = c->dt_G;
+    oc->dt_next = INFINITY;
+    oc->t_sampled = 0.0;
     memset(&oc->cnt, 0, sizeof(oc->cnt));
     memset(oc->acc, 0, sizeof(double) * 13 * (size_t)oc->ncells);
     if (oc->surf) memset(oc->surf, 0, sizeof(double) * 7 * (size_t)c->n_surf);
@@ -624,7 +631,9 @@ static int inject(const hso_gas *g, ocase *oc)
         const face_t *fc = &oc->faces[f];
         uint32_t w[4];
         hso_draw(c->seed, ST_FACE, (uint64_t)f, st, 0, w);
-        int64_t nf = (int64_t)floor(fc->lambda + hso_uniform(w[0]));
+        /* lambda is per dt_G; an adapted step scales it */
+        double lam = c->adapt_dt ? fc->lambda * (oc->dt_cur / c->dt_G) : fc->lambda;
+        int64_t nf = (int64_t)floor(lam + hso_uniform(w[0]));
         int a = fc->side / 2;
         double sg = (fc->side % 2 == 0) ? 1.0 : -1.0;
         int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
@@ -945,7 +954,7 @@ static void collide_cell(const hso_gas *g, ocase *oc, int64_t k, int64_t s0, int
         double n = (double)N * c->F_N / vol;
         double p = n * KB * T;
         double tau = hso_viscosity(g, T) / p;
-        double dtG = oc->dt_cell[k];
+        double dtG = c->dim == 0 ? oc->dt_cell[k] : oc->dt_cur;
         double dtc;
         if (c->dim == 0) {
             dtc = dtG;
@@ -956,6 +965,7 @@ static void collide_cell(const hso_gas *g, ocase *oc, int64_t k, int64_t s0, int
             double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
             dtc = L / (um + sqrt(g->gamma * R * T));
         }
+        if (c->dim > 0 && dtc < oc->dt_next) oc->dt_next = dtc;     /* Eq. 26 */
         double dtD, dtS;
         hso_split(dtc, tau, dtG, &dtD, &dtS);
         double p_relax = -expm1(-dtS / tau);             /* Eq. 16 */
@@ -1068,11 +1078,11 @@ static int step_case(const hso_gas *g, ocase *oc, int trace_on)
         int e = inject(g, oc);
         if (e) return e;
         for (int64_t i = 0; i < oc->np; ++i) {
-            double t = c->dt_G;
+            double t = oc->dt_cur;
             if (i >= n_old) {
                 uint32_t w[4];
                 hso_draw(c->seed, ST_PARTICLE, (uint64_t)oc->id[i], (uint32_t)oc->step, DRAW_INJ_TIME, w);
-                t = c->dt_G * hso_uniform(w[0]);
+                t = oc->dt_cur * hso_uniform(w[0]);
             }
             oc->cell[i] = move_particle(g, oc, &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
         }
@@ -1095,7 +1105,12 @@ static int step_case(const hso_gas *g, ocase *oc, int trace_on)
     }
     for (int64_t i = 0; i < oc->np * 3; ++i)
         if (!isfinite(oc->v[i])) return HSO_ENUM;
-    if ((int64_t)oc->step >= c->n_steady) oc->n_samples++;
+    if ((int64_t)oc->step >= c->n_steady) {
+        oc->n_samples++;
+        oc->t_sampled = oc->t_sampled + oc->dt_cur;
+    }
+    if (c->adapt_dt && c->dim > 0 && isfinite(oc->dt_next)) oc->dt_cur = oc->dt_next;
+    oc->dt_next = INFINITY;
     oc->step++;
     return HSO_OK;
 }
@@ -1303,8 +1318,8 @@ int hso_set_surface(hso_sim *s, int ci, const double *sums7)
 /* Element k spans polar angles [th_k, th_k+1), th_k = k pi / n_surf.  Its area: a
  * cylinder's two strips 2 R (th_k+1 - th_k) times the axial length (the unit depth h_z of a
  * 2-D case, nz h_z in 3-D); a sphere's zone 2 pi R^2 (cos th_k - cos th_k+1).  Over S
- * sampled steps of dt_G: p = -sum dP.n / (A S dt), tau = sum dP.t / (A S dt),
- * q = sum dE / (A S dt), force = sum dP / (S dt).  Eq. 35: C_p = (p - p_inf) / (rho U^2 / 2),
+ * sampled steps of total time t_S (S dt_G for a fixed step): p = -sum dP.n / (A t_S),
+ * tau = sum dP.t / (A t_S), q = sum dE / (A t_S), force = sum dP / t_S.  Eq. 35: C_p = (p - p_inf) / (rho U^2 / 2),
  * C_h = q / (rho U^3 / 2) (and C_f = tau / (rho U^2 / 2)); Eq. 36: C_D, C_L = force along
  * the freestream direction u / |u| and along (-u_y, u_x, 0) / |u|, over rho U^2 A_ref / 2 with
  * A_ref = 2 R times the axial length (cylinder) or pi R^2 (sphere). */
@@ -1318,7 +1333,7 @@ int hso_surface_sample(const hso_sim *s, int ci, double *elem8, double *body5, i
     int ns = c->n_surf;
     double R = c->body_r;
     double len = c->dim == 3 ? (double)c->nz * c->h[2] : c->h[2];
-    double time = (double)oc->n_samples * c->dt_G;
+    double time = oc->t_sampled;
     const hso_state *f = &c->inflow;
     double U = sqrt(f->u[0] * f->u[0] + f->u[1] * f->u[1] + f->u[2] * f->u[2]);
     double rho = f->n * s->gas.m, pinf = f->n * KB * f->T;
@@ -1360,4 +1375,51 @@ int hso_surface_sample(const hso_sim *s, int ci, double *elem8, double *body5, i
         body5[4] = qd > 0.0 ? lift / (qd * aref) : 0.0;
     }
     return HSO_OK;
+}
+
+int hso_step_dt(const hso_sim *s, int ci, double *dt_next, double *t_sampled)
+{
+    if (!s || ci < 0 || ci >= s->n_cases) return HSO_EARG;
+    if (dt_next) *dt_next = s->cases[ci].dt_cur;
+    if (t_sampled) *t_sampled = s->cases[ci].t_sampled;
+    return HSO_OK;
+}
+
+int hso_set_step_dt(hso_sim *s, int ci, double dt, double t_sampled)
+{
+    if (!s || ci < 0 || ci >= s->n_cases || !(dt > 0.0) || !(t_sampled >= 0.0)) return HSO_EARG;
+    s->cases[ci].dt_cur = dt;
+    s->cases[ci].t_sampled = t_sampled;
+    return HSO_OK;
+}
+
+int hso_dsmc_ratio(const hso_sim *s, int ci, double *ratio)
+{
+    if (!s || ci < 0 || ci >= s->n_cases || !ratio) return HSO_EARG;
+    const ocase *oc = &s->cases[ci];
+    const hso_case *c = &oc->p;
+    const hso_gas *g = &s->gas;
+    int64_t nc = oc->ncells;
+    double *n = malloc(sizeof(double) * (size_t)nc), *u = malloc(sizeof(double) * 3 * (size_t)nc);
+    double *T = malloc(sizeof(double) * (size_t)nc);
+    if (!n || !u || !T) { free(n); free(u); free(T); return HSO_ECAP; }
+    int e = hso_sample_moments((hso_sim *)s, ci, 0, n, u, T, NULL, NULL);
+    double R = KB / g->m;
+    double L = c->h[0];
+    for (int a = 1; a < c->dim; ++a) if (c->h[a] < L) L = c->h[a];
+    for (int64_t k = 0; !e && k < nc; ++k) {
+        ratio[k] = 0.0;
+        if (!(n[k] > 0.0) || !(T[k] > 0.0)) continue;
+        double tau = hso_viscosity(g, T[k]) / (n[k] * KB * T[k]);
+        double dtc;
+        if (c->dim == 0) {
+            dtc = oc->dt_cell[k];
+        } else {
+            const double *U = &u[3 * k];
+            dtc = L / (sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + sqrt(g->gamma * R * T[k]));
+        }
+        ratio[k] = dtc <= tau ? 1.0 : tau / dtc;
+    }
+    free(n); free(u); free(T);
+    return e;
 }

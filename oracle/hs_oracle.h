@@ -51,6 +51,7 @@ typedef struct {
     uint64_t seed;
     int64_t n_steady, capacity;
     int32_t n_surf;                  /* body surface elements sampled (0: none)        */
+    int32_t adapt_dt;                /* 1: Eq. 26 global step, min of Eq. 25 over cells */
 } hso_case;
 
 typedef struct hso_sim hso_sim;
@@ -100,6 +101,19 @@ int  hso_get_trace(const hso_sim *s, int c, hso_trace *out);
  * hso_surface_sample turns them into time averages: per element 8 doubles (mid angle,
  * area, p, tau, q, C_p, C_f, C_h) and per case 5 (force x, y, z per unit time, C_D, C_L),
  * with the inflow state as freestream (coefficients 0 when it has no speed). */
+/* Global time step (Eq. 26).  With adapt_dt the step after step s uses the minimum over
+ * the case's active cells (N >= 2, T > 0) of the Eq. 25 local step from step s's Step (3)
+ * moments (the first step uses dt_G; a step without active cells keeps the last value);
+ * otherwise dt_G throughout.  Inflow counts scale with the step.  hso_step_dt gives the
+ * step the next hso_step will use and the sampled time (sum of the steps of the sampled
+ * steps); hso_set_step_dt sets both (state import). */
+int  hso_step_dt(const hso_sim *s, int c, double *dt_next, double *t_sampled);
+int  hso_set_step_dt(hso_sim *s, int c, double dt, double t_sampled);
+/* "Ratio of DSMC" per cell from the time-averaged moments (n, U, T of Step (6)):
+ * Dt_DSMC / Dt_G = 1 if Dt_c <= tau, else tau / Dt_c (Eq. 27), with tau = mu(T) / (n k T)
+ * (Eq. 10) and Dt_c from Eq. 25 (0-D: the cell's own step); 0 where a cell has no
+ * samples. */
+int  hso_dsmc_ratio(const hso_sim *s, int c, double *ratio);
 int  hso_get_surface(const hso_sim *s, int c, double *sums7);
 int  hso_set_surface(hso_sim *s, int c, const double *sums7);
 int  hso_surface_sample(const hso_sim *s, int c, double *elem8, double *body5, int64_t *n_samples);

@@ -56,7 +56,8 @@ class Case(C.Structure):
                 ("region_box", C.POINTER(C.c_double)), ("region_state", C.POINTER(State)),
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
-                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32)]
+                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32),
+                ("adapt_dt", C.c_int32)]
 
 
 class Trace(C.Structure):
@@ -99,6 +100,9 @@ def lib():
         L.hso_sample_moments.argtypes = [C.c_void_p, C.c_int, C.c_int, P(C.c_double), P(C.c_double),
                                          P(C.c_double), P(C.c_double), P(C.c_int64)]
         L.hso_get_surface.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
+        L.hso_step_dt.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double)]
+        L.hso_set_step_dt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+        L.hso_dsmc_ratio.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
         L.hso_set_surface.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
         L.hso_surface_sample.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int64)]
         L.hso_num_particles.argtypes = [C.c_void_p, C.c_int]
@@ -184,6 +188,7 @@ class _CaseHolder:
         c.n_steady = int(d["n_steady"])
         c.capacity = int(d["capacity"])
         c.n_surf = int(d.get("n_surf", 0))
+        c.adapt_dt = int(bool(d.get("adapt_dt", False)))
         self.c = c
 
 
@@ -282,6 +287,21 @@ class Oracle:
             acc = np.ascontiguousarray(acc, dtype=np.float64)
             ap = _dp(acc)
         _check(self.L.hso_set_cells(self.h, c, sp, ap, int(n_samples)), "set_cells")
+
+    def step_dt(self, c=0):
+        """(global step of the next step, sampled time so far)."""
+        dt, ts = C.c_double(), C.c_double()
+        _check(self.L.hso_step_dt(self.h, c, C.byref(dt), C.byref(ts)), "step_dt")
+        return dt.value, ts.value
+
+    def set_step_dt(self, c, dt, t_sampled=0.0):
+        _check(self.L.hso_set_step_dt(self.h, c, float(dt), float(t_sampled)), "set_step_dt")
+
+    def dsmc_ratio(self, c=0) -> np.ndarray:
+        """Ratio of DSMC (Dt_DSMC / Dt_G) per cell from the time-averaged moments."""
+        out = np.zeros(self.num_cells(c))
+        _check(self.L.hso_dsmc_ratio(self.h, c, _dp(out)), "dsmc_ratio")
+        return out
 
     def surface_sums(self, c=0) -> np.ndarray:
         """Raw wall sums, (n_surf, 7): reflections, sum dP.n, sum dP.t, sum dE, sum dP."""
