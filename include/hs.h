@@ -105,7 +105,12 @@ typedef struct {
  *    c* = 10 sqrt(k T_sigma / m); n_steady: first sampled step (Step 5); capacity: the
  *    largest number of particles the case may hold.  Arrays are copied at init.
  *  n_surf: number of body surface elements sampled from step n_steady on (0: none; needs
- *    a body; at most 65536); see hs_surface_sample. */
+ *    a body; at most 65536); see hs_surface_sample.
+ *  adapt_dt: 0 keeps dt_G; 1 makes the global step adaptive (Eq. 26): the step after
+ *    step s is the minimum over the case's active cells (N >= 2, T > 0) of the Eq. 25
+ *    local step from step s's Step (3) moments, the first step uses dt_G, a step without
+ *    active cells keeps the last value, and inflow counts scale with the step (dim >= 1;
+ *    see hs_step_dt). */
 typedef struct {
     int32_t dim, nx, ny, nz;
     double lo[3], h[3];
@@ -122,6 +127,7 @@ typedef struct {
     uint64_t seed;
     int64_t n_steady, capacity;
     int32_t n_surf;
+    int32_t adapt_dt;
 } hs_case;
 
 typedef struct hs_sim hs_sim;
@@ -171,7 +177,8 @@ hs_status hs_sync(hs_sim *sim);
 hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, double *u3,
                             double *T, double *q3, int64_t *n_samples);
 
-/* Checkpoint of one case (native precision, bit-exact resume).  Layout: hs_state_header,
+/* Checkpoint of one case (native precision, bit-exact resume).  Layout: hs_state_header
+ * (version 2; only that version is accepted),
  * then pos[3][np], vel[3][np] (element size 8 for HS_FP64, 4 for HS_FP32_MIXED; pos is
  * the cell-relative position in [0,1) per axis), cell[np] (int32, case-local),
  * id[np] (int64), sigc_max[ncells], acc[ncells][13] (double).  Particles are sorted by
@@ -180,6 +187,7 @@ hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, doubl
 typedef struct {
     uint32_t magic, version, precision, dim;
     int64_t np, ncells, next_id, step, n_samples;
+    double dt_next, t_sampled;     /* the case's next global step and sampled time (v2) */
 } hs_state_header;
 size_t hs_state_bytes(hs_sim *sim, int case_id);
 hs_status hs_export_state(hs_sim *sim, int case_id, void *host_buf, size_t bytes);
@@ -251,6 +259,19 @@ hs_status hs_set_grid(hs_sim *sim, int which, int32_t blocks);
  * hs_sync. */
 hs_status hs_surface_sums(hs_sim *sim, int case_id, double *sums7);
 hs_status hs_surface_sample(hs_sim *sim, int case_id, double *elem8, double *body5, int64_t *n_samples);
+
+/* Global step of case_id that the next hs_step will use (dt_G, or the Eq. 26 value with
+ * adapt_dt), and the sampled time (the sum of the global steps of the sampled steps).
+ * Either pointer may be NULL.  Synchronises.  Errors: HS_ERR_ARG for a bad case_id. */
+hs_status hs_step_dt(hs_sim *sim, int case_id, double *dt_next, double *t_sampled);
+
+/* "Ratio of DSMC" of each cell of case_id, from the time-averaged moments of Step (6)
+ * (n, U, T as hs_sample_moments mode 0): Dt_DSMC / Dt_G of Eq. 27, i.e. 1 where
+ * Dt_c <= tau and tau / Dt_c elsewhere, with tau = mu(T) / (n k T) (Eq. 10) and Dt_c the
+ * Eq. 25 local step (a 0-D cell: its own step); 0 for a cell without samples.  ratio is a
+ * caller-owned host array of ncells doubles.  Synchronises.  Errors: HS_ERR_ARG for a bad
+ * case_id or NULL array; device errors as hs_sync. */
+hs_status hs_dsmc_ratio(hs_sim *sim, int case_id, double *ratio);
 
 /* Human-readable description of the last error (never NULL). */
 const char *hs_error_string(const hs_sim *sim);

@@ -12,6 +12,7 @@
 namespace hsk {
 
 constexpr int kMaxCases = 256;
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;   // +inf as double bits
 constexpr int kMaxBounce = 8;        // body reflections per particle per step
 constexpr int kMaxShakhov = 64;      // Shakhov acceptance-rejection attempts
 constexpr int kMaxInjectAR = 64;     // inflow normal-speed attempts
@@ -51,6 +52,7 @@ struct CaseDev {
     double in_n, in_u[3], in_T;
     int32_t bb_lo[3], bb_hi[3];     // cell-index box around the body (1-cell margin)
     int32_t surf0, n_surf;          // body surface elements: first of the batch, count
+    int32_t adapt_dt;               // 1: Eq. 26 global step
 };
 
 struct FaceDev {
@@ -82,6 +84,9 @@ struct Globals {
     int64_t inj_id_base[kMaxCases];
     int64_t n_samples[kMaxCases];
     long long counters[kMaxCases][HS_NUM_COUNTERS];
+    double dt_cur[kMaxCases];                // global step of the current step
+    unsigned long long dt_next[kMaxCases];   // Eq. 26 minimum so far (bits of a positive double)
+    double t_sampled[kMaxCases];             // sum of the global steps of the sampled steps
 };
 
 // Cell trace record (same field order as hs_trace).
@@ -154,6 +159,7 @@ void launch_moments_now(const Ctx &c, void *stream, int case_id, int ncells, dou
 void launch_build_big(const Ctx &c, void *stream);
 void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
 void launch_surface_finalize(const Ctx &c, void *stream, int case_id, double *out);
+void launch_dsmc_ratio(const Ctx &c, void *stream, int case_id, int ncells, double *out);
 int cap_wave();
 int tile_width();
 int cap_block(int precision);

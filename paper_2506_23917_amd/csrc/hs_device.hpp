@@ -358,7 +358,7 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
         }
     }
     for (int a = 0; a < 3; ++a) if (a < dim) {
-        const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+        const P dth = (full_step && !cs.adapt_dt) ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
         P x = xr[a] + v[a] * dth;
         const P f = Real<P>::fl(x);
         int i = ijk[a] + (int)f;
@@ -401,7 +401,7 @@ __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v
         const int na = body_axes(cs);
         bool near = true;
         for (int a = 0; a < 3; ++a) if (a < na) {
-            const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+            const P dth = (full_step && !cs.adapt_dt) ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
             const P x = xr[a] + v[a] * dth;
             const int i = ijk[a] + (int)Real<P>::fl(x);
             const int lo = i < ijk[a] ? i : ijk[a], hi = i < ijk[a] ? ijk[a] : i;
@@ -411,7 +411,7 @@ __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v
     }
     vchg = false;
     for (int a = 0; a < 3; ++a) if (a < dim) {
-        const P dth = full_step ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
+        const P dth = (full_step && !cs.adapt_dt) ? (P)cs.dt_over_h[a] : (P)(t / cs.h[a]);
         P x = xr[a] + v[a] * dth;
         const P f = Real<P>::fl(x);
         int i = ijk[a] + (int)f;

@@ -270,6 +270,9 @@ __global__ void k_init_finish(Ctx C, int64_t step0)
         const int64_t np = (int64_t)C.cstart[cs.cell0 + cs.ncells] - C.cstart[cs.cell0];
         G->next_id[c] = np;
         G->n_samples[c] = 0;
+        G->dt_cur[c] = cs.dt_G;
+        G->dt_next[c] = kInfBits;
+        G->t_sampled[c] = 0.0;
         for (int k = 0; k < HS_NUM_COUNTERS; ++k) G->counters[c][k] = 0;
         if (np > cs.capacity) raise_error(G, kErrCapacity);
     }
@@ -450,7 +453,9 @@ __global__ void k_inject_count(Ctx C)
     const FaceDev fd = C.faces[f];
     const CaseDev &cs = C.cases[fd.case_id];
     const W4 w = draw(cs, kStreamFace, (uint64_t)fd.local, (uint32_t)C.g->step, 0);
-    C.face_cnt[f] = (int)floor(fd.lambda + unid(w.x));
+    // lambda is per dt_G; an adapted global step (Eq. 26) scales it
+    const double lam = cs.adapt_dt ? fd.lambda * (C.g->dt_cur[fd.case_id] / cs.dt_G) : fd.lambda;
+    C.face_cnt[f] = (int)floor(lam + unid(w.x));
 }
 
 __global__ void k_inject_scan(Ctx C)
@@ -573,15 +578,15 @@ __device__ __forceinline__ int wave_slot(int32_t *count, int nc, bool want)
 // (-1: left the domain); to_body when the path may meet the body.
 template <typename P>
 __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> &S, int i, int g, P (&xr)[3],
-                                              P (&v)[3], uint32_t st, int n_live, int &nc, bool &to_body)
+                                              P (&v)[3], uint32_t st, int n_live, double dt, int &nc, bool &to_body)
 {
     if (cs.dim == 0) {
         nc = g;
         return;
     }
     const bool full = i < n_live;
-    double t = cs.dt_G;
-    if (!full) t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
+    double t = dt;
+    if (!full) t = dt * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
     bool vchg = false;
     const int nl = flight<P>(cs, g - cs.cell0, xr, v, t, full, vchg);
     if (nl == -2) {
@@ -627,10 +632,10 @@ __global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
         int nc = -1, cid = cu;
         bool to_body = false;
         if (one) {
-            if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, nc, to_body);
+            if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, const_read(&G->dt_cur[cu]), nc, to_body);
         } else if (valid) {
             cid = case_of(C, g);
-            move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, nc, to_body);
+            move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
         }
         // worklist of body candidates
         {
@@ -677,10 +682,11 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
             for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
             const bool full = i < n_live;
             int64_t id = -1;
-            double t = cs.dt_G;
+            const double dt = G->dt_cur[cid];
+            double t = dt;
             if (!full) {
                 id = S.id[i];
-                t = cs.dt_G * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
+                t = dt * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
             }
             // wall sums of the body (Step (5) on the surface) in sampled steps
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady) ? C.surf : nullptr;
@@ -719,200 +725,6 @@ struct CellCounts {
     long long cand, acc, relax, ar, arcap, skipped;
 };
 
-// Per-cell results of the moments / split / NTC stage, kept in LDS between stages.
-template <typename P>
-struct CellSlot {
-    double *U;      // [3] Step (3) mean velocity
-    double *T;      // Step (3) temperature
-    double *pr;     // relaxation probability (0 when the cell is inactive)
-    double *obs;    // largest sigma c seen by the NTC chain
-    int *act;       // collision stage active
-    P *par;         // [7] Q[3], p, RT, sqrt(2RT), A_max for the Shakhov draws
-};
-
-// Sequential per-cell stage (one lane, particles in sorted order in LDS):
-// Eq. 31 moments, Eq. 10 / 25-28 timescales and split, NTC chain (Eq. 5-9).
-template <typename P>
-__device__ void cell_stage_a(const Ctx &C, const CaseDev &cs, int g, uint32_t st, P *vx, P *vy, P *vz, int n,
-                             const CellSlot<P> &o, CellCounts &cc)
-{
-    const GasDev &gas = C.gas;
-    TraceDev *tr = C.trace ? &C.trace[g] : nullptr;
-    double s1[3] = {0.0, 0.0, 0.0}, s2 = 0.0;
-    for (int k = 0; k < n; ++k) {
-        const double a = (double)vx[k], b = (double)vy[k], c = (double)vz[k];
-        s1[0] = s1[0] + a;
-        s1[1] = s1[1] + b;
-        s1[2] = s1[2] + c;
-        s2 = s2 + (a * a + b * b + c * c);
-    }
-    if (tr) {
-        *tr = TraceDev{};
-        tr->n = n;
-        tr->pre_sum[0] = s1[0];
-        tr->pre_sum[1] = s1[1];
-        tr->pre_sum[2] = s1[2];
-        tr->pre_sum[3] = s2;
-    }
-    double U[3];
-    #pragma unroll
-    for (int a = 0; a < 3; ++a) U[a] = n > 0 ? s1[a] / (double)n : 0.0;
-    o.U[0] = U[0];
-    o.U[1] = U[1];
-    o.U[2] = U[2];
-    *o.T = 0.0;
-    *o.pr = 0.0;
-    *o.obs = 0.0;
-    *o.act = 0;
-    if (n < 2) return;
-    double c2s = 0.0, c3s[3] = {0.0, 0.0, 0.0};
-    if constexpr (sizeof(P) == 4) {
-        // FP32 peculiar velocities and products, compensated (TwoSum) sums
-        const float uf[3] = {(float)U[0], (float)U[1], (float)U[2]};
-        const float df[3] = {(float)(U[0] - (double)uf[0]), (float)(U[1] - (double)uf[1]),
-                             (float)(U[2] - (double)uf[2])};
-        float sum[4] = {0.f, 0.f, 0.f, 0.f}, cmp[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int k = 0; k < n; ++k) {
-            const float cx = ((float)vx[k] - uf[0]) - df[0];
-            const float cy = ((float)vy[k] - uf[1]) - df[1];
-            const float cz = ((float)vz[k] - uf[2]) - df[2];
-            const float c2 = cx * cx + cy * cy + cz * cz;
-            const float term[4] = {c2, c2 * cx, c2 * cy, c2 * cz};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float t = sum[j] + term[j];
-                const float bp = t - sum[j];
-                cmp[j] += (sum[j] - (t - bp)) + (term[j] - bp);
-                sum[j] = t;
-            }
-        }
-        c2s = (double)sum[0] + (double)cmp[0];
-        #pragma unroll
-        for (int a = 0; a < 3; ++a) c3s[a] = (double)sum[1 + a] + (double)cmp[1 + a];
-    } else {
-        for (int k = 0; k < n; ++k) {
-            const double cx = vx[k] - U[0], cy = vy[k] - U[1], cz = vz[k] - U[2];
-            const double c2 = cx * cx + cy * cy + cz * cz;
-            c2s = c2s + c2;
-            c3s[0] = c3s[0] + c2 * cx;
-            c3s[1] = c3s[1] + c2 * cy;
-            c3s[2] = c3s[2] + c2 * cz;
-        }
-    }
-    const double vol = C.vol[g];
-    double T;
-    if constexpr (sizeof(P) == 4) {
-        // FP32-mixed: T from the FP64 sums, the form the FP64 rescale restores exactly
-        T = gas.m * (s2 - (s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2]) / (double)n) /
-            (3.0 * kKB * (double)(n - 1));
-    } else {
-        T = gas.m * c2s / (3.0 * kKB * (double)(n - 1));
-    }
-    *o.T = T;
-    double Q[3] = {0.0, 0.0, 0.0};
-    if (n >= 3 && vol > 0.0) {
-        const double nd = (double)n * cs.F_N / vol;
-        const double f = nd * (double)n / ((double)(n - 1) * (double)(n - 2));
-        #pragma unroll
-        for (int a = 0; a < 3; ++a) Q[a] = f * 0.5 * gas.m * c3s[a];
-    }
-    if (!isfinite(T) || !isfinite(Q[0] + Q[1] + Q[2])) raise_error(C.g, kErrNumeric);
-    if (!(T > 0.0 && vol > 0.0)) {
-        cc.skipped++;
-        return;
-    }
-    *o.act = 1;
-    const double nd = (double)n * cs.F_N / vol;
-    const double p = nd * kKB * T;
-    const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
-    const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
-    double dtc;
-    if (cs.dim == 0) {
-        dtc = dtG;
-    } else {
-        const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-        dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
-    }
-    double dtD, dtS;
-    if (dtc <= tau) {
-        dtD = dtG;
-        dtS = 0.0;
-    } else {
-        dtD = (tau / dtc) * dtG;
-        dtS = dtG - dtD;
-    }
-    const double p_relax = -expm1(-dtS / tau);
-    *o.pr = p_relax;
-    double a_max = 1.0;
-    if (p_relax > 0.0) {
-        const double qm = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
-        a_max = 1.0 + 20.0 * (1.0 - gas.Pr) * qm / (p * sqrt(gas.R * T));
-        o.par[0] = (P)Q[0];
-        o.par[1] = (P)Q[1];
-        o.par[2] = (P)Q[2];
-        o.par[3] = (P)p;
-        o.par[4] = (P)(gas.R * T);
-        o.par[5] = (P)sqrt(2.0 * gas.R * T);
-        o.par[6] = (P)a_max;
-    }
-    if (tr) {
-        tr->T = T;
-        tr->tau = tau;
-        tr->dt_dsmc = dtD;
-        tr->p_relax = p_relax;
-        tr->a_max = p_relax > 0.0 ? a_max : 0.0;
-    }
-    // NTC (Eq. 5-9): candidates in index order, (sigma c)_max fixed during the step
-    const int lc = g - cs.cell0;
-    const double scmax = C.sigc[g];
-    const double M = 0.5 * (double)n * (double)(n - 1) * cs.F_N * scmax * dtD / vol;
-    const double Mu = M + unid(draw(cs, kStreamCell, (uint64_t)lc, st, 0).x);
-    long long ncol = 0;
-    if (Mu >= 0.0 && Mu < 1e9) ncol = (long long)floor(Mu);
-    else raise_error(C.g, kErrNumeric);
-    const P scm = (P)scmax;
-    const P K = (P)gas.K_vhs, ex = (P)gas.vhs_exp;
-    double obs = 0.0;
-    long long nacc = 0;
-    uint64_t hash = 0;
-    for (long long k = 0; k < ncol; ++k) {
-        const W4 w = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(1 + 2 * k));
-        const uint32_t i = unidx(w.x, (uint32_t)n);
-        uint32_t j = unidx(w.y, (uint32_t)(n - 1));
-        if (j >= i) ++j;
-        const P ua = Real<P>::uni(w.z);
-        const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
-        const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
-        const P sc = K * Real<P>::pw(cr, ex);
-        if ((double)sc > obs) obs = (double)sc;
-        if (ua < sc / scm) {
-            const W4 w2 = draw(cs, kStreamCell, (uint64_t)lc, st, (uint32_t)(2 + 2 * k));
-            const P cchi = (P)2 * Real<P>::uni(w2.x) - (P)1;
-            const P schi = Real<P>::sq((P)1 - cchi * cchi);
-            P sth, cth;
-            Real<P>::sc2pi(Real<P>::uni(w2.y), &sth, &cth);
-            const P om[3] = {cchi, schi * cth, schi * sth};
-            P *vv[3] = {vx, vy, vz};
-            #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const P sum = vv[a][i] + vv[a][j];
-                vv[a][i] = (P)0.5 * (sum - cr * om[a]);
-                vv[a][j] = (P)0.5 * (sum + cr * om[a]);
-            }
-            ++nacc;
-            hash ^= (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
-        }
-    }
-    *o.obs = obs;
-    if (tr) {
-        tr->ncol = ncol;
-        tr->nacc = nacc;
-        tr->acc_hash = hash;
-    }
-    cc.cand += ncol;
-    cc.acc += nacc;
-}
-
 // Shakhov acceptance-rejection draw (Eq. 17-18) for one relaxing particle.
 template <typename P>
 __device__ __forceinline__ int shakhov_draw(uint32_t sd0, uint32_t sd1, int64_t id, uint32_t st, const P *par,
@@ -937,93 +749,6 @@ __device__ __forceinline__ int shakhov_draw(uint32_t sd0, uint32_t sd1, int64_t 
         if (A / am > Real<P>::uni(w5.x)) return a + 1;
     }
     return -kMaxShakhov;
-}
-
-// Sequential per-cell stage after the Shakhov draws: Eq. 19 rescale in FP64 with the
-// Step (3) U, T; Step (5) sums; (sigma c)_max; trace record.
-template <typename P>
-__device__ void cell_stage_c(const Ctx &C, int g, bool sampling, P *vx, P *vy, P *vz, int n,
-                             const CellSlot<P> &o, const int32_t *rel)
-{
-    TraceDev *tr = C.trace ? &C.trace[g] : nullptr;
-    double post[4] = {0.0, 0.0, 0.0, 0.0};
-    bool rescaled = false;
-    if (*o.act) {
-        double r1[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < n; ++k) {
-            r1[0] = r1[0] + (double)vx[k];
-            r1[1] = r1[1] + (double)vy[k];
-            r1[2] = r1[2] + (double)vz[k];
-        }
-        const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
-        double r2 = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double cx = (double)vx[k] - Up[0], cy = (double)vy[k] - Up[1], cz = (double)vz[k] - Up[2];
-            r2 = r2 + (cx * cx + cy * cy + cz * cz);
-        }
-        const double Tp = C.gas.m * r2 / (3.0 * kKB * (double)(n - 1));
-        if (Tp > 0.0) {
-            rescaled = true;
-            const double f = sqrt(*o.T / Tp);
-            const double U0 = o.U[0], U1 = o.U[1], U2 = o.U[2];
-            for (int k = 0; k < n; ++k) {
-                const double a = U0 + ((double)vx[k] - Up[0]) * f;
-                const double b = U1 + ((double)vy[k] - Up[1]) * f;
-                const double c = U2 + ((double)vz[k] - Up[2]) * f;
-                if (tr) {
-                    post[0] = post[0] + a;
-                    post[1] = post[1] + b;
-                    post[2] = post[2] + c;
-                    post[3] = post[3] + (a * a + b * b + c * c);
-                }
-                vx[k] = (P)a;
-                vy[k] = (P)b;
-                vz[k] = (P)c;
-            }
-        }
-        if (*o.obs > C.sigc[g]) C.sigc[g] = *o.obs;
-    }
-    if (tr) {
-        if (!rescaled) {
-            for (int k = 0; k < n; ++k) {
-                const double a = (double)vx[k], b = (double)vy[k], c = (double)vz[k];
-                post[0] = post[0] + a;
-                post[1] = post[1] + b;
-                post[2] = post[2] + c;
-                post[3] = post[3] + (a * a + b * b + c * c);
-            }
-        }
-        #pragma unroll
-        for (int a = 0; a < 4; ++a) tr->post_sum[a] = post[a];
-        tr->nrelax = rel[0];
-        tr->ar_attempts = rel[1];
-        tr->ar_cap = rel[2];
-    }
-    if (sampling) {
-        double sm[12];
-        #pragma unroll
-        for (int j = 0; j < 12; ++j) sm[j] = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double x = (double)vx[k], y = (double)vy[k], z = (double)vz[k];
-            const double c2 = x * x + y * y + z * z;
-            sm[0] = sm[0] + x;
-            sm[1] = sm[1] + y;
-            sm[2] = sm[2] + z;
-            sm[3] = sm[3] + x * x;
-            sm[4] = sm[4] + y * y;
-            sm[5] = sm[5] + z * z;
-            sm[6] = sm[6] + x * y;
-            sm[7] = sm[7] + x * z;
-            sm[8] = sm[8] + y * z;
-            sm[9] = sm[9] + c2 * x;
-            sm[10] = sm[10] + c2 * y;
-            sm[11] = sm[11] + c2 * z;
-        }
-        double *A = &C.acc[13 * (size_t)g];
-        A[0] += (double)n;
-        #pragma unroll
-        for (int j = 0; j < 12; ++j) A[1 + j] += sm[j];
-    }
 }
 
 __device__ __forceinline__ void flush_counts(const Ctx &C, int cid, CellCounts &cc)
@@ -1100,6 +825,16 @@ __device__ __forceinline__ void seg_round(double (&x)[K], int head, int tail, do
 // XCD c mod 8, and its blocks sweep them in order.  The grid is a multiple of 8.
 constexpr int kXcds = 8;
 constexpr int kTileChunk = 256;
+
+// Eq. 26: fold a wave's smallest local step of case cid (lanes hold their own minima, +inf
+// where none) into the case's minimum for the next global step; one atomic per wave.
+__device__ __forceinline__ void wave_flush_dtmin(const Ctx &C, int cid, double dtmin)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dtmin = fmin(dtmin, __shfl_xor(dtmin, off, 64));
+    if ((threadIdx.x & 63) == 0 && cid >= 0 && dtmin < INFINITY)
+        atomicMin(&C.g->dt_next[cid], (unsigned long long)__double_as_longlong(dtmin));
+}
 
 // Tile of the p-th position in this block's XCD sequence (increasing in p).
 __device__ __forceinline__ int xcd_tile(int p, int xcd)
@@ -1446,6 +1181,7 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
     long long skipped[1] = {0};
     CaseTally tally{0, -1, 0};
     int my_case = -1;
+    double dtmin = INFINITY;          // smallest Eq. 25 local step of my_case's cells so far
 
     const int xcd = blockIdx.x % kXcds, nbx = gridDim.x / kXcds;
     int pos = blockIdx.x / kXcds;
@@ -1467,6 +1203,8 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
         if (cid != my_case) {
             tally_add<1>(C, tally, my_case, HS_CNT_SKIPPED_CELLS, skipped);
             skipped[0] = 0;
+            wave_flush_dtmin(C, my_case, dtmin);
+            dtmin = INFINITY;
             my_case = cid;
         }
         const CaseDev &cs = case_const(C, cid);
@@ -1596,13 +1334,14 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
             const double nd = (double)nn * cs.F_N / vol;
             p = nd * kKB * T;
             tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
-            const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+            const double dtG = cs.dim == 0 ? C.dt_cell[g] : const_read(&G->dt_cur[cid]);
             double dtc;
             if (cs.dim == 0) {
                 dtc = dtG;
             } else {
                 const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
                 dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+                if (cs.adapt_dt) dtmin = fmin(dtmin, dtc);
             }
             double dtS;
             if (dtc <= tau) {
@@ -1674,6 +1413,7 @@ __global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
     }
     tally_add<1>(C, tally, my_case, HS_CNT_SKIPPED_CELLS, skipped);
     tally_flush<1>(C, tally, HS_CNT_SKIPPED_CELLS);
+    wave_flush_dtmin(C, my_case, dtmin);
 }
 
 // Steps (4)-(5) of the tiles' cells on the sorted state: NTC, SP-Shakhov resampling, Eq. 19
@@ -2351,13 +2091,16 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             const double nd = (double)n * cs.F_N / vol;
             const double p = nd * kKB * T;
             const double tau = gas.mu_ref * pow(T / gas.T_ref, gas.omega) / p;
-            const double dtG = cs.dim == 0 ? C.dt_cell[g] : cs.dt_G;
+            const double dtG = cs.dim == 0 ? C.dt_cell[g] : G->dt_cur[cid];
             double dtc;
             if (cs.dim == 0) {
                 dtc = dtG;
             } else {
                 const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
                 dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+                // Eq. 26: the next global step is the smallest local step of this one
+                if (cs.adapt_dt && tid == 0)
+                    atomicMin(&G->dt_next[cid], (unsigned long long)__double_as_longlong(dtc));
             }
             double dtD, dtS;
             if (dtc <= tau) {
@@ -2618,8 +2361,16 @@ __global__ void k_finish_step(Ctx C, int sorted)
     Globals *G = C.g;
     if (G->halt) return;
     const int64_t step = G->step;
-    for (int c = threadIdx.x; c < C.n_cases; c += blockDim.x)
-        if (step >= C.cases[c].n_steady) G->n_samples[c] += 1;
+    for (int c = threadIdx.x; c < C.n_cases; c += blockDim.x) {
+        const CaseDev &cs = C.cases[c];
+        if (step >= cs.n_steady) {
+            G->n_samples[c] += 1;
+            G->t_sampled[c] = G->t_sampled[c] + G->dt_cur[c];
+        }
+        // Eq. 26 for the next step (kept when no cell was active)
+        if (cs.adapt_dt && cs.dim > 0 && G->dt_next[c] != kInfBits) G->dt_cur[c] = __longlong_as_double((long long)G->dt_next[c]);
+        G->dt_next[c] = kInfBits;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (sorted) {
@@ -2875,7 +2626,7 @@ __global__ void k_surface_finalize(Ctx C, int case_id, double *out)
     const int ns = cs.n_surf;
     const double R = cs.body_r;
     const double len = cs.dim == 3 ? (double)cs.n[2] * cs.h[2] : cs.h[2];
-    const double time = (double)C.g->n_samples[case_id] * cs.dt_G;
+    const double time = C.g->t_sampled[case_id];
     const double U = sqrt(cs.in_u[0] * cs.in_u[0] + cs.in_u[1] * cs.in_u[1] + cs.in_u[2] * cs.in_u[2]);
     const double rho = cs.in_n * C.gas.m, pinf = cs.in_n * kKB * cs.in_T;
     const double qd = 0.5 * rho * U * U;
@@ -2924,6 +2675,41 @@ __global__ void k_surface_finalize(Ctx C, int case_id, double *out)
 void launch_surface_finalize(const Ctx &c, void *s, int case_id, double *out)
 {
     hipLaunchKernelGGL(k_surface_finalize, dim3(1), dim3(256), 0, S_(s), c, case_id, out);
+}
+
+// Ratio of DSMC per cell (Eq. 27's Dt_DSMC / Dt_G) from the time-averaged n, U, T of the
+// Step (5) sums: 1 where Dt_c <= tau, tau / Dt_c elsewhere (tau of Eq. 10, Dt_c of Eq. 25;
+// a 0-D cell's own step); 0 without samples.
+__global__ void k_dsmc_ratio(Ctx C, int case_id, double *out)
+{
+    const CaseDev &cs = C.cases[case_id];
+    const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lc >= cs.ncells) return;
+    const int g = cs.cell0 + lc;
+    const double *A = &C.acc[13 * (size_t)g];
+    const double S = (double)C.g->n_samples[case_id];
+    const double vol = C.vol[g];
+    double r = 0.0;
+    if (A[0] > 0.0 && S > 0.0 && vol > 0.0) {
+        const double nn = cs.F_N * A[0] / (S * vol);
+        double U[3];
+        for (int a = 0; a < 3; ++a) U[a] = A[1 + a] / A[0];
+        const double cc = (A[4] + A[5] + A[6]) / A[0];
+        const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+        const double T = C.gas.m / (3.0 * kKB) * (cc - uu);
+        if (nn > 0.0 && T > 0.0) {
+            const double tau = C.gas.mu_ref * pow(T / C.gas.T_ref, C.gas.omega) / (nn * kKB * T);
+            const double dtc = cs.dim == 0 ? C.dt_cell[g]
+                                           : cs.L_cell / (sqrt(uu) + sqrt(C.gas.gamma * C.gas.R * T));
+            r = dtc <= tau ? 1.0 : tau / dtc;
+        }
+    }
+    out[lc] = r;
+}
+
+void launch_dsmc_ratio(const Ctx &c, void *s, int case_id, int ncells, double *out)
+{
+    hipLaunchKernelGGL(k_dsmc_ratio, dim3(blocks_for(ncells, 256)), dim3(256), 0, S_(s), c, case_id, out);
 }
 
 void launch_finalize(const Ctx &c, void *s, int case_id, int ncells, double *out)

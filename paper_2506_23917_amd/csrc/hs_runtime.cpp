@@ -82,6 +82,7 @@ hs_status validate(const hs_gas *g, const hs_case *cs, int n, std::string &why)
                     return HS_ERR_ARG;
                 }
         }
+        if (c.adapt_dt != 0 && c.adapt_dt != 1) { why = "adapt_dt must be 0 or 1"; return HS_ERR_ARG; }
         if (c.n_surf < 0 || c.n_surf > 65536 || (c.n_surf > 0 && c.body == HS_BODY_NONE)) {
             why = "n_surf (0..65536, needs a body)";
             return HS_ERR_ARG;
@@ -147,6 +148,7 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         d.capacity = c.capacity;
         d.surf0 = P.cases.empty() ? 0 : P.cases.back().surf0 + P.cases.back().n_surf;
         d.n_surf = c.n_surf;
+        d.adapt_dt = c.adapt_dt;
         for (int a = 0; a < 3; ++a) {
             d.lo[a] = c.lo[a];
             d.h[a] = c.h[a];
@@ -597,6 +599,32 @@ hs_status hs_surface_sample(hs_sim *s, int c, double *elem8, double *body5, int6
     return HS_OK;
 }
 
+hs_status hs_step_dt(hs_sim *s, int c, double *dt_next, double *t_sampled)
+{
+    if (!s || c < 0 || c >= (int)s->plan.cases.size()) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    Globals G;
+    if ((st = read_globals(s, G))) return st;
+    if (dt_next) *dt_next = G.dt_cur[c];
+    if (t_sampled) *t_sampled = G.t_sampled[c];
+    return HS_OK;
+}
+
+hs_status hs_dsmc_ratio(hs_sim *s, int c, double *ratio)
+{
+    if (!s || !ratio || c < 0 || c >= (int)s->plan.cases.size()) return HS_ERR_ARG;
+    hs_status st = check_device(s);
+    if (st) return st;
+    const int nc = s->plan.cases[c].ncells;
+    double *out = (double *)(s->ws + s->lay.out);
+    launch_dsmc_ratio(s->ctx, s->stream, c, nc, out);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(ratio, out, 8 * (size_t)nc, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return HS_OK;
+}
+
 hs_status hs_sync(hs_sim *s)
 {
     if (!s) return HS_ERR_ARG;
@@ -684,7 +712,7 @@ hs_status hs_export_state(hs_sim *s, int c, void *host_buf, size_t bytes)
     const size_t es = s->prec == HS_FP64 ? 8 : 4;
     hs_state_header hd;
     hd.magic = kMagic;
-    hd.version = 1;
+    hd.version = 2;
     hd.precision = s->prec;
     hd.dim = cs.dim;
     hd.np = (int64_t)np;
@@ -692,6 +720,8 @@ hs_status hs_export_state(hs_sim *s, int c, void *host_buf, size_t bytes)
     hd.next_id = G.next_id[c];
     hd.step = G.step;
     hd.n_samples = G.n_samples[c];
+    hd.dt_next = G.dt_cur[c];
+    hd.t_sampled = G.t_sampled[c];
     char *p = (char *)host_buf;
     std::memcpy(p, &hd, sizeof(hd));
     p += sizeof(hd);
@@ -727,8 +757,9 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     std::memcpy(&hd, host_buf, sizeof(hd));
     const CaseDev &cs = s->plan.cases[c];
     const size_t es = s->prec == HS_FP64 ? 8 : 4;
-    if (hd.magic != kMagic || hd.precision != (uint32_t)s->prec || hd.dim != (uint32_t)cs.dim ||
-        hd.ncells != cs.ncells || hd.np < 0 || hd.step < 0) {
+    if (hd.magic != kMagic || hd.version != 2 || hd.precision != (uint32_t)s->prec || hd.dim != (uint32_t)cs.dim ||
+        hd.ncells != cs.ncells || hd.np < 0 || hd.step < 0 || !(hd.t_sampled >= 0.0) ||
+        (cs.dim > 0 ? !(hd.dt_next > 0.0) : !(hd.dt_next >= 0.0))) {
         s->err = "state header does not match the case";
         return HS_ERR_ARG;
     }
@@ -833,6 +864,9 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     G.n_tiles = (int32_t)(((int64_t)total + 4 * s->plan.ncells + tile_width() - 1) / tile_width());
     G.next_id[c] = hd.next_id;
     G.n_samples[c] = hd.n_samples;
+    G.dt_cur[c] = hd.dt_next;
+    G.dt_next[c] = kInfBits;
+    G.t_sampled[c] = hd.t_sampled;
     HIPCHK(s, hipMemcpy(s->ws + s->lay.globals, &G, sizeof(G), hipMemcpyHostToDevice));
     Launch::tile_table(s->ctx, s->stream);
     HIPCHK(s, hipGetLastError());

@@ -53,13 +53,15 @@ class HsCase(C.Structure):
                 ("region_box", C.POINTER(C.c_double)), ("region_state", C.POINTER(HsState)),
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
-                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32)]
+                ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32),
+                ("adapt_dt", C.c_int32)]
 
 
 class HsStateHeader(C.Structure):
     _fields_ = [("magic", C.c_uint32), ("version", C.c_uint32), ("precision", C.c_uint32),
                 ("dim", C.c_uint32), ("np", C.c_int64), ("ncells", C.c_int64),
-                ("next_id", C.c_int64), ("step", C.c_int64), ("n_samples", C.c_int64)]
+                ("next_id", C.c_int64), ("step", C.c_int64), ("n_samples", C.c_int64),
+                ("dt_next", C.c_double), ("t_sampled", C.c_double)]
 
 
 TRACE_DTYPE = np.dtype([("n", "i8"), ("ncol", "i8"), ("nacc", "i8"), ("nrelax", "i8"),
@@ -98,6 +100,8 @@ def lib():
             "hs_autotune": ([V, C.c_int, P(HsTuneReport)], C.c_int),
             "hs_set_grid": ([V, C.c_int, C.c_int32], C.c_int),
             "hs_surface_sums": ([V, C.c_int, P(C.c_double)], C.c_int),
+            "hs_step_dt": ([V, C.c_int, P(C.c_double), P(C.c_double)], C.c_int),
+            "hs_dsmc_ratio": ([V, C.c_int, P(C.c_double)], C.c_int),
             "hs_surface_sample": ([V, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int64)], C.c_int),
             "hs_error_string": ([V], C.c_char_p),
             "hs_destroy": ([V], None),
@@ -115,7 +119,8 @@ def exported_symbols():
     return ["hs_plan", "hs_init_particles", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
             "hs_export_state", "hs_import_state", "hs_last_trace", "hs_counters", "hs_num_cells",
             "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
-            "hs_surface_sums", "hs_surface_sample", "hs_error_string", "hs_destroy", "hs_debug_philox"]
+            "hs_surface_sums", "hs_surface_sample", "hs_step_dt", "hs_dsmc_ratio", "hs_error_string", "hs_destroy",
+            "hs_debug_philox"]
 
 
 def make_gas(g: dict) -> HsGas:
@@ -161,6 +166,7 @@ class _Cases:
             c.n_steady = int(d["n_steady"])
             c.capacity = int(d["capacity"])
             c.n_surf = int(d.get("n_surf", 0))
+            c.adapt_dt = int(bool(d.get("adapt_dt", False)))
         self.arr = arr
         self.n = len(cases)
 
@@ -263,6 +269,18 @@ class Sim:
     def _n_surf(self, c):
         return int(self.cases[c].get("n_surf", 0))
 
+    def step_dt(self, c=0):
+        """(global step the next step of case c will use, sampled time so far)."""
+        dt, ts = C.c_double(), C.c_double()
+        self._check(self.L.hs_step_dt(self.h, c, C.byref(dt), C.byref(ts)), "hs_step_dt")
+        return dt.value, ts.value
+
+    def dsmc_ratio(self, c=0) -> np.ndarray:
+        """Ratio of DSMC (Dt_DSMC / Dt_G) per cell from the time-averaged moments."""
+        out = np.zeros(self.num_cells(c))
+        self._check(self.L.hs_dsmc_ratio(self.h, c, out.ctypes.data_as(C.POINTER(C.c_double))), "hs_dsmc_ratio")
+        return out
+
     def surface_sums(self, c=0) -> np.ndarray:
         """Raw body wall sums of case c, (n_surf, 7): reflections, sum dP.n, sum dP.t, sum dE,
         sum dP (x, y, z)."""
@@ -315,7 +333,8 @@ class Sim:
         sigc = np.frombuffer(raw, np.float64, nc, o).copy(); o += 8 * nc
         acc = np.frombuffer(raw, np.float64, 13 * nc, o).reshape(nc, 13).copy()
         return dict(pos=pos, vel=vel, cell=cell, id=ids, sigc_max=sigc, acc=acc, next_id=hd.next_id,
-                    step=hd.step, n_samples=hd.n_samples, dim=hd.dim, precision=hd.precision)
+                    step=hd.step, n_samples=hd.n_samples, dim=hd.dim, precision=hd.precision,
+                    dt_next=hd.dt_next, t_sampled=hd.t_sampled)
 
     def import_state(self, c, st: dict):
         rdt = self.rdt
@@ -323,8 +342,11 @@ class Sim:
         vel = np.asarray(st["vel"], rdt).reshape(-1, 3)
         np_ = vel.shape[0]
         nc = self.num_cells(c)
-        hd = HsStateHeader(MAGIC, 1, self.prec, int(self.cases[c]["dim"]), np_, nc, int(st["next_id"]),
-                           int(st["step"]), int(st.get("n_samples", 0)))
+        ns = int(st.get("n_samples", 0))
+        dt0 = float(self.cases[c]["dt_G"])
+        hd = HsStateHeader(MAGIC, 2, self.prec, int(self.cases[c]["dim"]), np_, nc, int(st["next_id"]),
+                           int(st["step"]), ns, float(st.get("dt_next", dt0)),
+                           float(st.get("t_sampled", ns * dt0)))
         sigc = np.asarray(st["sigc_max"], np.float64).reshape(nc)
         acc = np.asarray(st.get("acc", np.zeros((nc, 13))), np.float64).reshape(nc, 13)
         parts = [bytes(hd), np.ascontiguousarray(pos.T).tobytes(), np.ascontiguousarray(vel.T).tobytes(),

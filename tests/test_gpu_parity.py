@@ -208,3 +208,34 @@ def test_fp64_surface_sums_match_oracle(gas, name):
     assert np.allclose(rg["force"], ro["force"], rtol=1e-11, atol=1e-12 * np.abs(ro["force"]).max())
     for k in ("CD", "CL"):
         assert abs(rg[k] - ro[k]) <= 1e-11 * max(abs(ro["CD"]), 1e-300), (name, k)
+
+
+@pytest.mark.parametrize("name,steps", [("cylinder", 5), ("sod", 6), ("jets", 8)])
+def test_fp64_adaptive_step_matches_oracle(gas, name, steps):
+    """Eq. 26 global step: the same step sequence (1e-12) and, step by step, the same
+    particles (cells and ids exact, velocities and positions 1e-12), inflow counts
+    included; then the ratio-of-DSMC field of the sampled moments."""
+    cases = []
+    for c in small_cases()[name]:
+        c = dict(c)
+        c.update(adapt_dt=True, n_steady=0, n_surf=0)
+        cases.append(c)
+    sim = _sim(gas, cases, precision="fp64")
+    ora = Oracle(gas, cases)
+    ora.init_particles()
+    changed = False
+    for s in range(steps):
+        sim.step(1)
+        ora.step(1)
+        for k, case in enumerate(cases):
+            dg, tg = sim.step_dt(k)
+            do, to = ora.step_dt(k)
+            assert dg == pytest.approx(do, rel=1e-12, abs=0), (name, s, k)
+            assert tg == pytest.approx(to, rel=1e-12, abs=0), (name, s, k)
+            changed = changed or do != case["dt_G"]
+            _compare(gas, case, sim.export_state(k), ora.get_state(k), label="adaptive %s step %d" % (name, s))
+    assert changed
+    for k in range(len(cases)):
+        rg, ro = sim.dsmc_ratio(k), ora.dsmc_ratio(k)
+        assert np.allclose(rg, ro, rtol=1e-11, atol=1e-14), (name, k)
+        assert np.any((ro > 0) & (ro <= 1))

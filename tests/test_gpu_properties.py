@@ -35,7 +35,7 @@ def _same(a, b, label=""):
     for k in STATE_KEYS:
         assert a[k].shape == b[k].shape, (label, k, a[k].shape, b[k].shape)
         assert np.array_equal(a[k], b[k]), (label, k)
-    for k in ("next_id", "step", "n_samples"):
+    for k in ("next_id", "step", "n_samples", "dt_next", "t_sampled"):
         assert a[k] == b[k], (label, k, a[k], b[k])
 
 
@@ -83,8 +83,10 @@ def test_graph_replay_matches_eager(gas, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_export_import_resume_is_exact(gas, prec):
+@pytest.mark.parametrize("adapt", [False, True])
+def test_export_import_resume_is_exact(gas, prec, adapt):
     case = _cyl(n_steady=2)
+    case["adapt_dt"] = adapt
     a = _sim(gas, case, precision=prec)
     a.step(6)
     b = _sim(gas, case, precision=prec)
