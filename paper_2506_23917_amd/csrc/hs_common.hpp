@@ -13,6 +13,7 @@ namespace hsk {
 
 constexpr int kMaxCases = 256;
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;   // +inf as double bits
+constexpr int kSurfCopies = 16;     // copies of the wall sums, so few atomics share an address
 constexpr int kMaxBounce = 8;        // body reflections per particle per step
 constexpr int kMaxShakhov = 64;      // Shakhov acceptance-rejection attempts
 constexpr int kMaxInjectAR = 64;     // inflow normal-speed attempts
@@ -119,7 +120,7 @@ struct Ctx {
     int32_t *count, *cstart;      // per cell; cstart has ncells_total + 1 entries
     double *sigc, *acc, *vol;     // (sigma c)_max, 13 sums per cell, fluid volume
     double *cellrec;              // 16 doubles per cell: scalars of the collision stage
-    double *surf;                 // 7 sums per body surface element (all cases)
+    double *surf;                 // kSurfCopies x (7 sums per body surface element, all cases)
     int32_t *face_cnt, *face_start;
     int32_t *scan_part;
     int32_t *big_list;
@@ -130,6 +131,7 @@ struct Ctx {
     Globals *g;
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
     int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension
+    int32_t n_surf_total;         // surface elements of the batch (one copy)
     int64_t capacity;             // total particle capacity of the batch
     // launch shapes (blocks per grid; 0 = the built-in default), chosen by the autotuner
     int32_t grid[HS_NUM_KERNELS];
@@ -160,6 +162,7 @@ void launch_build_big(const Ctx &c, void *stream);
 void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double *out8);
 void launch_surface_finalize(const Ctx &c, void *stream, int case_id, double *out);
 void launch_dsmc_ratio(const Ctx &c, void *stream, int case_id, int ncells, double *out);
+void launch_surface_reduce(const Ctx &c, void *stream, int case_id, double *out);
 int cap_wave();
 int tile_width();
 int cap_block(int precision);

@@ -602,7 +602,7 @@ __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> 
 // Every particle: straight flight with specular / open walls, new cell and slot recorded.
 // Particles whose path may meet the body go to a worklist for k_move_body.
 template <typename P>
-__global__ __launch_bounds__(kBlock) void k_move_fast(Ctx C)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_move_fast(Ctx C)
 {
     Globals *G = C.g;
     if (G->halt) return;
@@ -689,7 +689,10 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
                 t = dt * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
             }
             // wall sums of the body (Step (5) on the surface) in sampled steps
-            double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady) ? C.surf : nullptr;
+            // (each wave adds to one of kSurfCopies copies of the sums)
+            const int copy = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kSurfCopies);
+            double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
+                               ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
             const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
             if (nl >= 0) {
                 nc = cs.cell0 + nl;
@@ -1165,7 +1168,7 @@ enum : int {
 // partial sums by a butterfly, so every lane of the group holds the cell's totals and
 // derives the scalars itself; lane `sub == 0` records them.
 template <typename P, int TW, int D>
-__global__ __launch_bounds__(64) void k_cell_scalars(Ctx C)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_cell_scalars(Ctx C)
 {
     constexpr int MAXC = TW / 4;
     Globals *G = C.g;
@@ -2616,6 +2619,32 @@ void launch_build_big(const Ctx &c, void *s)
     hipLaunchKernelGGL(k_build_big, dim3(blocks_for(c.ncells_total, 256)), dim3(256), 0, S_(s), c);
 }
 
+// Wall sums of surface element e of the batch: the kSurfCopies copies added in copy order.
+__device__ inline void surf_sums(const Ctx &C, int e, double (&S)[7])
+{
+    for (int j = 0; j < 7; ++j) S[j] = 0.0;
+    for (int c = 0; c < kSurfCopies; ++c) {
+        const double *P = C.surf + 7 * ((size_t)c * (size_t)C.n_surf_total + (size_t)e);
+        for (int j = 0; j < 7; ++j) S[j] = S[j] + P[j];
+    }
+}
+
+__global__ void k_surface_reduce(Ctx C, int case_id, double *out)
+{
+    const CaseDev &cs = C.cases[case_id];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cs.n_surf) return;
+    double S[7];
+    surf_sums(C, cs.surf0 + k, S);
+    for (int j = 0; j < 7; ++j) out[7 * (size_t)k + j] = S[j];
+}
+
+void launch_surface_reduce(const Ctx &c, void *s, int case_id, double *out)
+{
+    const int ns = c.n_surf_total > 0 ? c.n_surf_total : 1;
+    hipLaunchKernelGGL(k_surface_reduce, dim3(blocks_for(ns, 256)), dim3(256), 0, S_(s), c, case_id, out);
+}
+
 // Time averages of one case's body wall sums: per element the mid angle, area, p, tau, q
 // and the Eq. 35 coefficients (with C_f for the shear), then the body force and the Eq. 36
 // C_D, C_L (freestream = the case's inflow state).  One block; out holds 8 n_surf + 5.
@@ -2634,7 +2663,8 @@ __global__ void k_surface_finalize(Ctx C, int case_id, double *out)
     const double aref = cyl ? 2.0 * R * len : kPi * R * R;
     double F[3] = {0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-        const double *S = C.surf + 7 * (size_t)(cs.surf0 + k);
+        double S[7];
+        surf_sums(C, cs.surf0 + k, S);
         const double t0 = kPi * (double)k / (double)ns, t1 = kPi * (double)(k + 1) / (double)ns;
         const double area = cyl ? 2.0 * R * (t1 - t0) * len : 2.0 * kPi * R * R * (cos(t0) - cos(t1));
         double p = 0.0, tau = 0.0, q = 0.0;

@@ -275,7 +275,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.cellrec = take(8 * 16 * nc);
     size_t nsurf = 0;
     for (const auto &c : P.cases) nsurf += (size_t)c.n_surf;
-    L.surf_bytes = 8 * 7 * std::max<size_t>(nsurf, 1);
+    L.surf_bytes = 8 * 7 * (size_t)kSurfCopies * std::max<size_t>(nsurf, 1);
     L.surf = take(L.surf_bytes);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
     size_t maxcase = 1;
@@ -486,6 +486,11 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     c.tile_case = (int32_t *)(w + L.tilecase);
     c.cellrec = (double *)(w + L.cellrec);
     c.surf = (double *)(w + L.surf);
+    {
+        size_t ns = 0;
+        for (const auto &cd : s->plan.cases) ns += (size_t)cd.n_surf;
+        c.n_surf_total = (int32_t)ns;
+    }
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
     c.tile_w = tile_width();
     c.dim_max = s->plan.dim_max;
@@ -571,8 +576,10 @@ hs_status hs_surface_sums(hs_sim *s, int c, double *sums7)
     hs_status st = check_device(s);
     if (st) return st;
     const CaseDev &cs = s->plan.cases[c];
-    HIPCHK(s, hipMemcpyAsync(sums7, s->ctx.surf + 7 * (size_t)cs.surf0, 8 * 7 * (size_t)cs.n_surf,
-                             hipMemcpyDeviceToHost, s->stream));
+    double *out = (double *)(s->ws + s->lay.out);
+    launch_surface_reduce(s->ctx, s->stream, c, out);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(sums7, out, 8 * 7 * (size_t)cs.n_surf, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return HS_OK;
 }
