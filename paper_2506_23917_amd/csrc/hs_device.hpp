@@ -385,11 +385,39 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
     return cell_local(cs, ijk);
 }
 
+// Whether the flight x + c s, 0 <= s <= t, from the particle's absolute position (formed as
+// the body-reflection path forms it, in FP64) comes within the body radius (1 + 1e-9) of the
+// body's centre: a conservative test, so every path that the exact FP64 intersection of
+// k_move_body would find hitting the wall is sent there, and the others fly here.
+template <typename P>
+__device__ __forceinline__ bool may_hit_body(const CaseDev &cs, const int ijk[3], const P xr[3], const P v[3],
+                                             double t)
+{
+    const int na = body_axes(cs);
+    double d[3] = {0.0, 0.0, 0.0}, w[3] = {0.0, 0.0, 0.0};
+    double dv = 0.0, vv = 0.0;
+    for (int k = 0; k < 3; ++k) if (k < na) {
+        d[k] = cs.lo[k] + ((double)ijk[k] + (double)xr[k]) * cs.h[k] - cs.body_c[k];
+        w[k] = (double)v[k];
+        dv = dv + d[k] * w[k];
+        vv = vv + w[k] * w[k];
+    }
+    double sm = vv > 0.0 ? -dv / vv : 0.0;
+    sm = sm < 0.0 ? 0.0 : (sm > t ? t : sm);
+    double m2 = 0.0;
+    for (int k = 0; k < 3; ++k) if (k < na) {
+        const double e = d[k] + w[k] * sm;
+        m2 = m2 + e * e;
+    }
+    const double r = cs.body_r * (1.0 + 1e-9);
+    return m2 <= r * r;
+}
+
 // Plain flight (Eq. 4) in cell units for particles that cannot meet the body this step:
 // specular walls by mirroring, removal through open faces.  Returns the new case-local
-// cell, -1 when the particle left, or -2 when the cell box of the straight path overlaps
-// the body's cell box (the caller then runs move_particle on the untouched state).
-// vchg is set when a wall changed the velocity.
+// cell, -1 when the particle left, or -2 when the straight path may meet the body (its
+// cell box overlaps the body's and may_hit_body holds; the caller then runs move_particle
+// on the untouched state).  vchg is set when a wall changed the velocity.
 template <typename P>
 __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v[3], double t, bool full_step,
                                       bool &vchg)
@@ -407,7 +435,7 @@ __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v
             const int lo = i < ijk[a] ? i : ijk[a], hi = i < ijk[a] ? ijk[a] : i;
             if (hi < cs.bb_lo[a] || lo > cs.bb_hi[a]) near = false;
         }
-        if (near) return -2;
+        if (near && may_hit_body(cs, ijk, xr, v, t)) return -2;
     }
     vchg = false;
     for (int a = 0; a < 3; ++a) if (a < dim) {
