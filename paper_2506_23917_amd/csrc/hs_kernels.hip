@@ -933,6 +933,11 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
     __shared__ int32_t s_dsrc[MAXP];      // source of each destination slot
     __shared__ uint8_t s_lc[MAXP];
     __shared__ int32_t c_start[MAXC], c_off[MAXC + 1];
+    // first slot of every non-empty cell as a bit, and the cell of each non-empty ordinal:
+    // the cell of slot s is s_ord[(non-empty cells starting at or before s) - 1]
+    constexpr int RW = (MAXP + 63) / 64;
+    __shared__ unsigned long long s_first[RW];
+    __shared__ uint8_t s_ord[MAXC];
     Globals *G = C.g;
     if (G->halt) return;
     const int lane = threadIdx.x;
@@ -977,22 +982,28 @@ __global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
         const int np = __shfl(incl, 63, 64);
         if (own) c_off[lane] = off;
         if (lane == 0) c_off[ncl] = np;
+        if (lane < RW) s_first[lane] = 0ull;
+        team_sync<64>();
+        const bool ne = nn > 0;
+        const unsigned long long mne = __ballot(ne);
+        if (ne) {
+            atomicOr(&s_first[off >> 6], 1ull << (off & 63));
+            s_ord[__popcll(mne & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+        }
         team_sync<64>();
         // slots -> cells, sources (all index loads issued before any is used)
-        constexpr int R = (MAXP + 63) / 64;
+        constexpr int R = RW;
         {
             int pidx[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = lane + 64 * r;
                 pidx[r] = -1;
+                // non-empty cells starting before this row (their starts increase with the lane)
+                const int before = __popcll(__ballot(ne && off < 64 * r));
                 if (s < np) {
-                    int a = 0, b = ncl - 1;
-                    while (a < b) {
-                        const int mid = (a + b + 1) >> 1;
-                        if (c_off[mid] <= s) a = mid;
-                        else b = mid - 1;
-                    }
+                    const unsigned long long wbits = s_first[r];
+                    const int a = s_ord[before + __popcll(wbits & ((2ull << lane) - 1ull)) - 1];
                     s_lc[s] = (uint8_t)a;
                     pidx[r] = c_start[a] + (s - c_off[a]);
                 }
