@@ -1479,7 +1479,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
     const GasDev &gas = C.gas;
     const bool tracing = C.trace != nullptr;
     // counts of this wave: candidates, accepted, relaxed, AR attempts, AR cap hits
-    long long cnt[5] = {0, 0, 0, 0, 0};
+    int cnt[5] = {0, 0, 0, 0, 0};        // per lane and case: small, widened when tallied
     CaseTally tally{0, -1, 0};
     int my_case = -1;
 
@@ -1501,7 +1501,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         }
         if (ncl == 0) continue;          // a tile inside one dense cell
         if (cid != my_case) {
-            tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, cnt);
+            const long long w5[5] = {cnt[0], cnt[1], cnt[2], cnt[3], cnt[4]};
+            tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, w5);
 #pragma unroll
             for (int j = 0; j < 5; ++j) cnt[j] = 0;
             my_case = cid;
@@ -1632,12 +1633,12 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         for (int off = 32; off > 0; off >>= 1) kbmax = max(kbmax, __shfl_xor(kbmax, off, 64));
         double scmax = 0.0, U[3] = {0.0, 0.0, 0.0}, T = 0.0, pr = 0.0;
         P par[7] = {(P)0, (P)0, (P)0, (P)0, (P)0, (P)0, (P)0};
-        long long ncol = 0;
+        int ncol = 0;
         bool active = false;
         if (own) {
             const double *R = C.cellrec + (size_t)kRecLen * g;
             scmax = R[kRecScm];
-            ncol = (long long)R[kRecNcol];
+            ncol = (int)R[kRecNcol];
             active = R[kRecAct] != 0.0;
             U[0] = R[kRecU + 0];
             U[1] = R[kRecU + 1];
@@ -1937,7 +1938,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         }
         team_sync<64>();
     }
-    tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, cnt);
+    const long long w5[5] = {cnt[0], cnt[1], cnt[2], cnt[3], cnt[4]};
+    tally_add<5>(C, tally, my_case, HS_CNT_CANDIDATES, w5);
     tally_flush<5>(C, tally, HS_CNT_CANDIDATES);
 }
 
