@@ -1664,7 +1664,6 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             pr = 0.0;
         }
         const bool lead = work && sub == 0;
-        TraceDev *tr = (lead && tracing) ? &C.trace[g] : nullptr;
 
         // candidate ranges of the cells, in cell order
         if (lead) c_kb[gc] = (int)ncol;
@@ -1792,7 +1791,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             if (obs > scmax) C.sigc[g] = obs;
             cnt[0] += ncol;
             cnt[1] += c_nacc[gc];
-            if (tr) {
+            if (tracing) {
+                TraceDev *tr = &C.trace[g];
                 tr->ncol = ncol;
                 tr->nacc = c_nacc[gc];
                 tr->acc_hash = (unsigned long long)c_hash[gc];
