@@ -39,6 +39,14 @@ def test_plan_validates_on_host():
         assert e.code == 1
     else:
         raise AssertionError("expected an argument error")
+    # surface elements need a body, and at most 65536 of them
+    for bad in (dict(W.sod_1d(), n_surf=4), dict(W.cylinder_2d(nx=40, ny=30), n_surf=70000)):
+        try:
+            hs.plan_bytes(g, bad)
+        except hs.HsError as e:
+            assert e.code == 1
+        else:
+            raise AssertionError("expected an argument error")
     # two cases with the same seed are rejected
     try:
         hs.plan_bytes(g, [W.sod_1d(seed=3), W.sod_1d(seed=3)])

@@ -239,3 +239,21 @@ def test_fp64_adaptive_step_matches_oracle(gas, name, steps):
         rg, ro = sim.dsmc_ratio(k), ora.dsmc_ratio(k)
         assert np.allclose(rg, ro, rtol=1e-11, atol=1e-14), (name, k)
         assert np.any((ro > 0) & (ro <= 1))
+
+
+def test_fp64_many_small_cases_match_oracle(gas):
+    """A batch of 120 small Sod tubes (distinct seeds; several cases per tile walk of a
+    wave, so the per-wave counter slots fill and flush): states and every counter of every
+    case equal the oracle's after a few steps."""
+    cases = [W.sod_1d(seed=s + 11, ncells=40, ppc_left=48, n_steady=0) for s in range(120)]
+    sim = _sim(gas, cases, precision="fp64")
+    ora = Oracle(gas, cases)
+    ora.init_particles()
+    sim.step(3)
+    ora.step(3)
+    for c, case in enumerate(cases):
+        _compare(gas, case, sim.export_state(c), ora.get_state(c), label="case %d" % c)
+        gc, oc = sim.counters(c), ora.counters(c)
+        for k in oc:
+            assert gc[k] == oc[k], (c, k, gc[k], oc[k])
+    assert sum(ora.counters(c)["candidates"] for c in range(len(cases))) > 0
