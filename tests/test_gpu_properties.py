@@ -426,3 +426,54 @@ def test_free_molecular_cylinder_drag(gas, precision):
     assert se < 0.02 * ref
     r = sim.surface_sample(0)
     assert abs(r["CD"] - cds.mean()) < 1e-6 * ref
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_time_averages_within_three_standard_errors(gas, prec):
+    """Cylinder 80 x 60 from the impulsive start, sampled from step 100 to 400: the GPU's
+    time-averaged n and T per cell against the oracle's, in units of the standard error of
+    a difference of two such averages (from 6 batch means of the oracle's run).  FP32-mixed
+    runs apart from the oracle within a few steps, so this is a test between statistically
+    independent runs; FP64 stays closer."""
+    from oracle.oracle import Oracle
+    case = W.cylinder_2d(nx=80, ny=60, ppc=10, n_steady=100)
+    ora = Oracle(gas, case)
+    ora.init_particles()
+    ora.step(100)
+    batches = []
+    prev = None
+    for b in range(6):
+        ora.step(50)
+        st = ora.get_cells(0)
+        acc = st["acc"].copy()
+        batches.append(acc - (prev if prev is not None else 0.0))
+        prev = acc
+    vol = ora.get_cells(0)["vol"]
+    m = gas["m"]
+    KB_ = 1.380649e-23
+
+    def n_T(acc, nsamp):
+        N = acc[:, 0]
+        ok = (N > 0) & (vol > 0)
+        n = np.where(ok, case["F_N"] * N / (nsamp * np.where(vol > 0, vol, 1)), 0.0)
+        cc = np.where(ok, (acc[:, 4] + acc[:, 5] + acc[:, 6]) / np.where(ok, N, 1), 0.0)
+        uu = np.where(ok, (acc[:, 1] ** 2 + acc[:, 2] ** 2 + acc[:, 3] ** 2) / np.where(ok, N, 1) ** 2, 0.0)
+        return n, m / (3 * KB_) * (cc - uu)
+
+    bn, bT = zip(*[n_T(a, 50) for a in batches])
+    bn, bT = np.array(bn), np.array(bT)
+    on, oT = bn.mean(0), bT.mean(0)
+    se_n = bn.std(0, ddof=1) / np.sqrt(6) * np.sqrt(2)      # of a difference of two runs
+    se_T = bT.std(0, ddof=1) / np.sqrt(6) * np.sqrt(2)
+    sim = _sim(gas, case, precision=prec)
+    sim.step(400)
+    g = sim.sample_moments(0, mode=0)
+    assert g["n_samples"] == 300
+    sel = (on > 0) & (se_n > 0) & (se_T > 0) & (vol > 0)
+    zn = (g["n"][sel] - on[sel]) / se_n[sel]
+    zT = (g["T"][sel] - oT[sel]) / se_T[sel]
+    print(prec, "mean z^2 n %.3f T %.3f; |z|>4: %.4f %.4f" % ((zn ** 2).mean(), (zT ** 2).mean(),
+                                                          (abs(zn) > 4).mean(), (abs(zT) > 4).mean()))
+    for z in (zn, zT):
+        assert (z ** 2).mean() < 2.0
+        assert (abs(z) > 4).mean() < 0.01
