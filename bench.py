@@ -13,7 +13,11 @@ events on the simulation's stream inside the timed region.  Its HBM traffic come
 committed rocprofv3 counter summary and is reported only while the kernel sources are the
 ones it was measured on.
 
-Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: this build runs on one GPU.
+The FP64 run's developed state is then imported into an FP32-mixed sim and both take one step
+from it with the same random numbers: the relative L2 differences of the cell moments n, u, T, q
+go into the line's "accuracy" object (the mixed path's bound is 1e-3).
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: the build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -90,6 +94,27 @@ def run_gpu(prec, case, gas, warmup, steps):
     sim.set_timing(False)
     sim.clear_timing()
     return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches, tune=tune)
+
+
+def paired_accuracy(sim64, case, gas):
+    """FP32-mixed against FP64 from the same developed state and RNG stream: one step of each,
+    relative L2 over the cells of n, T and q, and of u relative to the local speed scale
+    sqrt(|u|^2 + kT/m)."""
+    import numpy as np
+    from paper_2506_23917_amd.hs import Sim
+    st = sim64.export_state(0)
+    s32 = Sim(gas, case, precision="fp32", device="cuda:0", no_particles=True)
+    s32.import_state(0, st)
+    s32.step(1)
+    sim64.step(1)
+    a, b = s32.sample_moments(0, mode=1), sim64.sample_moments(0, mode=1)
+    sel = b["n"] > 0
+    rel = lambda x, y: float(np.sqrt(np.sum((x - y) ** 2)) / max(np.sqrt(np.sum(y ** 2)), 1e-300))
+    out = {k: rel(a[k][sel], b[k][sel]) for k in ("n", "T", "q")}
+    scale = np.sqrt(np.sum(b["u"][sel] ** 2) + np.sum(1.380649e-23 * np.maximum(b["T"][sel], 0.0) / gas["m"]))
+    out["u"] = float(np.sqrt(np.sum((a["u"][sel] - b["u"][sel]) ** 2)) / scale)
+    del s32
+    return out
 
 
 def cpu_baseline(sim, case, gas, nsteps):
@@ -180,6 +205,11 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps, "tile_kernel_ms": r64["tile_ms"]}
         out["mixed_speedup_vs_fp64"] = value / v64
         log("[bench] fp64: %.3f ms/step, %.3e particle-steps/s" % (1e3 * r64["dt"] / args.steps, v64))
+        acc = paired_accuracy(sim64, case, gas)
+        out["accuracy"] = {"paired_one_step_rel_l2": acc, "bound": 1e-3,
+                           "state": "the FP64 run's developed cylinder state after %d steps, imported "
+                                    "into an FP32-mixed sim; one step of each" % (args.warmup + args.steps)}
+        log("[bench] FP32-mixed vs FP64, one paired step, relative L2: %s" % acc)
         base_sim = sim64
     else:
         base_sim = sim32

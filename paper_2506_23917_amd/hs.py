@@ -339,6 +339,9 @@ class Sim:
     def import_state(self, c, st: dict):
         rdt = self.rdt
         pos = np.asarray(st["pos"], rdt).reshape(-1, 3)
+        if rdt == np.float32:
+            # an FP64 offset just below 1 rounds to 1.0f: keep it inside its cell
+            pos = np.minimum(pos, np.nextafter(np.float32(1.0), np.float32(0.0)))
         vel = np.asarray(st["vel"], rdt).reshape(-1, 3)
         np_ = vel.shape[0]
         nc = self.num_cells(c)
