@@ -26,13 +26,14 @@
 #define MAX_INJ_AR 64                 /* inflow normal-speed attempts                    */
 #define MAX_POS_TRY 64                /* initial-position attempts in a cut cell         */
 #define SUB 16                        /* sub-cells per axis for cut-cell volumes         */
+#define MAX_CROSS 4096                /* mesh edge crossings per particle per step       */
 
 enum { ST_PARTICLE = 0, ST_CELL = 1, ST_FACE = 2, ST_INIT = 3 };
 enum { DRAW_RELAX = 0, DRAW_AR = 1, DRAW_BOUNCE = 200, DRAW_INJ_TIME = 300 };
 
 typedef struct {
     int32_t cell;      /* boundary cell, case-local */
-    int32_t side;      /* 0..5 = -x,+x,-y,+y,-z,+z */
+    int32_t side;      /* grid: 0..5 = -x,+x,-y,+y,-z,+z; mesh: the cell's edge 0..3 */
     double lambda;     /* expected number of entering particles per step */
 } face_t;
 
@@ -43,6 +44,10 @@ typedef struct {
     double *dt_over_tau;
     int64_t ncells;
     double *vol, *sigc_max, *acc, *dt_cell;
+    double *lcell;                /* L_cell of Eq. 25 per cell */
+    hso_mesh mesh;                /* own copy of a mesh case's arrays */
+    double *mxy;
+    int32_t *mquad, *mnbr;
     double *surf;                 /* 7 sums per body surface element */
     double dt_cur, dt_next;       /* global step of the coming step; Eq. 26 minimum so far */
     double t_sampled;             /* sum of the global steps of the sampled steps */
@@ -232,6 +237,7 @@ double hso_sample_normal_speed(double s, const uint32_t *w, int n_attempts, int 
 
 static int64_t ncells_of(const hso_case *c)
 {
+    if (c->mesh) return c->mesh->n_cells;
     if (c->dim == 0) return c->nx;
     int64_t n = c->nx;
     if (c->dim >= 2) n *= c->ny;
@@ -308,8 +314,56 @@ int64_t hso_cut_count(const hso_case *c, int i, int j, int k)
     return out;
 }
 
+/* Node j (taken mod 4) of mesh cell k. */
+static void mesh_node(const hso_mesh *m, int64_t k, int j, double P[2])
+{
+    int32_t n = m->quad[4 * k + (j & 3)];
+    P[0] = m->xy[2 * n];
+    P[1] = m->xy[2 * n + 1];
+}
+
+/* z component of the cross product of (a1 - a0) and (b1 - b0). */
+static double cross_d(const double a0[2], const double a1[2], const double b0[2], const double b1[2])
+{
+    return (a1[0] - a0[0]) * (b1[1] - b0[1]) - (a1[1] - a0[1]) * (b1[0] - b0[0]);
+}
+
+/* Area of the convex quad (two triangles from node 0) and its longest edge. */
+static void mesh_cell_geometry(const hso_mesh *m, int64_t k, double *area, double *longest)
+{
+    double P[4][2];
+    for (int j = 0; j < 4; ++j) mesh_node(m, k, j, P[j]);
+    *area = 0.5 * (cross_d(P[0], P[1], P[0], P[2]) + cross_d(P[0], P[2], P[0], P[3]));
+    double lmax = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double ex = P[(j + 1) & 3][0] - P[j][0], ey = P[(j + 1) & 3][1] - P[j][1];
+        double l = sqrt(ex * ex + ey * ey);
+        if (l > lmax) lmax = l;
+    }
+    *longest = lmax;
+}
+
+/* Eq. 25's L_cell (reading: the cell's thickness): the smallest edge of a grid cell; a mesh
+ * quad's area over its longest edge, which is the same for a rectangle. */
+static double cell_length(const hso_case *c, int64_t k)
+{
+    if (c->mesh) {
+        double a, l;
+        mesh_cell_geometry(c->mesh, k, &a, &l);
+        return a / l;
+    }
+    double L = c->h[0];
+    for (int a = 1; a < c->dim; ++a) if (c->h[a] < L) L = c->h[a];
+    return L;
+}
+
 static double cell_volume(const hso_case *c, int64_t k)
 {
+    if (c->mesh) {
+        double a, l;
+        mesh_cell_geometry(c->mesh, k, &a, &l);
+        return a * c->h[2];
+    }
     double full = c->h[0] * c->h[1] * c->h[2];
     if (c->dim == 0 || c->body == HSO_BODY_NONE) return full;
     int64_t ijk[3];
@@ -339,8 +393,54 @@ static void maxwell_eq17(double T, double R, const uint32_t w[4], double C[3])
 /* Creation / destruction                                                                */
 /* ------------------------------------------------------------------------------------ */
 
+/* A mesh must hold convex counter-clockwise quads whose node ids are in range, and every
+ * edge must name a neighbour that names it back over the same two nodes, or a boundary
+ * code (WALL edges need body_T, INFLOW edges an inflow state). */
+static int validate_mesh(const hso_case *c)
+{
+    const hso_mesh *m = c->mesh;
+    if (c->dim != 2 || m->n_cells <= 0 || m->n_nodes <= 0 || !m->xy || !m->quad || !m->nbr)
+        return HSO_EARG;
+    if (c->body == HSO_BODY_SPHERE) return HSO_EARG;
+    for (int64_t k = 0; k < m->n_cells; ++k) {
+        for (int j = 0; j < 4; ++j) {
+            int32_t n = m->quad[4 * k + j];
+            if (n < 0 || n >= m->n_nodes) return HSO_EARG;
+        }
+        double P[4][2];
+        for (int j = 0; j < 4; ++j) mesh_node(m, k, j, P[j]);
+        for (int j = 0; j < 4; ++j)
+            if (!(cross_d(P[j], P[(j + 1) & 3], P[(j + 1) & 3], P[(j + 2) & 3]) > 0.0)) return HSO_EARG;
+        for (int j = 0; j < 4; ++j) {
+            int32_t nb = m->nbr[4 * k + j];
+            if (nb >= 0) {
+                if (nb >= m->n_cells) return HSO_EARG;
+                int back = 0;
+                for (int i = 0; i < 4; ++i)
+                    if (m->nbr[4 * (int64_t)nb + i] == (int32_t)k &&
+                        m->quad[4 * (int64_t)nb + i] == m->quad[4 * k + ((j + 1) & 3)] &&
+                        m->quad[4 * (int64_t)nb + ((i + 1) & 3)] == m->quad[4 * k + j]) back = 1;
+                if (!back) return HSO_EARG;
+            } else if (nb == HSO_EDGE_WALL) {
+                if (!(c->body_T > 0.0)) return HSO_EARG;
+            } else if (nb == HSO_EDGE_INFLOW) {
+                if (!(c->inflow.T > 0.0) || c->inflow.n < 0.0) return HSO_EARG;
+            } else if (nb != HSO_EDGE_OUTFLOW && nb != HSO_EDGE_SPECULAR) {
+                return HSO_EARG;
+            }
+        }
+    }
+    if (c->n_surf > 0 && (c->body != HSO_BODY_CYLINDER || !(c->body_r > 0.0))) return HSO_EARG;
+    return HSO_OK;
+}
+
 static int validate_case(const hso_case *c)
 {
+    if (c->mesh) {
+        for (int a = 0; a < 3; ++a) if (!(c->h[a] > 0.0)) return HSO_EARG;
+        if (!(c->F_N > 0.0) || !(c->T_sigma > 0.0) || c->capacity < 0 || !(c->dt_G > 0.0)) return HSO_EARG;
+        return validate_mesh(c);
+    }
     if (c->dim < 0 || c->dim > 3) return HSO_EARG;
     if (c->nx <= 0 || (c->dim >= 2 && c->ny <= 0) || (c->dim >= 3 && c->nz <= 0)) return HSO_EARG;
     for (int a = 0; a < 3; ++a) if (!(c->h[a] > 0.0)) return HSO_EARG;
@@ -370,6 +470,7 @@ static void free_case(ocase *c)
     free(c->x); free(c->v); free(c->cell); free(c->id);
     free(c->x2); free(c->v2); free(c->cell2); free(c->id2); free(c->count);
     free(c->faces); free(c->trace); free(c->surf);
+    free(c->lcell); free(c->mxy); free(c->mquad); free(c->mnbr);
 }
 
 static int alloc_particles(ocase *c, int64_t cap)
@@ -387,10 +488,38 @@ static int alloc_particles(ocase *c, int64_t cap)
 /* Inflow faces, in the order: side -x,+x,-y,+y,-z,+z; within a side the boundary cells in
  * x-fastest order.  A face is an inflow face if its side is HSO_BC_INFLOW and its centre
  * lies inside the slot box on every tangential axis where slot_hi > slot_lo. */
+/* Inflow edges of a mesh, in cell order and, within a cell, edge order.  The inward unit
+ * normal of edge j (node j -> node j+1 of a counter-clockwise quad) is (-e_y, e_x) / |e|;
+ * the face area is |e| times the depth h[2]. */
+static int build_mesh_faces(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    oc->faces = calloc((size_t)m->n_cells * 4, sizeof(face_t));
+    if (!oc->faces) return HSO_ECAP;
+    for (int64_t k = 0; k < m->n_cells; ++k)
+        for (int j = 0; j < 4; ++j) {
+            if (m->nbr[4 * k + j] != HSO_EDGE_INFLOW) continue;
+            double A[2], B[2];
+            mesh_node(m, k, j, A);
+            mesh_node(m, k, j + 1, B);
+            double ex = B[0] - A[0], ey = B[1] - A[1];
+            double len = sqrt(ex * ex + ey * ey);
+            double nrm[3] = { -ey / len, ex / len, 0.0 };
+            double flux = hso_inflow_number_flux(g, &c->inflow, nrm);
+            face_t *f = &oc->faces[oc->nfaces++];
+            f->cell = (int32_t)k;
+            f->side = j;
+            f->lambda = flux * (len * c->h[2]) * c->dt_G / c->F_N;
+        }
+    return HSO_OK;
+}
+
 static int build_faces(const hso_gas *g, ocase *oc)
 {
     const hso_case *c = &oc->p;
     oc->nfaces = 0;
+    if (c->mesh) return build_mesh_faces(g, oc);
     if (c->dim == 0) return HSO_OK;
     int64_t n[3] = { c->nx, c->dim >= 2 ? c->ny : 1, c->dim >= 3 ? c->nz : 1 };
     int64_t maxf = 0;
@@ -462,6 +591,23 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         }
         oc->p.region_box = oc->region_box;
         oc->p.region_state = oc->region_state;
+        if (c->mesh) {
+            const hso_mesh *m = c->mesh;
+            oc->mxy = malloc(sizeof(double) * 2 * (size_t)m->n_nodes);
+            oc->mquad = malloc(sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            oc->mnbr = malloc(sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            if (!oc->mxy || !oc->mquad || !oc->mnbr) { hso_destroy(s); return HSO_ECAP; }
+            memcpy(oc->mxy, m->xy, sizeof(double) * 2 * (size_t)m->n_nodes);
+            memcpy(oc->mquad, m->quad, sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            memcpy(oc->mnbr, m->nbr, sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            oc->mesh.n_nodes = m->n_nodes;
+            oc->mesh.n_cells = m->n_cells;
+            oc->mesh.xy = oc->mxy;
+            oc->mesh.quad = oc->mquad;
+            oc->mesh.nbr = oc->mnbr;
+            oc->p.mesh = &oc->mesh;
+        }
+        c = &oc->p;
         oc->ncells = ncells_of(c);
         int64_t nc = oc->ncells;
         if (c->dim == 0) {
@@ -473,9 +619,10 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         oc->sigc_max = calloc((size_t)nc, sizeof(double));
         oc->acc = calloc((size_t)nc * 13, sizeof(double));
         oc->dt_cell = calloc((size_t)nc, sizeof(double));
+        oc->lcell = calloc((size_t)nc, sizeof(double));
         oc->count = calloc((size_t)nc + 1, sizeof(int64_t));
         oc->trace = calloc((size_t)nc, sizeof(hso_trace));
-        if (!oc->vol || !oc->sigc_max || !oc->acc || !oc->dt_cell || !oc->count || !oc->trace)
+        if (!oc->vol || !oc->sigc_max || !oc->acc || !oc->dt_cell || !oc->lcell || !oc->count || !oc->trace)
             e = HSO_ECAP;
         if (c->n_surf < 0 || (c->n_surf > 0 && c->body == HSO_BODY_NONE)) e = HSO_EARG;
         if (!e && c->n_surf > 0) {
@@ -492,6 +639,7 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         double sc0 = hso_sigma_c(gas, 10.0 * sqrt(KB * c->T_sigma / gas->m));
         for (int64_t k = 0; k < nc; ++k) {
             oc->vol[k] = cell_volume(c, k);
+            oc->lcell[k] = c->dim > 0 ? cell_length(c, k) : 0.0;
             oc->sigc_max[k] = sc0;
             if (c->dim == 0) {
                 /* 0-D: the observation step equals the cell's own step r_k tau_0, with
@@ -525,17 +673,74 @@ static const hso_state *region_of(const hso_case *c, int64_t k)
     if (c->n_regions <= 0) return NULL;
     if (c->dim == 0) return &c->region_state[0];
     int64_t ijk[3];
-    cell_ijk(c, k, ijk);
+    double mc[2] = { 0.0, 0.0 };
+    if (c->mesh) {
+        /* a mesh cell's centre: the mean of its four nodes */
+        for (int j = 0; j < 4; ++j) {
+            double P[2];
+            mesh_node(c->mesh, k, j, P);
+            mc[0] = mc[0] + P[0];
+            mc[1] = mc[1] + P[1];
+        }
+        mc[0] = 0.25 * mc[0];
+        mc[1] = 0.25 * mc[1];
+    } else {
+        cell_ijk(c, k, ijk);
+    }
     for (int r = 0; r < c->n_regions; ++r) {
         const double *b = &c->region_box[6 * r];
         int in = 1;
         for (int a = 0; a < c->dim; ++a) {
-            double ctr = c->lo[a] + ((double)ijk[a] + 0.5) * c->h[a];
+            double ctr = c->mesh ? mc[a] : c->lo[a] + ((double)ijk[a] + 0.5) * c->h[a];
             if (!(ctr >= b[a] && ctr < b[3 + a])) in = 0;
         }
         if (in) return &c->region_state[r];
     }
     return NULL;
+}
+
+/* Position of the bilinear map of quad k at (u, w): (1-u)(1-w) P0 + u(1-w) P1 + u w P2 +
+ * (1-u) w P3, and its Jacobian J = (dX/du) x (dX/dw). */
+static double bilinear(const double P[4][2], double u, double w, double X[2])
+{
+    for (int a = 0; a < 2; ++a)
+        X[a] = (1.0 - u) * (1.0 - w) * P[0][a] + u * (1.0 - w) * P[1][a] + u * w * P[2][a] +
+               (1.0 - u) * w * P[3][a];
+    double du[2], dw[2];
+    for (int a = 0; a < 2; ++a) {
+        du[a] = (1.0 - w) * (P[1][a] - P[0][a]) + w * (P[2][a] - P[3][a]);
+        dw[a] = (1.0 - u) * (P[3][a] - P[0][a]) + u * (P[2][a] - P[1][a]);
+    }
+    return du[0] * dw[1] - du[1] * dw[0];
+}
+
+/* Step (1) in a mesh cell: a point uniform in the quad, by acceptance-rejection on the
+ * bilinear map: (u, w) uniform, accepted with probability J(u, w) / J_max (J is bilinear,
+ * so J_max is its largest corner value); draws as in the grid case (words 0, 1 the
+ * coordinates, word 2 the test); after MAX_POS_TRY rejections the map's centre. */
+static void mesh_place(const hso_mesh *m, int64_t k, uint64_t seed, int64_t q, double x[3])
+{
+    double P[4][2], X[2];
+    for (int j = 0; j < 4; ++j) mesh_node(m, k, j, P[j]);
+    double jmax = 0.0;
+    for (int cu = 0; cu < 2; ++cu)
+        for (int cw = 0; cw < 2; ++cw) {
+            double jc = bilinear(P, (double)cu, (double)cw, X);
+            if (jc > jmax) jmax = jc;
+        }
+    for (int t = 0; t < MAX_POS_TRY; ++t) {
+        uint32_t w[4];
+        hso_draw(seed, ST_INIT, (uint64_t)k, 0, (uint32_t)(1 + 128 * q + t), w);
+        double J = bilinear(P, hso_uniform(w[0]), hso_uniform(w[1]), X);
+        if (hso_uniform(w[2]) * jmax < J) {
+            x[0] = X[0];
+            x[1] = X[1];
+            return;
+        }
+    }
+    bilinear(P, 0.5, 0.5, X);
+    x[0] = X[0];
+    x[1] = X[1];
 }
 
 /* Step (1): particles uniformly at random inside each cell's fluid part, velocities
@@ -561,13 +766,15 @@ static int init_case(const hso_gas *g, ocase *oc)
         hso_draw(c->seed, ST_INIT, (uint64_t)k, 0, 0, w);
         int64_t N = (int64_t)floor(st->n * oc->vol[k] / c->F_N + hso_uniform(w[0]));
         if (oc->np + N > oc->cap) return HSO_ECAP;
-        int64_t ijk[3];
-        cell_ijk(c, k, ijk);
+        int64_t ijk[3] = { 0, 0, 0 };
+        if (!c->mesh) cell_ijk(c, k, ijk);
         for (int64_t q = 0; q < N; ++q) {
             int64_t i = oc->np++;
             double *x = &oc->x[3 * i];
             x[0] = x[1] = x[2] = 0.0;
-            if (c->dim > 0) {
+            if (c->mesh) {
+                mesh_place(c->mesh, k, c->seed, q, x);
+            } else if (c->dim > 0) {
                 int placed = 0;
                 for (int t = 0; t < MAX_POS_TRY && !placed; ++t) {
                     hso_draw(c->seed, ST_INIT, (uint64_t)k, 0, (uint32_t)(1 + 128 * q + t), w);
@@ -620,9 +827,72 @@ int hso_init_particles(hso_sim *s)
  * domain are removed).  Count floor(lambda_f + u); each entering particle is placed
  * uniformly on the face, with a flux-weighted normal speed, Gaussian tangential speeds
  * (Eq. 17 form) and a fresh id; it then moves for a uniform fraction of the step. */
+/* Inflow through a mesh edge: the same draws as a grid face, in the edge's frame.  n is the
+ * inward unit normal, t the in-plane unit tangent (-n_y, n_x) or its opposite, whichever has
+ * t_x + t_y >= 0 (for axis-aligned edges this is the grid face's first tangential axis), z
+ * the depth axis.  The point runs along +t from the edge end with the smaller t
+ * coordinate; c = n z_n / beta + t (U.t + a cos(2 pi R1) sqrt(-ln R2)) +
+ * e_z (U_z + a sin(2 pi R1) sqrt(-ln R2)). */
+static int inject_mesh(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    double beta = 1.0 / sqrt(2.0 * R * c->inflow.T);
+    for (int64_t f = 0; f < oc->nfaces; ++f) {
+        const face_t *fc = &oc->faces[f];
+        uint32_t w[4];
+        hso_draw(c->seed, ST_FACE, (uint64_t)f, st, 0, w);
+        double lam = c->adapt_dt ? fc->lambda * (oc->dt_cur / c->dt_G) : fc->lambda;
+        int64_t nf = (int64_t)floor(lam + hso_uniform(w[0]));
+        double A[2], B[2];
+        mesh_node(m, fc->cell, fc->side, A);
+        mesh_node(m, fc->cell, fc->side + 1, B);
+        double ex = B[0] - A[0], ey = B[1] - A[1];
+        double len = sqrt(ex * ex + ey * ey);
+        double nx = -ey / len, ny = ex / len;
+        double tx = -ny, ty = nx;
+        if (tx + ty < 0.0) { tx = -tx; ty = -ty; }
+        const double *S = A, *E = B;
+        if (B[0] * tx + B[1] * ty < A[0] * tx + A[1] * ty) { S = B; E = A; }
+        double sn = (c->inflow.u[0] * nx + c->inflow.u[1] * ny) * beta;
+        double ut = c->inflow.u[0] * tx + c->inflow.u[1] * ty;
+        for (int64_t q = 0; q < nf; ++q) {
+            if (oc->np >= oc->cap) return HSO_ECAP;
+            int64_t i = oc->np++;
+            double *x = &oc->x[3 * i], *v = &oc->v[3 * i];
+            uint32_t base = (uint32_t)(1 + 128 * q);
+            hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base, w);
+            double frac = hso_uniform(w[0]);
+            x[0] = S[0] + frac * (E[0] - S[0]);
+            x[1] = S[1] + frac * (E[1] - S[1]);
+            x[2] = 0.0;
+            hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 1, w);
+            double at = sqrt(2.0 * R * c->inflow.T);
+            double rr = sqrt(-log(hso_uniform(w[1])));
+            double vt = ut + at * cos(2.0 * PI * hso_uniform(w[0])) * rr;
+            v[2] = c->inflow.u[2] + at * sin(2.0 * PI * hso_uniform(w[0])) * rr;
+            uint32_t ws[4 * MAX_INJ_AR];
+            for (int att = 0; att < MAX_INJ_AR; ++att)
+                hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 2 + (uint32_t)att, &ws[4 * att]);
+            int used;
+            double z = hso_sample_normal_speed(sn, ws, MAX_INJ_AR, &used);
+            if (used < 0) oc->cnt.inject_cap++;
+            v[0] = nx * z / beta + tx * vt;
+            v[1] = ny * z / beta + ty * vt;
+            oc->cell[i] = fc->cell;
+            oc->id[i] = oc->next_id++;
+            oc->cnt.injected++;
+        }
+    }
+    return HSO_OK;
+}
+
 static int inject(const hso_gas *g, ocase *oc)
 {
     const hso_case *c = &oc->p;
+    if (c->mesh) return inject_mesh(g, oc);
     double R = KB / g->m;
     uint32_t st = (uint32_t)oc->step;
     int64_t n[3] = { c->nx, c->dim >= 2 ? c->ny : 1, c->dim >= 3 ? c->nz : 1 };
@@ -699,16 +969,24 @@ static double body_hit(const hso_case *c, const double x[3], const double v[3], 
  * c_n = sqrt(2 R T_w) sqrt(-ln R1): the printed "cos" is spurious); tangential speeds in
  * the Eq. 17 (y, z) form.  Tangent frame: cylinder t1 = (-n_y, n_x, 0), t2 = z; sphere
  * t1 = normalise(e x n) with e the axis of smallest |n_e| (first on ties), t2 = n x t1. */
-static void diffuse_reflect(const hso_case *c, double R, const double xh[3], const uint32_t w[4],
-                            double v[3])
+/* Outward unit normal of the body at the wall point xh. */
+static void body_normal(const hso_case *c, const double xh[3], double nrm[3])
 {
-    double nrm[3] = { 0.0, 0.0, 0.0 }, t1[3] = { 0.0, 0.0, 0.0 }, t2[3] = { 0.0, 0.0, 0.0 };
     int na = body_axes(c);
     double len = 0.0;
+    for (int k = 0; k < 3; ++k) nrm[k] = 0.0;
     for (int k = 0; k < na; ++k) { nrm[k] = xh[k] - c->body_c[k]; len = len + nrm[k] * nrm[k]; }
     len = sqrt(len);
     for (int k = 0; k < na; ++k) nrm[k] = nrm[k] / len;
-    if (c->body == HSO_BODY_CYLINDER) {
+}
+
+/* The same with the wall's unit normal nrm (pointing into the gas) given; a mesh wall and
+ * a cylinder use the planar frame. */
+static void diffuse_reflect_n(const hso_case *c, double R, const double nrm[3], const uint32_t w[4],
+                              double v[3])
+{
+    double t1[3] = { 0.0, 0.0, 0.0 }, t2[3] = { 0.0, 0.0, 0.0 };
+    if (c->mesh || c->body == HSO_BODY_CYLINDER) {
         t1[0] = -nrm[1]; t1[1] = nrm[0];
         t2[2] = 1.0;
     } else {
@@ -734,17 +1012,19 @@ static void diffuse_reflect(const hso_case *c, double R, const double xh[3], con
     for (int k = 0; k < 3; ++k) v[k] = cn * nrm[k] + cs * t1[k] + ct * t2[k];
 }
 
-/* Outward unit normal of the body at wall point xh, polar angle th from the upstream
- * stagnation direction s = -x, and the unit tangent of growing th,
- * t = (n cos th - s) / sin th (zero at the poles). */
-static void body_frame(const hso_case *c, const double xh[3], double nrm[3], double *th, double tan[3])
+static void diffuse_reflect(const hso_case *c, double R, const double xh[3], const uint32_t w[4],
+                            double v[3])
 {
-    int na = body_axes(c);
-    double len = 0.0;
-    for (int k = 0; k < 3; ++k) nrm[k] = 0.0;
-    for (int k = 0; k < na; ++k) { nrm[k] = xh[k] - c->body_c[k]; len = len + nrm[k] * nrm[k]; }
-    len = sqrt(len);
-    for (int k = 0; k < na; ++k) nrm[k] = nrm[k] / len;
+    double nrm[3];
+    body_normal(c, xh, nrm);
+    diffuse_reflect_n(c, R, nrm, w, v);
+}
+
+/* For the wall's outward unit normal nrm: its polar angle th from the upstream stagnation
+ * direction s = -x, and the unit tangent of growing th, t = (n cos th - s) / sin th (zero
+ * at the poles). */
+static void polar_frame(const double nrm[3], double *th, double tan[3])
+{
     double ct = -nrm[0];
     if (ct > 1.0) ct = 1.0;
     if (ct < -1.0) ct = -1.0;
@@ -756,12 +1036,12 @@ static void body_frame(const hso_case *c, const double xh[3], double nrm[3], dou
 
 /* Step (5) on the wall: the momentum and energy one diffuse reflection gives the body,
  * added to the surface element of the hit point (sampled steps only). */
-static void surface_hit(const hso_gas *g, ocase *oc, const double xh[3], const double vin[3],
+static void surface_hit(const hso_gas *g, ocase *oc, const double nrm[3], const double vin[3],
                         const double vout[3])
 {
     const hso_case *c = &oc->p;
-    double nrm[3], tan[3], th;
-    body_frame(c, xh, nrm, &th, tan);
+    double tan[3], th;
+    polar_frame(nrm, &th, tan);
     int k = (int)floor(th / PI * (double)c->n_surf);
     if (k < 0) k = 0;
     if (k > c->n_surf - 1) k = c->n_surf - 1;
@@ -800,7 +1080,11 @@ static int32_t move_particle(const hso_gas *g, ocase *oc, double *x, double *v, 
             hso_draw(c->seed, ST_PARTICLE, (uint64_t)id, st, (uint32_t)(DRAW_BOUNCE + b), w);
             double vin[3] = { v[0], v[1], v[2] };
             diffuse_reflect(c, R, x, w, v);
-            if (oc->surf && oc->step >= c->n_steady) surface_hit(g, oc, x, vin, v);
+            if (oc->surf && oc->step >= c->n_steady) {
+                double nrm[3];
+                body_normal(c, x, nrm);
+                surface_hit(g, oc, nrm, vin, v);
+            }
         }
     }
     for (int k = 0; k < c->dim; ++k) x[k] = x[k] + v[k] * t;
@@ -823,6 +1107,79 @@ static int32_t move_particle(const hso_gas *g, ocase *oc, double *x, double *v, 
         idx[k] = i;
     }
     return (int32_t)(idx[0] + (int64_t)c->nx * (idx[1] + (int64_t)c->ny * idx[2]));
+}
+
+/* Free transport on a mesh (Eq. 4 with face-to-face tracking): inside its convex cell the
+ * particle flies straight; the edge it leaves through is the one with an outward-moving
+ * normal (c.n > 0) reached first, at time d / (c.n) with d the distance to the edge's line
+ * along n (taken as 0 when rounding puts the particle just outside; ties go to the lower
+ * edge index; an exit at exactly the remaining time keeps the particle in the cell).  Across
+ * an interior edge the flight continues in the neighbour; OUTFLOW and INFLOW edges remove
+ * it; a SPECULAR edge mirrors c about the edge; a WALL edge re-emits it diffusely at body_T
+ * about the edge's unit normal (Eq. 30 reading as for the body), the wall sums taking that
+ * normal, and the remaining time goes on.  Caps as for the body (MAX_BOUNCE reflections),
+ * and MAX_CROSS edge crossings; a capped particle stops where it is.  Returns the new cell
+ * or -1. */
+static int32_t move_mesh(const hso_gas *g, ocase *oc, int32_t k, double *x, double *v, int64_t id,
+                         double t)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    int bounce = 0, cross = 0;
+    for (;;) {
+        double tmin = t;
+        int jmin = -1;
+        for (int j = 0; j < 4; ++j) {
+            double A[2], B[2];
+            mesh_node(m, k, j, A);
+            mesh_node(m, k, j + 1, B);
+            double ex = B[0] - A[0], ey = B[1] - A[1];
+            double vn = v[0] * ey - v[1] * ex;          /* c . (e_y, -e_x), outward */
+            if (!(vn > 0.0)) continue;
+            double d = (A[0] - x[0]) * ey - (A[1] - x[1]) * ex;
+            double tj = d / vn;
+            if (tj < 0.0) tj = 0.0;
+            if (tj < tmin) { tmin = tj; jmin = j; }
+        }
+        if (jmin < 0) {
+            x[0] = x[0] + v[0] * t;
+            x[1] = x[1] + v[1] * t;
+            return k;
+        }
+        x[0] = x[0] + v[0] * tmin;
+        x[1] = x[1] + v[1] * tmin;
+        t = t - tmin;
+        int32_t nb = m->nbr[4 * (int64_t)k + jmin];
+        if (nb >= 0) {
+            if (cross == MAX_CROSS) { oc->cnt.bounce_cap++; return k; }
+            ++cross;
+            k = nb;
+            continue;
+        }
+        if (nb == HSO_EDGE_OUTFLOW || nb == HSO_EDGE_INFLOW) return -1;
+        double A[2], B[2];
+        mesh_node(m, k, jmin, A);
+        mesh_node(m, k, jmin + 1, B);
+        double ex = B[0] - A[0], ey = B[1] - A[1];
+        double len = sqrt(ex * ex + ey * ey);
+        double nrm[3] = { -ey / len, ex / len, 0.0 };     /* into the cell */
+        if (nb == HSO_EDGE_SPECULAR) {
+            double vn = v[0] * nrm[0] + v[1] * nrm[1];
+            v[0] = v[0] - 2.0 * vn * nrm[0];
+            v[1] = v[1] - 2.0 * vn * nrm[1];
+            continue;
+        }
+        oc->cnt.wall_hits++;
+        if (bounce == MAX_BOUNCE) { oc->cnt.bounce_cap++; return k; }
+        uint32_t w[4];
+        hso_draw(c->seed, ST_PARTICLE, (uint64_t)id, st, (uint32_t)(DRAW_BOUNCE + bounce), w);
+        ++bounce;
+        double vin[3] = { v[0], v[1], v[2] };
+        diffuse_reflect_n(c, R, nrm, w, v);
+        if (oc->surf && oc->step >= c->n_steady) surface_hit(g, oc, nrm, vin, v);
+    }
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -959,9 +1316,8 @@ static void collide_cell(const hso_gas *g, ocase *oc, int64_t k, int64_t s0, int
         if (c->dim == 0) {
             dtc = dtG;
         } else {
-            /* Eq. 25 with L_cell = the cell's minimum edge */
-            double L = c->h[0];
-            for (int a = 1; a < c->dim; ++a) if (c->h[a] < L) L = c->h[a];
+            /* Eq. 25 */
+            double L = oc->lcell[k];
             double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
             dtc = L / (um + sqrt(g->gamma * R * T));
         }
@@ -1084,7 +1440,10 @@ static int step_case(const hso_gas *g, ocase *oc, int trace_on)
                 hso_draw(c->seed, ST_PARTICLE, (uint64_t)oc->id[i], (uint32_t)oc->step, DRAW_INJ_TIME, w);
                 t = oc->dt_cur * hso_uniform(w[0]);
             }
-            oc->cell[i] = move_particle(g, oc, &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
+            if (c->mesh)
+                oc->cell[i] = move_mesh(g, oc, oc->cell[i], &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
+            else
+                oc->cell[i] = move_particle(g, oc, &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
         }
         sort_by_cell(oc);
     } else {
@@ -1405,8 +1764,6 @@ int hso_dsmc_ratio(const hso_sim *s, int ci, double *ratio)
     if (!n || !u || !T) { free(n); free(u); free(T); return HSO_ECAP; }
     int e = hso_sample_moments((hso_sim *)s, ci, 0, n, u, T, NULL, NULL);
     double R = KB / g->m;
-    double L = c->h[0];
-    for (int a = 1; a < c->dim; ++a) if (c->h[a] < L) L = c->h[a];
     for (int64_t k = 0; !e && k < nc; ++k) {
         ratio[k] = 0.0;
         if (!(n[k] > 0.0) || !(T[k] > 0.0)) continue;
@@ -1416,7 +1773,7 @@ int hso_dsmc_ratio(const hso_sim *s, int ci, double *ratio)
             dtc = oc->dt_cell[k];
         } else {
             const double *U = &u[3 * k];
-            dtc = L / (sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + sqrt(g->gamma * R * T[k]));
+            dtc = oc->lcell[k] / (sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + sqrt(g->gamma * R * T[k]));
         }
         ratio[k] = dtc <= tau ? 1.0 : tau / dtc;
     }

@@ -22,6 +22,8 @@ extern "C" {
 enum { HSO_OK = 0, HSO_EARG = 1, HSO_ECAP = 2, HSO_ENUM = 3, HSO_ESTATE = 5 };
 enum { HSO_BC_OUTFLOW = 0, HSO_BC_SPECULAR = 1, HSO_BC_INFLOW = 2 };
 enum { HSO_BODY_NONE = 0, HSO_BODY_CYLINDER = 1, HSO_BODY_SPHERE = 2 };
+/* What lies across a mesh edge that has no neighbour cell. */
+enum { HSO_EDGE_OUTFLOW = -1, HSO_EDGE_INFLOW = -2, HSO_EDGE_WALL = -3, HSO_EDGE_SPECULAR = -4 };
 
 /* Gas model (Sec. 4 opening paragraph: argon, VHS, d_ref, T_ref, mu_ref, omega). */
 typedef struct {
@@ -32,6 +34,18 @@ typedef struct {
 typedef struct {
     double n, u[3], T;
 } hso_state;
+
+/* A body-fitted 2-D mesh of convex quadrilaterals (the paper's unstructured meshes,
+ * Sec. 4.2 and 4.4).  Cell k has nodes quad[4k..4k+3] counter-clockwise; edge j runs from
+ * node j to node (j+1) mod 4 and nbr[4k+j] is the cell across it, or an HSO_EDGE_* code:
+ * OUTFLOW removes particles that cross it, INFLOW also feeds the inflow state's one-way
+ * flux through it, WALL reflects diffusely at body_T, SPECULAR mirrors. */
+typedef struct {
+    int32_t n_nodes, n_cells;
+    const double *xy;                /* 2 per node                                     */
+    const int32_t *quad;             /* 4 per cell                                     */
+    const int32_t *nbr;              /* 4 per cell                                     */
+} hso_mesh;
 
 /* One flow case on a uniform Cartesian grid (cells x-fastest).  dim = 0 is the
  * spatially homogeneous (0-D) mode: nx cells, no transport, per-cell time steps. */
@@ -52,6 +66,11 @@ typedef struct {
     int64_t n_steady, capacity;
     int32_t n_surf;                  /* body surface elements sampled (0: none)        */
     int32_t adapt_dt;                /* 1: Eq. 26 global step, min of Eq. 25 over cells */
+    const hso_mesh *mesh;            /* NULL: the grid above; else an hso_mesh (dim 2): the
+                                        cells are its quads, h[2] the depth; nx, ny, lo,
+                                        h[0..1], bc and the slot are unused; body only
+                                        frames the surface elements (its wall is the WALL
+                                        edges) */
 } hso_case;
 
 typedef struct hso_sim hso_sim;

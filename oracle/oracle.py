@@ -20,6 +20,7 @@ _lib = None
 
 BC = {"outflow": 0, "specular": 1, "inflow": 2}
 BODY = {"none": 0, "cylinder": 1, "sphere": 2}
+EDGE = {"outflow": -1, "inflow": -2, "wall": -3, "specular": -4}
 ERRORS = {1: "argument", 2: "capacity", 3: "numeric", 5: "state"}
 
 
@@ -47,6 +48,11 @@ class State(C.Structure):
     _fields_ = [("n", C.c_double), ("u", C.c_double * 3), ("T", C.c_double)]
 
 
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_cells", C.c_int32), ("xy", C.POINTER(C.c_double)),
+                ("quad", C.POINTER(C.c_int32)), ("nbr", C.POINTER(C.c_int32))]
+
+
 class Case(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lo", C.c_double * 3), ("h", C.c_double * 3), ("bc", C.c_int32 * 6),
@@ -57,7 +63,7 @@ class Case(C.Structure):
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32),
-                ("adapt_dt", C.c_int32)]
+                ("adapt_dt", C.c_int32), ("mesh", C.POINTER(Mesh))]
 
 
 class Trace(C.Structure):
@@ -189,6 +195,18 @@ class _CaseHolder:
         c.capacity = int(d["capacity"])
         c.n_surf = int(d.get("n_surf", 0))
         c.adapt_dt = int(bool(d.get("adapt_dt", False)))
+        self.mesh = None
+        if d.get("mesh") is not None:
+            m = d["mesh"]
+            self.mxy = np.ascontiguousarray(np.asarray(m["xy"], dtype=np.float64).reshape(-1))
+            self.mquad = np.ascontiguousarray(np.asarray(m["quad"], dtype=np.int32).reshape(-1))
+            self.mnbr = np.ascontiguousarray(np.array(
+                [EDGE[v] if isinstance(v, str) else int(v) for v in np.asarray(m["nbr"]).reshape(-1)],
+                dtype=np.int32))
+            self.mesh = Mesh(self.mxy.size // 2, self.mquad.size // 4, _dp(self.mxy),
+                             self.mquad.ctypes.data_as(C.POINTER(C.c_int32)),
+                             self.mnbr.ctypes.data_as(C.POINTER(C.c_int32)))
+            c.mesh = C.pointer(self.mesh)
         self.c = c
 
 

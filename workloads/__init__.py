@@ -193,3 +193,134 @@ def jets_2d(n_jets=32, grids=((200, 100), (400, 200), (800, 400)), batch_seed=20
                            seed=seed0 + j, n_steady=n_steady,
                            capacity=int(nx * ny * ppc * cap_factor) + 4096))
     return cases
+
+
+# ------------------------------------------------------------------------------------
+# Body-fitted quadrilateral meshes (2-D).  A mesh is a dict of numpy arrays: xy (nodes, 2),
+# quad (cells, 4) node ids counter-clockwise, nbr (cells, 4) the cell across edge j
+# (node j -> node j+1) or an edge code string ("outflow", "inflow", "wall", "specular")
+# that each binding maps onto its own enum.
+# ------------------------------------------------------------------------------------
+
+# Ma 5 argon cylinder of Sec. 4.2: R = 1 m, T = 273 K, U = 1537.44 m/s, wall at 273 K,
+# n = 1.29438e20 m^-3 (Kn = 0.01) or 1.29438e19 m^-3 (Kn = 0.1).
+CYL5_N = 1.29438e20
+CYL5_T = 273.0
+CYL5_U = 1537.44
+CYL5_A = 307.81556420789946       # sqrt(gamma R T) at 273 K
+
+
+def _edge_codes(nbr_int, codes):
+    """Object array of neighbours with the boundary entries replaced by their code names."""
+    out = np.empty(nbr_int.shape, dtype=object)
+    for idx, v in np.ndenumerate(nbr_int):
+        out[idx] = int(v) if v >= 0 else codes[int(v)]
+    return out
+
+
+def quad_box_mesh(nx, ny, lo=(0.0, 0.0), h=(1.0, 1.0), sides=("outflow",) * 4, jitter=0.0,
+                  jitter_seed=5):
+    """Structured quads of the box lo + [0, nx h0] x [0, ny h1], cells x-fastest like the
+    grid's, nodes at lo + (i h0, j h1); sides = codes of the -x, +x, -y, +y boundaries.
+    jitter > 0 moves every interior node by a seeded uniform offset of up to jitter * h
+    per axis (kept below 0.25 so every quad stays convex)."""
+    assert 0.0 <= jitter < 0.25
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    x = lo[0] + ii * h[0]
+    y = lo[1] + jj * h[1]
+    if jitter > 0.0:
+        rng = np.random.default_rng(jitter_seed)
+        inner = (ii > 0) & (ii < nx) & (jj > 0) & (jj < ny)
+        x = np.where(inner, x + jitter * h[0] * rng.uniform(-1.0, 1.0, x.shape), x)
+        y = np.where(inner, y + jitter * h[1] * rng.uniform(-1.0, 1.0, y.shape), y)
+    xy = np.stack([x.reshape(-1), y.reshape(-1)], axis=1)
+    node = lambda i, j: i + (nx + 1) * j
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ci, cj = ci.reshape(-1), cj.reshape(-1)
+    quad = np.stack([node(ci, cj), node(ci + 1, cj), node(ci + 1, cj + 1), node(ci, cj + 1)], axis=1)
+    cell = lambda i, j: i + nx * j
+    nbr = np.stack([np.where(cj > 0, cell(ci, cj - 1), -3),
+                    np.where(ci < nx - 1, cell(ci + 1, cj), -2),
+                    np.where(cj < ny - 1, cell(ci, cj + 1), -4),
+                    np.where(ci > 0, cell(ci - 1, cj), -1)], axis=1)
+    codes = {-1: sides[0], -2: sides[1], -3: sides[2], -4: sides[3]}
+    return dict(xy=xy, quad=quad.astype(np.int32), nbr=_edge_codes(nbr, codes))
+
+
+def o_grid_mesh(n_theta=180, R=1.0, first=0.001, growth=1.1, r_out=3.0, inner="wall",
+                outer="inflow"):
+    """O-grid around a circle of radius R at the origin (Sec. 4.2: uniform circumferential
+    nodes, first layer `first`, radial growth `growth`): layers are added until the
+    outer radius reaches r_out.  Cell (i, j) lies between angles 2 pi i / n_theta and
+    2 pi (i + 1) / n_theta and radii r_j, r_j+1; cells angle-fastest.  Edge 0 is the ray
+    at angle i, edge 1 the outer arc, edge 2 the ray at i + 1, edge 3 the inner arc."""
+    r = [R]
+    d = first
+    while r[-1] < r_out:
+        r.append(r[-1] + d)
+        d *= growth
+    r = np.asarray(r)
+    nr = len(r) - 1
+    th = 2.0 * np.pi * np.arange(n_theta) / n_theta
+    xy = np.stack([np.outer(r, np.cos(th)).reshape(-1), np.outer(r, np.sin(th)).reshape(-1)], axis=1)
+    node = lambda i, j: (i % n_theta) + n_theta * j
+    ci, cj = np.meshgrid(np.arange(n_theta), np.arange(nr), indexing="xy")
+    ci, cj = ci.reshape(-1), cj.reshape(-1)
+    quad = np.stack([node(ci, cj), node(ci, cj + 1), node(ci + 1, cj + 1), node(ci + 1, cj)], axis=1)
+    cell = lambda i, j: (i % n_theta) + n_theta * j
+    nbr = np.stack([cell(ci - 1 + n_theta, cj),
+                    np.where(cj < nr - 1, cell(ci, cj + 1), -2),
+                    cell(ci + 1, cj),
+                    np.where(cj > 0, cell(ci, cj - 1), -1)], axis=1)
+    codes = {-1: inner, -2: outer}
+    return dict(xy=xy, quad=quad.astype(np.int32), nbr=_edge_codes(nbr, codes), radii=r)
+
+
+def mesh_twin(case, jitter=0.0):
+    """The 2-D grid case `case` (no body) as a body-fitted quad mesh of the same cells,
+    boundaries and parameters."""
+    assert case["dim"] == 2 and case["body"] == "none"
+    m = quad_box_mesh(case["nx"], case["ny"], lo=case["lo"][:2], h=case["h"][:2],
+                      sides=tuple(case["bc"][:4]), jitter=jitter)
+    out = dict(case)
+    out["mesh"] = m
+    return out
+
+
+def cylinder_ogrid(n_theta=180, first=0.001, growth=1.1, r_out=3.0, kn=0.01, ppc_outer=1000,
+                   seed=1, n_steady=1 << 40, cap_factor=1.5, n_surf=90, adapt_dt=False):
+    """Ma 5 argon flow past the unit cylinder of Sec. 4.2 on its O-grid (wall at 273 K,
+    freestream on the outer circle); F_N puts ppc_outer particles in the outermost cells at
+    the freestream density; dt_G = first / (U + a) (the Eq. 26 value at freestream).  The
+    wall is sampled in n_surf bands of polar angle."""
+    m = o_grid_mesh(n_theta=n_theta, first=first, growth=growth, r_out=r_out)
+    r = m["radii"]
+    n = CYL5_N * (0.01 / kn)
+    st = dict(n=n, u=(CYL5_U, 0.0, 0.0), T=CYL5_T)
+    outer_area = 0.5 * (r[-1] ** 2 - r[-2] ** 2) * (2.0 * np.pi / n_theta)
+    fn = n * outer_area / ppc_outer
+    total = n * np.pi * (r[-1] ** 2 - r[0] ** 2) / fn
+    big = r[-1] + 1.0
+    return _case(dim=2, h=(1.0, 1.0, 1.0), inflow=st, body="cylinder", body_c=(0.0, 0.0, 0.0),
+                 body_r=1.0, body_T=CYL5_T, regions=[((-big, -big, 0.0, big, big, 1.0), st)],
+                 F_N=fn, dt_G=first / (CYL5_U + CYL5_A), T_sigma=CYL5_T * (1.0 + 25.0 / 3.0), seed=seed,
+                 n_steady=n_steady, capacity=int(total * cap_factor) + 4096, n_surf=n_surf,
+                 adapt_dt=adapt_dt, mesh=m)
+
+
+def free_molecular_ogrid(s=1.0, T=300.0, T_w=500.0, n=1.0e13, R=0.3, r_out=1.0, n_theta=72,
+                         first=0.02, growth=1.1, total=16000, n_surf=6, seed=9):
+    """free_molecular_body's cylinder on a body-fitted O-grid: a diffuse cylinder of radius R
+    at T_w inside a circle of radius r_out whose edges are freestream edges, filled with the
+    undisturbed stream (speed ratio s along +x); about `total` particles; every step
+    sampled."""
+    m = o_grid_mesh(n_theta=n_theta, R=R, first=first, growth=growth, r_out=r_out)
+    r = m["radii"]
+    U = s * math.sqrt(2.0 * R_ARGON * T)
+    st = dict(n=n, u=(U, 0.0, 0.0), T=T)
+    fn = n * math.pi * (r[-1] ** 2 - r[0] ** 2) / total
+    big = r[-1] + 1.0
+    return _case(dim=2, h=(1.0, 1.0, 1.0), inflow=st, body="cylinder", body_c=(0.0, 0.0, 0.0),
+                 body_r=R, body_T=T_w, regions=[((-big, -big, 0.0, big, big, 1.0), st)], F_N=fn,
+                 dt_G=0.5 * first / (U + 3.0 * math.sqrt(R_ARGON * T)), T_sigma=T, seed=seed,
+                 n_steady=0, capacity=int(2 * total) + 4096, n_surf=n_surf, mesh=m)
