@@ -54,6 +54,10 @@ typedef enum {
 typedef enum { HS_FP64 = 0, HS_FP32_MIXED = 1 } hs_precision;
 typedef enum { HS_BC_OUTFLOW = 0, HS_BC_SPECULAR = 1, HS_BC_INFLOW = 2 } hs_bc;
 typedef enum { HS_BODY_NONE = 0, HS_BODY_CYLINDER = 1, HS_BODY_SPHERE = 2 } hs_body;
+/* What lies across a mesh edge that has no neighbour cell (see hs_mesh). */
+typedef enum {
+    HS_EDGE_OUTFLOW = -1, HS_EDGE_INFLOW = -2, HS_EDGE_WALL = -3, HS_EDGE_SPECULAR = -4
+} hs_edge;
 
 enum {
     HS_FLAG_TRACE = 1,         /* keep a per-cell record of the last step (hs_last_trace)  */
@@ -86,7 +90,23 @@ typedef struct {
     double n, u[3], T;
 } hs_state;
 
-/* One flow case on a uniform Cartesian grid.
+/* A body-fitted 2-D mesh of convex quadrilaterals, the paper's unstructured meshes of
+ * Sec. 4.2 (the cylinder's O-grid) and Sec. 4.3 (the jet's quads), tracked face to face.
+ *  xy: 2 doubles per node (m).  quad: 4 node ids per cell, counter-clockwise.
+ *  nbr: 4 per cell; entry j is what lies across edge j (node j -> node (j+1) mod 4): the
+ *    neighbour cell, which must name this cell back across the same two nodes, or an
+ *    hs_edge code: OUTFLOW removes particles that cross it; INFLOW removes them and feeds
+ *    the case's inflow state's one-way flux through the edge; WALL re-emits them diffusely
+ *    at body_T about the edge's normal; SPECULAR mirrors them.
+ * Arrays are host memory, read and copied at init (the caller keeps ownership). */
+typedef struct {
+    int32_t n_nodes, n_cells;
+    const double *xy;
+    const int32_t *quad;
+    const int32_t *nbr;
+} hs_mesh;
+
+/* One flow case on a uniform Cartesian grid or (mesh != NULL) on a quad mesh.
  *  dim 1..3: cells nx (x ny (x nz)); lo = lower corner, h = cell edges; for unused axes
  *    h is the unit depth/area, so every cell volume is h0 h1 h2 times its fluid fraction.
  *  dim 0: nx independent homogeneous cells (no transport), each with its own step
@@ -110,7 +130,13 @@ typedef struct {
  *    step s is the minimum over the case's active cells (N >= 2, T > 0) of the Eq. 25
  *    local step from step s's Step (3) moments, the first step uses dt_G, a step without
  *    active cells keeps the last value, and inflow counts scale with the step (dim >= 1;
- *    see hs_step_dt). */
+ *    see hs_step_dt).
+ *  mesh: NULL for the grid; else dim must be 2 and the cells are the mesh's quads, numbered
+ *    as in the mesh, with volume = area x h[2] (h[2] the depth) and Eq. 25's L_cell = area /
+ *    longest edge; nx, ny, nz, lo, h[0..1], bc and the slot are ignored; regions select
+ *    cells by the mean of their four nodes; body may be NONE or CYLINDER and only frames
+ *    the surface elements (polar-angle bands about the WALL edges' normals; body_r sets the
+ *    element areas and A_ref), the wall itself being the WALL edges at body_T. */
 typedef struct {
     int32_t dim, nx, ny, nz;
     double lo[3], h[3];
@@ -128,6 +154,7 @@ typedef struct {
     int64_t n_steady, capacity;
     int32_t n_surf;
     int32_t adapt_dt;
+    const hs_mesh *mesh;
 } hs_case;
 
 typedef struct hs_sim hs_sim;
@@ -180,7 +207,8 @@ hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, doubl
 /* Checkpoint of one case (native precision, bit-exact resume).  Layout: hs_state_header
  * (version 2; only that version is accepted),
  * then pos[3][np], vel[3][np] (element size 8 for HS_FP64, 4 for HS_FP32_MIXED; pos is
- * the cell-relative position in [0,1) per axis), cell[np] (int32, case-local),
+ * the cell-relative position in [0,1) per axis; on a mesh, x and y relative to the cell's
+ * first node, in m), cell[np] (int32, case-local),
  * id[np] (int64), sigc_max[ncells], acc[ncells][13] (double).  Particles are sorted by
  * cell.  hs_state_bytes gives the size.  Importing requires cells non-decreasing; it sets
  * the sim's step counter (shared by all cases). */
@@ -241,7 +269,9 @@ hs_status hs_set_grid(hs_sim *sim, int which, int32_t blocks);
  * reflection at the body during a sampled step (step >= n_steady) adds to its element:
  * 1, dP.n, dP.t, dE and dP (x, y, z), with dP = m F_N (c_in - c_out) the momentum given to
  * the wall, dE = m F_N (|c_in|^2 - |c_out|^2) / 2 the energy, n the outward normal and t
- * the unit tangent of growing polar angle at the hit point.
+ * the unit tangent of growing polar angle at the hit point.  On a mesh, the wall points are
+ * the WALL edges and n is the unit normal of the edge hit (pointing into the gas); its polar
+ * angle chooses the element.
  *
  * hs_surface_sums copies these raw sums of case_id, n_surf x 7 doubles, into host memory.
  * hs_surface_sample gives their time averages over the S sampled steps of length dt_G:

@@ -1118,7 +1118,8 @@ static int32_t move_particle(const hso_gas *g, ocase *oc, double *x, double *v, 
  * it; a SPECULAR edge mirrors c about the edge; a WALL edge re-emits it diffusely at body_T
  * about the edge's unit normal (Eq. 30 reading as for the body), the wall sums taking that
  * normal, and the remaining time goes on.  Caps as for the body (MAX_BOUNCE reflections),
- * and MAX_CROSS edge crossings; a capped particle stops where it is.  Returns the new cell
+ * and MAX_CROSS edge crossings and mirrorings together; a capped particle stops where it
+ * is.  Returns the new cell
  * or -1. */
 static int32_t move_mesh(const hso_gas *g, ocase *oc, int32_t k, double *x, double *v, int64_t id,
                          double t)
@@ -1166,6 +1167,8 @@ static int32_t move_mesh(const hso_gas *g, ocase *oc, int32_t k, double *x, doub
         double len = sqrt(ex * ex + ey * ey);
         double nrm[3] = { -ey / len, ex / len, 0.0 };     /* into the cell */
         if (nb == HSO_EDGE_SPECULAR) {
+            if (cross == MAX_CROSS) { oc->cnt.bounce_cap++; return k; }
+            ++cross;
             double vn = v[0] * nrm[0] + v[1] * nrm[1];
             v[0] = v[0] - 2.0 * vn * nrm[0];
             v[1] = v[1] - 2.0 * vn * nrm[1];

@@ -15,6 +15,7 @@ constexpr int kMaxCases = 256;
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;   // +inf as double bits
 constexpr int kSurfCopies = 16;     // copies of the wall sums, so few atomics share an address
 constexpr int kMaxBounce = 8;        // body reflections per particle per step
+constexpr int kMaxCross = 4096;      // mesh edge crossings per particle per step
 constexpr int kMaxShakhov = 64;      // Shakhov acceptance-rejection attempts
 constexpr int kMaxInjectAR = 64;     // inflow normal-speed attempts
 constexpr int kMaxPosTry = 64;       // initial-position attempts in a cut cell
@@ -54,11 +55,12 @@ struct CaseDev {
     int32_t bb_lo[3], bb_hi[3];     // cell-index box around the body (1-cell margin)
     int32_t surf0, n_surf;          // body surface elements: first of the batch, count
     int32_t adapt_dt;               // 1: Eq. 26 global step
+    int32_t mesh;                   // 1: cells are quads of the mesh arrays of Ctx
 };
 
 struct FaceDev {
     int32_t cell;       // global boundary cell
-    int32_t side;       // 0..5
+    int32_t side;       // grid: 0..5 = -x,+x,-y,+y,-z,+z; mesh: the cell's edge 0..3
     int32_t case_id;
     int32_t local;      // face index within the case (Philox entity)
     double lambda;      // expected entering particles per step
@@ -128,6 +130,12 @@ struct Ctx {
     int32_t *tile_case;           // case of each tile (tiles never span cases)
     int32_t *work;                // body worklist (particle indices)
     TraceDev *trace;              // nullptr unless tracing
+    // quad meshes (nullptr without a mesh case): node coordinates (2 per node, all cases),
+    // per global cell its 4 global node ids, the 4 neighbours (global cell or hs_edge code)
+    // and (volume, L_cell)
+    const double *mxy;
+    const int32_t *mquad, *mnbr;
+    const double *mgeo;
     Globals *g;
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
     int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension

@@ -210,19 +210,27 @@ __device__ __forceinline__ double body_hit(const CaseDev &cs, const double X[3],
 // sqrt(2RT_w) sqrt(-ln R1), tangential speeds sqrt(2RT_w) {cos, sin}(2 pi R3) sqrt(-ln R4)
 // along t1 and t2 (cylinder: t1 = (-n_y, n_x, 0), t2 = z; sphere: t1 = e x n normalised,
 // e the axis of smallest |n_e|, t2 = n x t1).
-__device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, const double X[3], W4 w,
-                                       double V[3])
+// Outward unit normal of the body at the wall point X.
+__device__ __forceinline__ void body_normal(const CaseDev &cs, const double X[3], double nr[3])
 {
-    double nr[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
     const int na = body_axes(cs);
     double len = 0.0;
+    for (int k = 0; k < 3; ++k) nr[k] = 0.0;
     for (int k = 0; k < 3; ++k) if (k < na) {
         nr[k] = X[k] - cs.body_c[k];
         len = len + nr[k] * nr[k];
     }
     len = sqrt(len);
     for (int k = 0; k < 3; ++k) if (k < na) nr[k] = nr[k] / len;
-    if (cs.body == HS_BODY_CYLINDER) {
+}
+
+// The re-emission about a given unit wall normal nr (pointing into the gas); a mesh wall
+// uses the planar frame of the cylinder.
+__device__ inline void diffuse_reflect_n(const GasDev &gas, const CaseDev &cs, const double nr[3], W4 w,
+                                         double V[3])
+{
+    double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+    if (cs.mesh || cs.body == HS_BODY_CYLINDER) {
         t1[0] = -nr[1];
         t1[1] = nr[0];
         t2[2] = 1.0;
@@ -250,6 +258,14 @@ __device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, con
     for (int k = 0; k < 3; ++k) V[k] = cn * nr[k] + ct1 * t1[k] + ct2 * t2[k];
 }
 
+__device__ inline void diffuse_reflect(const GasDev &gas, const CaseDev &cs, const double X[3], W4 w,
+                                       double V[3])
+{
+    double nr[3];
+    body_normal(cs, X, nr);
+    diffuse_reflect_n(gas, cs, nr, w, V);
+}
+
 struct MoveStats {
     int hits, capped;
 };
@@ -264,18 +280,10 @@ struct MoveStats {
 // surface element of the hit point X.  Elements are bands of the polar angle th from the
 // upstream stagnation direction -x; dP is split on the outward normal n and on the unit
 // tangent of growing th, t = (n cos th + x) / sin th (zero at the poles).
-__device__ inline void surface_hit(const GasDev &gas, const CaseDev &cs, const double X[3], const double Vin[3],
-                                   const double Vout[3], double *surf)
+// (On a mesh wall, n is the unit normal of the edge hit.)
+__device__ inline void surface_hit_n(const GasDev &gas, const CaseDev &cs, const double nr[3], const double Vin[3],
+                                     const double Vout[3], double *surf)
 {
-    const int na = body_axes(cs);
-    double nr[3] = {0.0, 0.0, 0.0};
-    double len = 0.0;
-    for (int k = 0; k < 3; ++k) if (k < na) {
-        nr[k] = X[k] - cs.body_c[k];
-        len = len + nr[k] * nr[k];
-    }
-    len = sqrt(len);
-    for (int k = 0; k < 3; ++k) if (k < na) nr[k] = nr[k] / len;
     double ct = -nr[0];
     ct = ct > 1.0 ? 1.0 : (ct < -1.0 ? -1.0 : ct);
     const double th = acos(ct);
@@ -298,6 +306,14 @@ __device__ inline void surface_hit(const GasDev &gas, const CaseDev &cs, const d
     unsafeAtomicAdd(&S[2], dP[0] * tg[0] + dP[1] * tg[1] + dP[2] * tg[2]);
     unsafeAtomicAdd(&S[3], 0.5 * w * (ein - eout));
     for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&S[4 + a], dP[a]);
+}
+
+__device__ inline void surface_hit(const GasDev &gas, const CaseDev &cs, const double X[3], const double Vin[3],
+                                   const double Vout[3], double *surf)
+{
+    double nr[3];
+    body_normal(cs, X, nr);
+    surface_hit_n(gas, cs, nr, Vin, Vout, surf);
 }
 
 template <typename P>
@@ -422,6 +438,7 @@ template <typename P>
 __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v[3], double t, bool full_step,
                                       bool &vchg)
 {
+    if (cs.mesh) return -2;     // meshes are tracked face to face by move_mesh
     const int dim = cs.dim;
     int ijk[3];
     cell_ijk(cs, local, ijk);
@@ -465,6 +482,116 @@ __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v
         ijk[a] = i;
     }
     return cell_local(cs, ijk);
+}
+
+// ------------------------------------------------------------------------------------
+// Quad meshes
+// ------------------------------------------------------------------------------------
+
+// The four nodes of global mesh cell g (counter-clockwise).
+__device__ __forceinline__ void mesh_nodes(const Ctx &C, int g, double P[4][2])
+{
+    const int4 q = ((const int4 *)C.mquad)[g];
+    const int id[4] = {q.x, q.y, q.z, q.w};
+    for (int j = 0; j < 4; ++j) {
+        const double2 p = ((const double2 *)C.mxy)[id[j]];
+        P[j][0] = p.x;
+        P[j][1] = p.y;
+    }
+}
+
+__device__ __forceinline__ double2 mesh_origin(const Ctx &C, int g)
+{
+    return ((const double2 *)C.mxy)[C.mquad[4 * (size_t)g]];
+}
+
+// Point of the bilinear map of a quad at (u, w) and the map's Jacobian (dX/du x dX/dw).
+__device__ __forceinline__ double bilinear(const double P[4][2], double u, double w, double X[2])
+{
+    for (int a = 0; a < 2; ++a)
+        X[a] = (1.0 - u) * (1.0 - w) * P[0][a] + u * (1.0 - w) * P[1][a] + u * w * P[2][a] +
+               (1.0 - u) * w * P[3][a];
+    double du[2], dw[2];
+    for (int a = 0; a < 2; ++a) {
+        du[a] = (1.0 - w) * (P[1][a] - P[0][a]) + w * (P[2][a] - P[3][a]);
+        dw[a] = (1.0 - u) * (P[3][a] - P[0][a]) + u * (P[2][a] - P[1][a]);
+    }
+    return du[0] * dw[1] - du[1] * dw[0];
+}
+
+// Free flight (Eq. 4) on a quad mesh by face-to-face tracking, in FP64 on absolute
+// coordinates (the stored position is relative to the cell's first node).  Inside the
+// convex cell the path leaves through the edge with c.n > 0 (n the outward normal) reached
+// first, at d / (c.n) with d the distance to the edge's line (0 if rounding put the point
+// just outside; ties to the lower edge; an exit exactly at the remaining time stays).
+// Interior edges pass the particle on; OUTFLOW / INFLOW edges remove it; SPECULAR edges
+// mirror c; WALL edges re-emit it diffusely about the edge's unit normal (the wall sums
+// taking that normal).  kMaxBounce reflections and kMaxCross crossings and mirrorings
+// together are the caps (the particle then stops where it is), so the loop always ends.  Returns the new global cell, or -1.
+template <typename P>
+__device__ inline int move_mesh(const Ctx &C, const CaseDev &cs, int g, P xr[3], P v[3], int64_t &id,
+                                const int64_t *idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
+{
+    double Pn[4][2];
+    mesh_nodes(C, g, Pn);
+    double X[2] = {Pn[0][0] + (double)xr[0], Pn[0][1] + (double)xr[1]};
+    double V[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    int bounce = 0, cross = 0;
+    for (;;) {
+        double tmin = t;
+        int jmin = -1;
+        for (int j = 0; j < 4; ++j) {
+            const double *A = Pn[j], *B = Pn[(j + 1) & 3];
+            const double ex = B[0] - A[0], ey = B[1] - A[1];
+            const double vn = V[0] * ey - V[1] * ex;
+            if (!(vn > 0.0)) continue;
+            const double d = (A[0] - X[0]) * ey - (A[1] - X[1]) * ex;
+            double tj = d / vn;
+            if (tj < 0.0) tj = 0.0;
+            if (tj < tmin) { tmin = tj; jmin = j; }
+        }
+        if (jmin < 0) {
+            X[0] = X[0] + V[0] * t;
+            X[1] = X[1] + V[1] * t;
+            break;
+        }
+        X[0] = X[0] + V[0] * tmin;
+        X[1] = X[1] + V[1] * tmin;
+        t = t - tmin;
+        const int nb = C.mnbr[4 * (size_t)g + jmin];
+        if (nb >= 0) {
+            if (cross == kMaxCross) { ms.capped++; break; }
+            ++cross;
+            g = nb;
+            mesh_nodes(C, g, Pn);
+            continue;
+        }
+        if (nb == HS_EDGE_OUTFLOW || nb == HS_EDGE_INFLOW) return -1;
+        const double *A = Pn[jmin], *B = Pn[(jmin + 1) & 3];
+        const double ex = B[0] - A[0], ey = B[1] - A[1];
+        const double len = sqrt(ex * ex + ey * ey);
+        const double nr[3] = {-ey / len, ex / len, 0.0};
+        if (nb == HS_EDGE_SPECULAR) {
+            if (cross == kMaxCross) { ms.capped++; break; }
+            ++cross;
+            const double vn = V[0] * nr[0] + V[1] * nr[1];
+            V[0] = V[0] - 2.0 * vn * nr[0];
+            V[1] = V[1] - 2.0 * vn * nr[1];
+            continue;
+        }
+        ms.hits++;
+        if (bounce == kMaxBounce) { ms.capped++; break; }
+        if (id < 0) id = *idsrc;
+        const W4 w = draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + bounce);
+        ++bounce;
+        const double Vin[3] = {V[0], V[1], V[2]};
+        diffuse_reflect_n(C.gas, cs, nr, w, V);
+        if (surf) surface_hit_n(C.gas, cs, nr, Vin, V, surf);
+    }
+    xr[0] = (P)(X[0] - Pn[0][0]);
+    xr[1] = (P)(X[1] - Pn[0][1]);
+    for (int a = 0; a < 3; ++a) v[a] = (P)V[a];
+    return g;
 }
 
 // Flux-weighted normal speed z = beta c_n of a drifting Maxwellian entering a face,

@@ -168,6 +168,26 @@ __device__ inline const StateDev *region_of(const Ctx &C, const CaseDev &cs, con
     return nullptr;
 }
 
+// Region of a mesh cell: the first box holding the mean of its four nodes.
+__device__ inline const StateDev *region_of_mesh(const Ctx &C, const CaseDev &cs, int g)
+{
+    if (cs.nregions <= 0) return nullptr;
+    double P[4][2];
+    mesh_nodes(C, g, P);
+    double mc[2] = {0.0, 0.0};
+    for (int j = 0; j < 4; ++j) {
+        mc[0] = mc[0] + P[j][0];
+        mc[1] = mc[1] + P[j][1];
+    }
+    mc[0] = 0.25 * mc[0];
+    mc[1] = 0.25 * mc[1];
+    for (int r = 0; r < cs.nregions; ++r) {
+        const double *b = &C.region_box[6 * (cs.region0 + r)];
+        if (mc[0] >= b[0] && mc[0] < b[3] && mc[1] >= b[1] && mc[1] < b[4]) return &C.region_state[cs.region0 + r];
+    }
+    return nullptr;
+}
+
 __global__ void k_init_cells(Ctx C, int fill)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,13 +200,14 @@ __global__ void k_init_cells(Ctx C, int fill)
     for (int a = 0; a < 3; ++a) if (a < cs.dim) full *= kSub;
     const double vfull = cs.h[0] * cs.h[1] * cs.h[2];
     double vol = vfull;
-    if (cs.body != HS_BODY_NONE && cs.dim > 0) vol = (double)cut_count(cs, ijk) / (double)full * vfull;
+    if (cs.mesh) vol = C.mgeo[2 * (size_t)g];
+    else if (cs.body != HS_BODY_NONE && cs.dim > 0) vol = (double)cut_count(cs, ijk) / (double)full * vfull;
     C.vol[g] = vol;
     C.sigc[g] = cs.sigc0;
     for (int j = 0; j < 13; ++j) C.acc[13 * (size_t)g + j] = 0.0;
     int N = 0;
     if (fill && vol > 0.0) {
-        const StateDev *st = region_of(C, cs, ijk);
+        const StateDev *st = cs.mesh ? region_of_mesh(C, cs, g) : region_of(C, cs, ijk);
         if (st && st->n > 0.0) {
             const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, 0);
             N = (int)floor(st->n * vol / cs.F_N + unid(w.x));
@@ -210,13 +231,35 @@ __global__ void k_init_fill(Ctx C)
     const int lc = g - cs.cell0;
     int ijk[3];
     cell_ijk(cs, lc, ijk);
-    const StateDev *st = region_of(C, cs, ijk);
+    const StateDev *st = cs.mesh ? region_of_mesh(C, cs, g) : region_of(C, cs, ijk);
     Parts<P> B(C.buf[0]);
     const int64_t id0 = (int64_t)s - C.cstart[cs.cell0];
     const double a = sqrt(2.0 * C.gas.R * st->T);
+    double Pq[4][2], jmax = 0.0;
+    if (cs.mesh) {
+        mesh_nodes(C, g, Pq);
+        for (int cu = 0; cu < 2; ++cu)
+            for (int cw = 0; cw < 2; ++cw) {
+                double X[2];
+                const double jc = bilinear(Pq, (double)cu, (double)cw, X);
+                if (jc > jmax) jmax = jc;
+            }
+    }
     for (int q = 0; q < N; ++q) {
         double xr[3] = {0.0, 0.0, 0.0};
-        if (cs.dim > 0) {
+        if (cs.mesh) {
+            // uniform in the quad: the bilinear map accepted with probability J / J_max
+            double X[2];
+            bool placed = false;
+            for (int t = 0; t < kMaxPosTry && !placed; ++t) {
+                const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, (uint32_t)(1 + 128 * q + t));
+                const double J = bilinear(Pq, unid(w.x), unid(w.y), X);
+                placed = unid(w.z) * jmax < J;
+            }
+            if (!placed) bilinear(Pq, 0.5, 0.5, X);
+            xr[0] = X[0] - Pq[0][0];
+            xr[1] = X[1] - Pq[0][1];
+        } else if (cs.dim > 0) {
             bool placed = false;
             for (int t = 0; t < kMaxPosTry && !placed; ++t) {
                 const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, (uint32_t)(1 + 128 * q + t));
@@ -252,7 +295,7 @@ __global__ void k_init_fill(Ctx C)
         const size_t i = (size_t)s + q;
         for (int d = 0; d < 3; ++d) {
             P x = (P)xr[d];
-            if (!(x < (P)1)) x = Real<P>::below_one();
+            if (!cs.mesh && !(x < (P)1)) x = Real<P>::below_one();
             if (d < cs.dim) B.pos[d][i] = x;
             B.vel[d][i] = (P)(st->u[d] + C3[d]);
         }
@@ -513,6 +556,45 @@ __global__ void k_inject_fill(Ctx C)
     const int64_t slot0 = (int64_t)C.g->n_live + C.face_start[f];
     const int64_t id0 = C.g->inj_id_base[fd.case_id] + (C.face_start[f] - C.face_start[cs.face0]);
     long long capped = 0;
+    if (cs.mesh) {
+        // a mesh edge: inward normal n = (-e_y, e_x) / |e|, in-plane tangent t = (-n_y, n_x)
+        // or its opposite (t_x + t_y >= 0), points along +t from the end of smaller t.x
+        double Pq[4][2];
+        mesh_nodes(C, fd.cell, Pq);
+        const double *A = Pq[fd.side], *Bn = Pq[(fd.side + 1) & 3];
+        const double ex = Bn[0] - A[0], ey = Bn[1] - A[1];
+        const double len = sqrt(ex * ex + ey * ey);
+        const double nx = -ey / len, ny = ex / len;
+        double tx = -ny, ty = nx;
+        if (tx + ty < 0.0) { tx = -tx; ty = -ty; }
+        const double *S0 = A, *E0 = Bn;
+        if (Bn[0] * tx + Bn[1] * ty < A[0] * tx + A[1] * ty) { S0 = Bn; E0 = A; }
+        const double snm = (cs.in_u[0] * nx + cs.in_u[1] * ny) * beta;
+        const double ut = cs.in_u[0] * tx + cs.in_u[1] * ty;
+        for (int q = lane; q < cnt; q += 64) {
+            const uint32_t base = (uint32_t)(1 + 128 * q);
+            const W4 wp = draw(cs, kStreamFace, (uint64_t)fd.local, st, base);
+            const double frac = unid(wp.x);
+            const double X0 = S0[0] + frac * (E0[0] - S0[0]), X1 = S0[1] + frac * (E0[1] - S0[1]);
+            const W4 wv = draw(cs, kStreamFace, (uint64_t)fd.local, st, base + 1);
+            const double rr = sqrt(-log(unid(wv.y)));
+            double sn2, cs2;
+            sincospi(2.0 * unid(wv.x), &sn2, &cs2);
+            const double vt = ut + ath * cs2 * rr;
+            const double vz = cs.in_u[2] + ath * sn2 * rr;
+            int used;
+            const double z = normal_speed(cs, (uint32_t)fd.local, st, base + 2, snm, used);
+            if (used < 0) ++capped;
+            const size_t i = (size_t)(slot0 + q);
+            S.pos[0][i] = (P)(X0 - Pq[0][0]);
+            S.pos[1][i] = (P)(X1 - Pq[0][1]);
+            S.vel[0][i] = (P)(nx * z / beta + tx * vt);
+            S.vel[1][i] = (P)(ny * z / beta + ty * vt);
+            S.vel[2][i] = (P)vz;
+            S.cell[i] = fd.cell;
+            S.id[i] = id0 + q;
+        }
+    } else
     for (int q = lane; q < cnt; q += 64) {
         const uint32_t base = (uint32_t)(1 + 128 * q);
         double xr[3] = {0.0, 0.0, 0.0}, v[3];
@@ -693,7 +775,13 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
             const int copy = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kSurfCopies);
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
                                ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
-            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
+            int nl;
+            if (cs.mesh) {
+                const int gm = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+                nl = gm >= 0 ? gm - cs.cell0 : -1;
+            } else {
+                nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
+            }
             if (nl >= 0) {
                 nc = cs.cell0 + nl;
                 for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
@@ -1365,7 +1453,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 dtc = dtG;
             } else {
                 const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-                dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+                dtc = (cs.mesh ? C.mgeo[2 * (size_t)g + 1] : cs.L_cell) / (um + sqrt(gas.gamma * gas.R * T));
                 if (cs.adapt_dt) dtmin = fmin(dtmin, dtc);
             }
             double dtS;
@@ -2124,7 +2212,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 dtc = dtG;
             } else {
                 const double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-                dtc = cs.L_cell / (um + sqrt(gas.gamma * gas.R * T));
+                dtc = (cs.mesh ? C.mgeo[2 * (size_t)g + 1] : cs.L_cell) / (um + sqrt(gas.gamma * gas.R * T));
                 // Eq. 26: the next global step is the smallest local step of this one
                 if (cs.adapt_dt && tid == 0)
                     atomicMin(&G->dt_next[cid], (unsigned long long)__double_as_longlong(dtc));
@@ -2568,12 +2656,15 @@ void Launch::move_count(const Ctx &c, void *s, int any_body)
 {
     const int grid = c.grid[HS_KERNEL_MOVE] > 0 ? c.grid[HS_KERNEL_MOVE]
                                                 : std::min(4 * stream_grid(), blocks_for(c.capacity, kBlock));
+    // the worklist holds the body-near particles of grid cases (about 1%) but every particle
+    // of a mesh case: then it takes the full streaming grid
+    const int gbody = c.mxy ? grid : 256;
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(gbody), dim3(kBlock), 0, S_(s), c);
     } else {
         hipLaunchKernelGGL(k_move_fast<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(256), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(gbody), dim3(kBlock), 0, S_(s), c);
     }
 }
 void Launch::scatter(const Ctx &c, void *s)
@@ -2754,7 +2845,7 @@ __global__ void k_dsmc_ratio(Ctx C, int case_id, double *out)
         if (nn > 0.0 && T > 0.0) {
             const double tau = C.gas.mu_ref * pow(T / C.gas.T_ref, C.gas.omega) / (nn * kKB * T);
             const double dtc = cs.dim == 0 ? C.dt_cell[g]
-                                           : cs.L_cell / (sqrt(uu) + sqrt(C.gas.gamma * C.gas.R * T));
+                                           : (cs.mesh ? C.mgeo[2 * (size_t)g + 1] : cs.L_cell) / (sqrt(uu) + sqrt(C.gas.gamma * C.gas.R * T));
             r = dtc <= tau ? 1.0 : tau / dtc;
         }
     }

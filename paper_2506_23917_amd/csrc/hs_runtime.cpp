@@ -25,6 +25,7 @@ struct Layout {
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
     size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, surf, trace, out;
+    size_t mxy = 0, mquad = 0, mnbr = 0, mgeo = 0;
     size_t surf_bytes = 0;
 };
 
@@ -34,13 +35,65 @@ struct Plan {
     std::vector<double> rbox;
     std::vector<StateDev> rstate;
     std::vector<double> dtcell;     // per global cell, only if some case is 0-D
+    // quad meshes of the batch, only if some case has one: node coordinates (global node
+    // ids), per global cell the node ids, neighbours (global cells or hs_edge codes) and
+    // (volume, L_cell)
+    std::vector<double> mxy, mgeo;
+    std::vector<int32_t> mquad, mnbr;
     int64_t ncells = 0, capacity = 0;
     int dim_max = 0;
-    bool any_spatial = false, any_0d = false, any_body = false;
+    bool any_spatial = false, any_0d = false, any_body = false, any_mesh = false;
     GasDev gas;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+double cross2(const double *a0, const double *a1, const double *b0, const double *b1)
+{
+    return (a1[0] - a0[0]) * (b1[1] - b0[1]) - (a1[1] - a0[1]) * (b1[0] - b0[0]);
+}
+
+// A mesh: node ids in range, convex counter-clockwise quads, neighbours that name the cell
+// back across the same two nodes, boundary codes with what they need.
+bool valid_mesh(const hs_case &c, std::string &why)
+{
+    const hs_mesh *m = c.mesh;
+    if (c.dim != 2) { why = "a mesh case needs dim 2"; return false; }
+    if (m->n_cells <= 0 || m->n_nodes <= 0 || !m->xy || !m->quad || !m->nbr) { why = "mesh arrays"; return false; }
+    if (c.body == HS_BODY_SPHERE) { why = "a mesh case has no sphere"; return false; }
+    for (int64_t k = 0; k < m->n_cells; ++k) {
+        const int32_t *q = &m->quad[4 * k];
+        for (int j = 0; j < 4; ++j)
+            if (q[j] < 0 || q[j] >= m->n_nodes) { why = "mesh node id out of range"; return false; }
+        for (int j = 0; j < 4; ++j) {
+            const double *a = &m->xy[2 * q[j]], *b = &m->xy[2 * q[(j + 1) & 3]], *d = &m->xy[2 * q[(j + 2) & 3]];
+            if (!(cross2(a, b, b, d) > 0.0)) { why = "mesh cells must be convex and counter-clockwise"; return false; }
+        }
+        for (int j = 0; j < 4; ++j) {
+            const int32_t nb = m->nbr[4 * k + j];
+            if (nb >= 0) {
+                if (nb >= m->n_cells) { why = "mesh neighbour out of range"; return false; }
+                bool back = false;
+                for (int i = 0; i < 4; ++i)
+                    if (m->nbr[4 * (int64_t)nb + i] == (int32_t)k && m->quad[4 * (int64_t)nb + i] == q[(j + 1) & 3] &&
+                        m->quad[4 * (int64_t)nb + ((i + 1) & 3)] == q[j]) back = true;
+                if (!back) { why = "mesh neighbours must name each other across the same edge"; return false; }
+            } else if (nb == HS_EDGE_WALL) {
+                if (!(c.body_T > 0)) { why = "WALL edges need body_T"; return false; }
+            } else if (nb == HS_EDGE_INFLOW) {
+                if (!(c.inflow.T > 0 && c.inflow.n >= 0)) { why = "inflow state"; return false; }
+            } else if (nb != HS_EDGE_OUTFLOW && nb != HS_EDGE_SPECULAR) {
+                why = "unknown mesh edge code";
+                return false;
+            }
+        }
+    }
+    if (c.n_surf > 0 && (c.body != HS_BODY_CYLINDER || !(c.body_r > 0))) {
+        why = "mesh surface elements need a cylinder frame (body_r)";
+        return false;
+    }
+    return true;
+}
 
 hs_status validate(const hs_gas *g, const hs_case *cs, int n, std::string &why)
 {
@@ -54,6 +107,20 @@ hs_status validate(const hs_gas *g, const hs_case *cs, int n, std::string &why)
     int64_t cells = 0, cap = 0;
     for (int i = 0; i < n; ++i) {
         const hs_case &c = cs[i];
+        if (c.mesh) {
+            for (int a = 0; a < 3; ++a)
+                if (!(c.h[a] > 0)) { why = "cell size"; return HS_ERR_ARG; }
+            if (!(c.F_N > 0) || !(c.T_sigma > 0) || c.capacity < 0 || !(c.dt_G > 0)) { why = "F_N/T_sigma/capacity/dt_G"; return HS_ERR_ARG; }
+            if (c.n_regions < 0 || (c.n_regions > 0 && (!c.region_state || !c.region_box))) { why = "regions"; return HS_ERR_ARG; }
+            if (c.adapt_dt != 0 && c.adapt_dt != 1) { why = "adapt_dt must be 0 or 1"; return HS_ERR_ARG; }
+            if (c.n_surf < 0 || c.n_surf > 65536) { why = "n_surf (0..65536)"; return HS_ERR_ARG; }
+            if (!valid_mesh(c, why)) return HS_ERR_ARG;
+            for (int j = 0; j < i; ++j)
+                if (cs[j].seed == c.seed) { why = "cases need distinct seeds"; return HS_ERR_ARG; }
+            cells += c.mesh->n_cells;
+            cap += c.capacity;
+            continue;
+        }
         if (c.dim < 0 || c.dim > 3) { why = "dim"; return HS_ERR_ARG; }
         if (c.nx <= 0 || (c.dim >= 2 && c.ny <= 0) || (c.dim >= 3 && c.nz <= 0)) { why = "grid size"; return HS_ERR_ARG; }
         for (int a = 0; a < 3; ++a)
@@ -116,6 +183,15 @@ double face_flux(const hs_gas *g, const hs_state &st, int a, double sg)
     return st.n * (std::exp(-s * s) + std::sqrt(kPi_h) * s * (1.0 + std::erf(s))) / (2.0 * beta * std::sqrt(kPi_h));
 }
 
+// One-way number flux of the inflow state through a face with inward unit normal nrm.
+double edge_flux(const hs_gas *g, const hs_state &st, const double nrm[2])
+{
+    const double R = kKB_h / g->m;
+    const double beta = 1.0 / std::sqrt(2.0 * R * st.T);
+    const double s = beta * (st.u[0] * nrm[0] + st.u[1] * nrm[1]);
+    return st.n * (std::exp(-s * s) + std::sqrt(kPi_h) * s * (1.0 + std::erf(s))) / (2.0 * beta * std::sqrt(kPi_h));
+}
+
 void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
 {
     P.gas.m = g->m;
@@ -129,13 +205,15 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
     P.gas.vhs_exp = 2.0 - 2.0 * g->omega;
     int64_t cell0 = 0;
     for (int i = 0; i < n; ++i) if (cs[i].dim == 0) P.any_0d = true;
+    for (int i = 0; i < n; ++i) if (cs[i].mesh) P.any_mesh = true;
     for (int i = 0; i < n; ++i) {
         const hs_case &c = cs[i];
         CaseDev d;
         std::memset(&d, 0, sizeof(d));
         d.dim = c.dim;
-        d.n[0] = c.nx;
-        d.n[1] = c.dim >= 2 ? c.ny : 1;
+        d.mesh = c.mesh ? 1 : 0;
+        d.n[0] = c.mesh ? c.mesh->n_cells : c.nx;
+        d.n[1] = c.dim >= 2 && !c.mesh ? c.ny : 1;
         d.n[2] = c.dim >= 3 ? c.nz : 1;
         const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
         d.cell0 = (int32_t)cell0;
@@ -170,7 +248,7 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
             d.bb_lo[a] = 0;
             d.bb_hi[a] = d.n[a] - 1;
         }
-        if (c.body != HS_BODY_NONE) {
+        if (c.body != HS_BODY_NONE && !c.mesh) {
             const int na = c.body == HS_BODY_SPHERE ? 3 : 2;
             for (int a = 0; a < na; ++a) {
                 d.bb_lo[a] = (int32_t)std::floor((c.body_c[a] - c.body_r - c.lo[a]) / c.h[a]) - 1;
@@ -196,8 +274,53 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
             for (int64_t k = 0; k < nc; ++k) P.dtcell.push_back(c.dim == 0 ? c.dt_over_tau[k] * tau0 : c.dt_G);
         }
         // inflow faces: sides -x,+x,-y,+y,-z,+z; boundary cells x-fastest; slot filter
+        // (a mesh: its INFLOW edges, in cell and edge order)
         d.face0 = (int32_t)P.faces.size();
-        for (int s = 0; s < 2 * c.dim; ++s) {
+        if (P.any_mesh) {
+            const int32_t node0 = (int32_t)(P.mxy.size() / 2);
+            P.mgeo.resize(2 * (size_t)(cell0 + nc), 0.0);
+            P.mquad.resize(4 * (size_t)(cell0 + nc), 0);
+            P.mnbr.resize(4 * (size_t)(cell0 + nc), HS_EDGE_OUTFLOW);
+            if (c.mesh) {
+                const hs_mesh *m = c.mesh;
+                P.mxy.insert(P.mxy.end(), m->xy, m->xy + 2 * (size_t)m->n_nodes);
+                for (int64_t k = 0; k < nc; ++k) {
+                    const int32_t *q = &m->quad[4 * k];
+                    double Pq[4][2];
+                    for (int j = 0; j < 4; ++j) {
+                        P.mquad[4 * (cell0 + k) + j] = node0 + q[j];
+                        const int32_t nb = m->nbr[4 * k + j];
+                        P.mnbr[4 * (cell0 + k) + j] = nb >= 0 ? (int32_t)(cell0 + nb) : nb;
+                        Pq[j][0] = m->xy[2 * q[j]];
+                        Pq[j][1] = m->xy[2 * q[j] + 1];
+                    }
+                    // area from two triangles at node 0; L_cell = area / longest edge
+                    const double area = 0.5 * (cross2(Pq[0], Pq[1], Pq[0], Pq[2]) + cross2(Pq[0], Pq[2], Pq[0], Pq[3]));
+                    double lmax = 0.0;
+                    for (int j = 0; j < 4; ++j) {
+                        const double ex = Pq[(j + 1) & 3][0] - Pq[j][0], ey = Pq[(j + 1) & 3][1] - Pq[j][1];
+                        const double l = std::sqrt(ex * ex + ey * ey);
+                        if (l > lmax) lmax = l;
+                    }
+                    P.mgeo[2 * (cell0 + k)] = area * c.h[2];
+                    P.mgeo[2 * (cell0 + k) + 1] = area / lmax;
+                    for (int j = 0; j < 4; ++j) {
+                        if (m->nbr[4 * k + j] != HS_EDGE_INFLOW) continue;
+                        const double ex = Pq[(j + 1) & 3][0] - Pq[j][0], ey = Pq[(j + 1) & 3][1] - Pq[j][1];
+                        const double len = std::sqrt(ex * ex + ey * ey);
+                        const double nrm[2] = {-ey / len, ex / len};
+                        FaceDev f;
+                        f.cell = (int32_t)(cell0 + k);
+                        f.side = j;
+                        f.case_id = i;
+                        f.local = (int32_t)(P.faces.size() - d.face0);
+                        f.lambda = edge_flux(g, c.inflow, nrm) * (len * c.h[2]) * c.dt_G / c.F_N;
+                        P.faces.push_back(f);
+                    }
+                }
+            }
+        }
+        for (int s = 0; s < 2 * c.dim && !c.mesh; ++s) {
             if (c.bc[s] != HS_BC_INFLOW) continue;
             const int a = s / 2;
             const double sg = (s % 2 == 0) ? 1.0 : -1.0;
@@ -229,6 +352,7 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         P.capacity += c.capacity;
         P.dim_max = std::max(P.dim_max, c.dim);
         if (c.dim > 0) P.any_spatial = true;
+        if (c.mesh) P.any_body = true;     // mesh particles take the worklist move
     }
     P.ncells = cell0;
 }
@@ -278,6 +402,12 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.surf_bytes = 8 * 7 * (size_t)kSurfCopies * std::max<size_t>(nsurf, 1);
     L.surf = take(L.surf_bytes);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
+    if (P.any_mesh) {
+        L.mxy = take(sizeof(double) * std::max<size_t>(P.mxy.size(), 2));
+        L.mquad = take(sizeof(int32_t) * 4 * nc);
+        L.mnbr = take(sizeof(int32_t) * 4 * nc);
+        L.mgeo = take(sizeof(double) * 2 * nc);
+    }
     size_t maxcase = 1;
     for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
     size_t maxsurf = 0;
@@ -492,6 +622,12 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
         c.n_surf_total = (int32_t)ns;
     }
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
+    if (s->plan.any_mesh) {
+        c.mxy = (const double *)(w + L.mxy);
+        c.mquad = (const int32_t *)(w + L.mquad);
+        c.mnbr = (const int32_t *)(w + L.mnbr);
+        c.mgeo = (const double *)(w + L.mgeo);
+    }
     c.tile_w = tile_width();
     c.dim_max = s->plan.dim_max;
     c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
@@ -514,6 +650,12 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     e = e ? e : up(L.rbox, s->plan.rbox.data(), sizeof(double) * s->plan.rbox.size());
     e = e ? e : up(L.rstate, s->plan.rstate.data(), sizeof(StateDev) * s->plan.rstate.size());
     if (s->plan.any_0d) e = e ? e : up(L.dtcell, s->plan.dtcell.data(), sizeof(double) * s->plan.dtcell.size());
+    if (s->plan.any_mesh) {
+        e = e ? e : up(L.mxy, s->plan.mxy.data(), sizeof(double) * s->plan.mxy.size());
+        e = e ? e : up(L.mquad, s->plan.mquad.data(), sizeof(int32_t) * s->plan.mquad.size());
+        e = e ? e : up(L.mnbr, s->plan.mnbr.data(), sizeof(int32_t) * s->plan.mnbr.size());
+        e = e ? e : up(L.mgeo, s->plan.mgeo.data(), sizeof(double) * s->plan.mgeo.size());
+    }
     e = e ? e : hipMemsetAsync(w + L.globals, 0, sizeof(Globals), s->stream);
     e = e ? e : hipMemsetAsync(w + L.surf, 0, L.surf_bytes, s->stream);
     if (e != hipSuccess) {
@@ -791,7 +933,10 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
             if (!std::isfinite(rd(vel + d * es * np, i))) { s->err = "non-finite imported velocity"; return HS_ERR_NUMERIC; }
             if (d < cs.dim) {
                 const double x = rd(pos + d * es * np, i);
-                if (!(x >= 0.0 && x < 1.0)) { s->err = "imported positions must be cell-relative in [0,1)"; return HS_ERR_ARG; }
+                if (cs.mesh ? !std::isfinite(x) : !(x >= 0.0 && x < 1.0)) {
+                    s->err = "imported positions must be cell-relative in [0,1) (finite on a mesh)";
+                    return HS_ERR_ARG;
+                }
             }
         }
     }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhs.so")
 FP64, FP32_MIXED = 0, 1
 BC = {"outflow": 0, "specular": 1, "inflow": 2}
 BODY = {"none": 0, "cylinder": 1, "sphere": 2}
+EDGE = {"outflow": -1, "inflow": -2, "wall": -3, "specular": -4}
 FLAG_TRACE, FLAG_NO_PARTICLES, FLAG_GRAPH = 1, 2, 4
 KERNELS = {"inject": 0, "move": 1, "scan": 2, "scatter": 3, "gather": 4, "scalars": 5, "collide": 6,
            "dense": 7, "step": 8}
@@ -44,6 +45,11 @@ class HsState(C.Structure):
     _fields_ = [("n", C.c_double), ("u", C.c_double * 3), ("T", C.c_double)]
 
 
+class HsMesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_cells", C.c_int32), ("xy", C.POINTER(C.c_double)),
+                ("quad", C.POINTER(C.c_int32)), ("nbr", C.POINTER(C.c_int32))]
+
+
 class HsCase(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lo", C.c_double * 3), ("h", C.c_double * 3), ("bc", C.c_int32 * 6),
@@ -54,7 +60,7 @@ class HsCase(C.Structure):
                 ("F_N", C.c_double), ("dt_G", C.c_double), ("T_sigma", C.c_double),
                 ("dt_over_tau", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("n_steady", C.c_int64), ("capacity", C.c_int64), ("n_surf", C.c_int32),
-                ("adapt_dt", C.c_int32)]
+                ("adapt_dt", C.c_int32), ("mesh", C.POINTER(HsMesh))]
 
 
 class HsStateHeader(C.Structure):
@@ -167,6 +173,17 @@ class _Cases:
             c.capacity = int(d["capacity"])
             c.n_surf = int(d.get("n_surf", 0))
             c.adapt_dt = int(bool(d.get("adapt_dt", False)))
+            if d.get("mesh") is not None:
+                m = d["mesh"]
+                xy = np.ascontiguousarray(np.asarray(m["xy"], np.float64).reshape(-1))
+                quad = np.ascontiguousarray(np.asarray(m["quad"], np.int32).reshape(-1))
+                nbr = np.ascontiguousarray(np.array(
+                    [EDGE[v] if isinstance(v, str) else int(v) for v in np.asarray(m["nbr"]).reshape(-1)],
+                    np.int32))
+                hm = HsMesh(xy.size // 2, quad.size // 4, xy.ctypes.data_as(C.POINTER(C.c_double)),
+                            quad.ctypes.data_as(C.POINTER(C.c_int32)), nbr.ctypes.data_as(C.POINTER(C.c_int32)))
+                self.keep += [xy, quad, nbr, hm]
+                c.mesh = C.pointer(hm)
         self.arr = arr
         self.n = len(cases)
 
@@ -339,7 +356,7 @@ class Sim:
     def import_state(self, c, st: dict):
         rdt = self.rdt
         pos = np.asarray(st["pos"], rdt).reshape(-1, 3)
-        if rdt == np.float32:
+        if rdt == np.float32 and self.cases[c].get("mesh") is None:
             # an FP64 offset just below 1 rounds to 1.0f: keep it inside its cell
             pos = np.minimum(pos, np.nextafter(np.float32(1.0), np.float32(0.0)))
         vel = np.asarray(st["vel"], rdt).reshape(-1, 3)

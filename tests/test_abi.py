@@ -54,3 +54,46 @@ def test_plan_validates_on_host():
         assert e.code == 1
     else:
         raise AssertionError("expected an argument error")
+
+
+def test_plan_validates_meshes_on_host():
+    """hs_plan accepts the O-grid and the meshed box and rejects broken meshes (no GPU)."""
+    import numpy as np
+    from paper_2506_23917_amd import hs
+    import workloads as W
+    g = W.gas()
+    og = W.cylinder_ogrid()
+    assert hs.plan_bytes(g, og, hs.FP32_MIXED) > og["capacity"] * 32
+    st = dict(n=1e20, u=(800.0, 0.0, 0.0), T=300.0)
+    box = W._case(dim=2, nx=6, ny=4, h=(0.05, 0.05, 1.0), bc=("inflow", "outflow", "specular", "outflow",
+                  "outflow", "outflow"), inflow=st, regions=[((0, 0, 0, 0.3, 0.2, 1), st)], F_N=1e16,
+                  dt_G=1e-5, capacity=1000)
+    twin = W.mesh_twin(box)
+    hs.plan_bytes(g, [twin, dict(box, seed=2)])            # a mesh beside a grid case
+
+    def rejected(case):
+        try:
+            hs.plan_bytes(g, case)
+        except hs.HsError as e:
+            return e.code == 1
+        return False
+
+    for what in ("clockwise", "node", "nbr", "code", "sphere", "dim", "frame"):
+        c = dict(twin)
+        m = {k: np.array(v, copy=True) for k, v in twin["mesh"].items()}
+        if what == "clockwise":
+            m["quad"][3] = m["quad"][3][::-1]
+        elif what == "node":
+            m["quad"][1, 2] = 10_000
+        elif what == "nbr":
+            m["nbr"][0, 1] = 5
+        elif what == "code":
+            m["nbr"][0, 0] = -7
+        elif what == "sphere":
+            c["body"] = "sphere"
+        elif what == "dim":
+            c["dim"] = 3
+        else:
+            c["n_surf"] = 4                                 # surface elements need a cylinder frame
+        c["mesh"] = m
+        assert rejected(c), what

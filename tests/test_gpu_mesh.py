@@ -1,0 +1,179 @@
+"""Body-fitted quad meshes on the GPU (gfx950) against the FP64 oracle, through the C ABI.
+
+FP64 path from the same initial state and RNG streams: bit-exact ids, cells, counters and
+per-cell collision records; positions within 1e-12 of the domain size (the GPU keeps them
+relative to each cell's first node), velocities within 1e-12 relative; wall sums within
+1e-9.  FP32-mixed: the oracle's physics pins (equilibrium O-grid, free-molecular drag)
+hold on the GPU too.  Cases: a meshed box (inflow, specular and outflow edges), a jittered
+closed box (oblique interior edges, specular corners) and the cylinder O-grid of the
+paper's Ma 5 case (inflow circle, wall edges, surface sampling), small and full size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle
+from gpu_util import vel_rel_err
+from test_gpu_parity import _compare_trace
+from test_oracle_surface import cd_closed
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(gas, cases, **kw):
+    from paper_2506_23917_amd.hs import Sim
+    return Sim(gas, cases, **kw)
+
+
+def mesh_abs(case, st):
+    m = case["mesh"]
+    x = np.zeros((len(st["cell"]), 3))
+    x[:, :2] = m["xy"][m["quad"][st["cell"], 0]] + st["pos"][:, :2].astype(np.float64)
+    return x
+
+
+def extent(case):
+    xy = case["mesh"]["xy"]
+    return float((xy.max(axis=0) - xy.min(axis=0)).max())
+
+
+def _box(seed=3):
+    st = dict(n=1e20, u=(800.0, 100.0, 0.0), T=300.0)
+    return W._case(dim=2, nx=12, ny=8, h=(0.05, 0.05, 1.0),
+                   bc=("inflow", "outflow", "specular", "outflow", "outflow", "outflow"), inflow=st,
+                   regions=[((0.0, 0.0, 0.0, 0.6, 0.4, 1.0), st)], F_N=1e20 * 0.0025 / 40,
+                   dt_G=0.5 * 0.05 / 1100.0, T_sigma=600.0, seed=seed, n_steady=2, capacity=20000)
+
+
+def mesh_cases():
+    box = W.mesh_twin(_box())
+    closed = _box(seed=4)
+    closed["bc"] = ("specular",) * 4 + ("outflow",) * 2
+    jit = W.mesh_twin(closed, jitter=0.2)
+    og = W.cylinder_ogrid(n_theta=48, first=0.02, growth=1.15, r_out=2.0, ppc_outer=60, seed=5,
+                          n_steady=3, n_surf=12)
+    return dict(box=box, jitter=jit, ogrid=og)
+
+
+def _compare(gas, case, g, o, vtol=1e-12, label=""):
+    assert len(g["id"]) == len(o["id"]), (label, len(g["id"]), len(o["id"]))
+    assert np.array_equal(g["id"], o["id"]), label
+    assert np.array_equal(g["cell"], o["cell"]), label
+    assert g["next_id"] == o["next_id"], label
+    err = vel_rel_err(g["vel"], o["v"], gas)
+    assert err < vtol, (label, err)
+    if len(o["x"]):
+        perr = np.abs(mesh_abs(case, g)[:, :2] - o["x"][:, :2]).max() / extent(case)
+        assert perr < 1e-12, (label, perr)
+
+
+@pytest.mark.parametrize("name", ["box", "jitter", "ogrid"])
+def test_mesh_init_matches_oracle(gas, name):
+    case = mesh_cases()[name]
+    sim = _sim(gas, case, precision="fp64")
+    ora = Oracle(gas, case)
+    ora.init_particles()
+    _compare(gas, case, sim.export_state(0), ora.get_state(0), vtol=1e-14, label="init " + name)
+    # volumes and (sigma c)_max as the oracle's
+    sm = sim.sample_moments(0, 1)
+    om = ora.sample_moments(0, 1)
+    np.testing.assert_allclose(sm["n"], om["n"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,steps", [("box", 6), ("jitter", 6), ("ogrid", 8)])
+def test_mesh_fp64_steps_match_oracle(gas, name, steps):
+    case = mesh_cases()[name]
+    sim = _sim(gas, case, precision="fp64", trace=True)
+    ora = Oracle(gas, case, trace=True)
+    ora.init_particles()
+    for s in range(steps):
+        sim.step(1)
+        ora.step(1)
+        lab = "%s step %d" % (name, s + 1)
+        _compare(gas, case, sim.export_state(0), ora.get_state(0), label=lab)
+        _compare_trace(sim.trace(0), ora.trace(0), label=lab)
+    assert sim.counters(0) == ora.counters(0)
+    if name == "ogrid":
+        assert ora.counters(0)["wall_hits"] > 0 and ora.counters(0)["injected"] > 0
+        sg, so = sim.surface_sums(0), ora.surface_sums(0)
+        assert np.array_equal(sg[:, 0], so[:, 0])
+        np.testing.assert_allclose(sg, so, rtol=1e-9, atol=1e-9 * np.abs(so).max())
+        rg, ro = sim.surface_sample(0), ora.surface_sample(0)
+        for k in ("p", "tau", "q", "CD", "CL"):
+            np.testing.assert_allclose(rg[k], ro[k], rtol=1e-9, atol=1e-9 * np.abs(ro[k]).max() + 1e-300)
+    mg, mo = sim.sample_moments(0, 0), ora.sample_moments(0, 0)
+    np.testing.assert_allclose(mg["n"], mo["n"], rtol=1e-11)
+    np.testing.assert_allclose(sim.dsmc_ratio(0), ora.dsmc_ratio(0), rtol=1e-9, atol=1e-12)
+
+
+def test_mesh_adaptive_step_and_batch_with_a_grid_case(gas):
+    """Eq. 26 with the mesh's L_cell, and a mesh case batched with a grid case."""
+    og = mesh_cases()["ogrid"]
+    og["adapt_dt"] = True
+    grid = W.cylinder_2d(nx=40, ny=30, ppc=8, seed=11, n_surf=6, n_steady=0)
+    cases = [grid, og]
+    sim = _sim(gas, cases, precision="fp64")
+    ora = Oracle(gas, cases)
+    ora.init_particles()
+    for s in range(5):
+        sim.step(1)
+        ora.step(1)
+        _compare(gas, og, sim.export_state(1), ora.get_state(1), label="adaptive step %d" % (s + 1))
+        dg, do = sim.step_dt(1), ora.step_dt(1)
+        assert abs(dg[0] - do[0]) <= 1e-12 * do[0]
+    assert ora.step_dt(1)[0] != og["dt_G"]
+    g0, o0 = sim.export_state(0), ora.get_state(0)
+    assert np.array_equal(g0["id"], o0["id"]) and np.array_equal(g0["cell"], o0["cell"])
+
+
+def test_mesh_full_size_ogrid_steps(gas):
+    """The Ma 5 cylinder O-grid of Sec. 4.2 at its full size (180 x 56 cells, first layer
+    1 mm, growth 1.1, about 0.67M particles): two FP64 steps from the initial state, every
+    particle against the oracle."""
+    case = W.cylinder_ogrid(n_steady=0)
+    sim = _sim(gas, case, precision="fp64")
+    ora = Oracle(gas, case)
+    ora.init_particles()
+    _compare(gas, case, sim.export_state(0), ora.get_state(0), vtol=1e-14, label="full init")
+    for s in range(2):
+        sim.step(1)
+        ora.step(1)
+        _compare(gas, case, sim.export_state(0), ora.get_state(0), label="full step %d" % (s + 1))
+    assert sim.counters(0) == ora.counters(0)
+    np.testing.assert_allclose(sim.surface_sums(0), ora.surface_sums(0), rtol=1e-9,
+                               atol=1e-9 * np.abs(ora.surface_sums(0)).max())
+
+
+def test_mesh_fp32_gas_at_rest_stays_uniform(gas):
+    T = 300.0
+    case = W.free_molecular_ogrid(s=0.0, T=T, T_w=T, n_surf=4, total=40000)
+    sim = _sim(gas, case, precision="fp32")
+    sim.step(1500)
+    m = sim.sample_moments(0, 0)
+    ora = Oracle(gas, case)
+    vol = ora.get_cells(0)["vol"]
+    n_ring = (m["n"] * vol).reshape(-1, 72).sum(axis=1) / vol.reshape(-1, 72).sum(axis=1)
+    n0 = case["inflow"]["n"]
+    assert np.all(np.abs(n_ring[4:] / n0 - 1.0) < 0.02), n_ring / n0
+    r = sim.surface_sample(0)
+    assert np.all(np.abs(r["p"] / (n0 * W.K_BOLTZMANN * T) - 1.0) < 0.05)
+
+
+def test_mesh_fp32_free_molecular_drag(gas):
+    T, Tw, s = 300.0, 500.0, 1.0
+    case = W.free_molecular_ogrid(s=s, T=T, T_w=Tw, total=60000)
+    sim = _sim(gas, case, precision="fp32")
+    R = case["body_r"]
+    n, U = case["inflow"]["n"], case["inflow"]["u"][0]
+    qd = 0.5 * n * W.ARGON["m"] * U * U
+    prev, cds = np.zeros((case["n_surf"], 7)), []
+    for _ in range(8):
+        sim.step(250)
+        S = sim.surface_sums(0)
+        d, prev = S - prev, S
+        cds.append(d[:, 4].sum() / (250 * case["dt_G"]) / (qd * 2 * R))
+    cds = np.array(cds)
+    ref = cd_closed(s, T, Tw, False)
+    assert abs(cds.mean() - ref) < 5.0 * cds.std(ddof=1) / math.sqrt(8) + 5e-3 * ref, (cds.mean(), ref)

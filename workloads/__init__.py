@@ -287,7 +287,7 @@ def mesh_twin(case, jitter=0.0):
     return out
 
 
-def cylinder_ogrid(n_theta=180, first=0.001, growth=1.1, r_out=3.0, kn=0.01, ppc_outer=1000,
+def cylinder_ogrid(n_theta=180, first=0.001, growth=1.1, r_out=3.0, kn=0.01, ppc_outer=500,
                    seed=1, n_steady=1 << 40, cap_factor=1.5, n_surf=90, adapt_dt=False):
     """Ma 5 argon flow past the unit cylinder of Sec. 4.2 on its O-grid (wall at 273 K,
     freestream on the outer circle); F_N puts ppc_outer particles in the outermost cells at
