@@ -17,6 +17,11 @@ The FP64 run's developed state is then imported into an FP32-mixed sim and both 
 from it with the same random numbers: the relative L2 differences of the cell moments n, u, T, q
 go into the line's "accuracy" object (the mixed path's bound is 1e-3).
 
+`--workload ogrid` measures the body-fitted mesh path instead: a batch of twelve O-grid runs of
+the paper's Ma 5 cylinder (first layer 1 mm, growth 1.1 or 1.05, Kn 0.01 or 0.1; ~10.4M
+particles, 149k quads), face-to-face tracking in k_move_mesh.  Its roofline object is for that
+kernel, timed the same way.
+
 Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: the build runs on one GPU.
 """
 from __future__ import annotations
@@ -42,6 +47,10 @@ TILE_BYTES_PER_CELL = 4 + 64 + 8 + 208
 # Whole step, FP32-mixed 2-D: one state read + write for the sort and one for move and
 # collide, plus cell traffic (about 128 B per particle-step).
 STEP_BYTES_PER_PARTICLE = 128
+# Mesh move (FP32-mixed, per particle): cell (4), position (8) and velocity (12) read;
+# position, velocity, new cell and slot written (8 + 12 + 4 + 4).  Node coordinates and
+# neighbours are per cell and stay in cache.
+MESH_MOVE_BYTES_PER_PARTICLE = 24 + 28
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_traffic.txt")
 KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.hpp", "hs_common.hpp"]
 
@@ -71,7 +80,7 @@ def committed_traffic():
     return float(m_b.group(1))
 
 
-def run_gpu(prec, case, gas, warmup, steps):
+def run_gpu(prec, case, gas, warmup, steps, timed_group="collide"):
     import torch
     from paper_2506_23917_amd.hs import Sim
 
@@ -81,16 +90,17 @@ def run_gpu(prec, case, gas, warmup, steps):
     # launch shapes (blocks per grid of each kernel group) picked by the autotuner on the
     # developed flow; its trial steps are further warmup steps
     tune = sim.autotune(steps_per_trial=10)
-    n0 = sim.num_particles(0)
-    sim.set_timing(["collide"])
+    nc = len(sim.cases)
+    n0 = sum(sim.num_particles(c) for c in range(nc))
+    sim.set_timing([timed_group])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    n1 = sim.num_particles(0)
-    tile_ms, launches = sim.kernel_timing("collide")
+    n1 = sum(sim.num_particles(c) for c in range(nc))
+    tile_ms, launches = sim.kernel_timing(timed_group)
     sim.set_timing(False)
     sim.clear_timing()
     return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches, tune=tune)
@@ -138,6 +148,48 @@ def cpu_baseline(sim, case, gas, nsteps):
     return n * nsteps / dt, n, dt
 
 
+def main_ogrid(args):
+    """The body-fitted O-grid batch (mesh path): FP32-mixed and FP64 throughput, the mesh
+    move kernel against the HBM roofline."""
+    import workloads as W
+    gas = W.gas()
+    cases = W.ogrid_batch()
+    for c in cases:
+        c["n_steady"] = args.warmup
+    ncells = sum(len(c["mesh"]["quad"]) for c in cases)
+    log("[bench] ogrid fp32-mixed: warmup %d, timed %d" % (args.warmup, args.steps))
+    sim32, r32 = run_gpu("fp32", cases, gas, args.warmup, args.steps, timed_group="move")
+    npart = 0.5 * (r32["n0"] + r32["n1"])
+    value = npart * args.steps / r32["dt"]
+    ms_step = 1e3 * r32["dt"] / args.steps
+    move_bytes = MESH_MOVE_BYTES_PER_PARTICLE * npart
+    achieved = move_bytes / (r32["tile_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s, 2-D Ma5 cylinder on body-fitted O-grids",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64-mixed", "data": "synthetic",
+        "config": {"workload": "12 O-grid runs of the Ma 5 argon cylinder (180 nodes around, first layer "
+                               "1 mm, growth 1.1 / 1.05, outer radius 3 R, Kn 0.01 / 0.1, 500 particles "
+                               "in the outermost cells), FP32-mixed, sampling on",
+                   "particles": int(npart), "cells": ncells},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "move group: k_move_fast (passes mesh waves) + k_move_mesh (face-to-face tracking)",
+                     "kernel_ms": r32["tile_ms"], "launches_timed": r32["launches"],
+                     "algorithmic_bytes_per_launch": move_bytes},
+    }
+    if not args.no_fp64:
+        del sim32
+        import torch
+        torch.cuda.empty_cache()
+        sim64, r64 = run_gpu("fp64", cases, gas, args.warmup, args.steps, timed_group="move")
+        v64 = 0.5 * (r64["n0"] + r64["n1"]) * args.steps / r64["dt"]
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps, "move_ms": r64["tile_ms"]}
+        out["mixed_speedup_vs_fp64"] = value / v64
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,11 +198,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps of the CPU baseline sample")
+    ap.add_argument("--workload", choices=("cylinder", "ogrid"), default="cylinder")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ogrid":
+        main_ogrid(args)
+        return
 
     import workloads as W
     gas = W.gas()

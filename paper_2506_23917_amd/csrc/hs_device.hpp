@@ -438,7 +438,6 @@ template <typename P>
 __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v[3], double t, bool full_step,
                                       bool &vchg)
 {
-    if (cs.mesh) return -2;     // meshes are tracked face to face by move_mesh
     const int dim = cs.dim;
     int ijk[3];
     cell_ijk(cs, local, ijk);

@@ -697,13 +697,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const bool valid = i < n_total;       // the valid lanes of a wave are a prefix
         int g = 0;
         P xr[3] = {(P)0, (P)0, (P)0}, v[3] = {(P)0, (P)0, (P)0};
+        // state loads first (guarded by the batch's largest dimension, not the case's); in a
+        // batch with mesh cases, only once the wave is known not to be a mesh case's
+        const bool early = C.mxy == nullptr;
         if (valid) {
-            // state loads first (guarded by the batch's largest dimension, not the case's)
             g = S.cell[i];
+            if (early) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
+                for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+                for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+            }
         }
         // Cases are contiguous in the particle array (the sorted live part, then the injected
         // particles case by case), so a wave nearly always lies in the case of its first
@@ -711,13 +715,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const int cu = case_of(C, __builtin_amdgcn_readfirstlane(g));
         const CaseDev &csu = case_const(C, cu);
         const bool one = __all(!valid || (g >= csu.cell0 && g < csu.cell0 + csu.ncells));
+        if (one && csu.mesh) continue;          // a mesh case's wave: k_move_mesh moves it
+        if (!early && valid) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
+        }
         int nc = -1, cid = cu;
-        bool to_body = false;
+        bool to_body = false, skip = false;
         if (one) {
             if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, const_read(&G->dt_cur[cu]), nc, to_body);
         } else if (valid) {
             cid = case_of(C, g);
-            move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
+            skip = C.cases[cid].mesh != 0;
+            if (!skip) move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
+        }
+        if (skip) {
+            nc = -1;
+            to_body = false;
         }
         // worklist of body candidates
         {
@@ -731,11 +747,64 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 if (to_body) C.work[basew + __popcll(m & ((1ull << lane) - 1ull))] = i;
             }
         }
-        const bool counted = valid && !to_body && nc >= 0;
-        if (valid && !to_body) C.newcell[i] = nc;
+        const bool counted = valid && !skip && !to_body && nc >= 0;
+        if (valid && !skip && !to_body) C.newcell[i] = nc;
         const int myslot = wave_slot(C.count, nc, counted);
         if (counted) C.slot[i] = myslot;
-        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, valid && !to_body && nc < 0);
+        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, valid && !skip && !to_body && nc < 0);
+    }
+}
+
+// Every particle of the mesh cases: face-to-face tracking (move_mesh), new cell and slot.
+// Waves of grid cases pass straight through (k_move_fast moves them).
+template <typename P>
+__global__ __launch_bounds__(kBlock) void k_move_mesh(Ctx C)
+{
+    Globals *G = C.g;
+    if (G->halt) return;
+    const int n_total = G->n_total, n_live = G->n_live;
+    const uint32_t st = (uint32_t)G->step;
+    const Parts<P> S(C.buf[G->step & 1]);
+    const int stride = gridDim.x * blockDim.x;
+    const int copy = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kSurfCopies);
+    for (int base = blockIdx.x * blockDim.x; base < n_total; base += stride) {
+        const int i = base + threadIdx.x;
+        const bool valid = i < n_total;
+        const int g = valid ? S.cell[i] : 0;
+        const int cu = case_of(C, __builtin_amdgcn_readfirstlane(g));
+        const CaseDev &csu = case_const(C, cu);
+        const bool one = __all(!valid || (g >= csu.cell0 && g < csu.cell0 + csu.ncells));
+        if (one && !csu.mesh) continue;
+        const int cid = one ? cu : (valid ? case_of(C, g) : cu);
+        const CaseDev &cs = C.cases[cid];
+        const bool mine = valid && cs.mesh;
+        int nc = -1;
+        MoveStats ms{0, 0};
+        if (mine) {
+            P xr[3] = {S.pos[0][i], S.pos[1][i], (P)0}, v[3] = {S.vel[0][i], S.vel[1][i], S.vel[2][i]};
+            const bool full = i < n_live;
+            int64_t id = -1;
+            const double dt = G->dt_cur[cid];
+            double t = dt;
+            if (!full) {
+                id = S.id[i];
+                t = dt * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
+            }
+            double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
+                               ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
+            nc = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+            if (nc >= 0) {
+                S.pos[0][i] = xr[0];
+                S.pos[1][i] = xr[1];
+                for (int a = 0; a < 3; ++a) S.vel[a][i] = v[a];
+            }
+            C.newcell[i] = nc;
+        }
+        const int myslot = wave_slot(C.count, nc, mine && nc >= 0);
+        if (mine && nc >= 0) C.slot[i] = myslot;
+        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, mine && nc < 0);
+        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_WALL_HITS, ms.hits, mine);
+        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_BOUNCE_CAP, ms.capped, mine);
     }
 }
 
@@ -775,13 +844,7 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
             const int copy = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kSurfCopies);
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
                                ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
-            int nl;
-            if (cs.mesh) {
-                const int gm = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
-                nl = gm >= 0 ? gm - cs.cell0 : -1;
-            } else {
-                nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
-            }
+            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
             if (nl >= 0) {
                 nc = cs.cell0 + nl;
                 for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
@@ -2656,15 +2719,16 @@ void Launch::move_count(const Ctx &c, void *s, int any_body)
 {
     const int grid = c.grid[HS_KERNEL_MOVE] > 0 ? c.grid[HS_KERNEL_MOVE]
                                                 : std::min(4 * stream_grid(), blocks_for(c.capacity, kBlock));
-    // the worklist holds the body-near particles of grid cases (about 1%) but every particle
-    // of a mesh case: then it takes the full streaming grid
-    const int gbody = c.mxy ? grid : 256;
+    // the worklist holds the body-near particles of grid cases (about 1%); mesh cases have
+    // their own kernel over the whole particle array
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(gbody), dim3(kBlock), 0, S_(s), c);
+        if (c.mxy) hipLaunchKernelGGL(k_move_mesh<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
     } else {
         hipLaunchKernelGGL(k_move_fast<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(gbody), dim3(kBlock), 0, S_(s), c);
+        if (c.mxy) hipLaunchKernelGGL(k_move_mesh<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(256), dim3(kBlock), 0, S_(s), c);
     }
 }
 void Launch::scatter(const Ctx &c, void *s)

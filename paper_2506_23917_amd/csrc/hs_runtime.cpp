@@ -352,7 +352,6 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         P.capacity += c.capacity;
         P.dim_max = std::max(P.dim_max, c.dim);
         if (c.dim > 0) P.any_spatial = true;
-        if (c.mesh) P.any_body = true;     // mesh particles take the worklist move
     }
     P.ncells = cell0;
 }

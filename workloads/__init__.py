@@ -324,3 +324,11 @@ def free_molecular_ogrid(s=1.0, T=300.0, T_w=500.0, n=1.0e13, R=0.3, r_out=1.0, 
                  body_r=R, body_T=T_w, regions=[((-big, -big, 0.0, big, big, 1.0), st)], F_N=fn,
                  dt_G=0.5 * first / (U + 3.0 * math.sqrt(R_ARGON * T)), T_sigma=T, seed=seed,
                  n_steady=0, capacity=int(2 * total) + 4096, n_surf=n_surf, mesh=m)
+
+
+def ogrid_batch(n_cases=12, seed0=300):
+    """The three O-grid runs of Sec. 4.2, repeated with different seeds: mesh1 (first layer
+    1 mm, growth 1.1) at Kn 0.01, mesh2 (growth 1.05) at Kn 0.01 and mesh1 at Kn 0.1, all
+    with outer radius 3 R; cases cycle through the three."""
+    kinds = [dict(growth=1.1, kn=0.01), dict(growth=1.05, kn=0.01), dict(growth=1.1, kn=0.1)]
+    return [cylinder_ogrid(seed=seed0 + i, **kinds[i % 3]) for i in range(n_cases)]
