@@ -177,3 +177,29 @@ def test_mesh_fp32_free_molecular_drag(gas):
     cds = np.array(cds)
     ref = cd_closed(s, T, Tw, False)
     assert abs(cds.mean() - ref) < 5.0 * cds.std(ddof=1) / math.sqrt(8) + 5e-3 * ref, (cds.mean(), ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mesh_graph_resume_and_tuning_change_nothing(gas, prec):
+    """On an O-grid: a graph-replayed run, a run resumed from an exported state (positions
+    relative to each cell's first node) and an autotuned run all equal the plain run."""
+    from test_gpu_properties import _same
+    case = mesh_cases()["ogrid"]
+    a = _sim(gas, case, precision=prec)
+    g = _sim(gas, case, precision=prec, graph=True)
+    for rnd in range(3):
+        a.step(2)
+        g.step(2)
+        _same(a.export_state(0), g.export_state(0), "%s replay %d" % (prec, rnd))
+    b = _sim(gas, case, precision=prec)
+    b.step(3)
+    c = _sim(gas, case, precision=prec, no_particles=True)
+    c.import_state(0, b.export_state(0))
+    c.step(3)
+    _same(a.export_state(0), c.export_state(0), prec + " resume")
+    t = _sim(gas, case, precision=prec)
+    rep = t.autotune(steps_per_trial=1)
+    t.step(2)
+    u = _sim(gas, case, precision=prec)
+    u.step(rep["steps"] + 2)
+    _same(t.export_state(0), u.export_state(0), prec + " tuned")
