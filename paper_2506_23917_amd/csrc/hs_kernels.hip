@@ -697,17 +697,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const bool valid = i < n_total;       // the valid lanes of a wave are a prefix
         int g = 0;
         P xr[3] = {(P)0, (P)0, (P)0}, v[3] = {(P)0, (P)0, (P)0};
-        // state loads first (guarded by the batch's largest dimension, not the case's); in a
-        // batch with mesh cases, only once the wave is known not to be a mesh case's
-        const bool early = C.mxy == nullptr;
         if (valid) {
+            // state loads first (guarded by the batch's largest dimension, not the case's)
             g = S.cell[i];
-            if (early) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
+            for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
-            }
+            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
         }
         // Cases are contiguous in the particle array (the sorted live part, then the injected
         // particles case by case), so a wave nearly always lies in the case of its first
@@ -716,12 +712,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const CaseDev &csu = case_const(C, cu);
         const bool one = __all(!valid || (g >= csu.cell0 && g < csu.cell0 + csu.ncells));
         if (one && csu.mesh) continue;          // a mesh case's wave: k_move_mesh moves it
-        if (!early && valid) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) if (a < C.dim_max) xr[a] = S.pos[a][i];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
-        }
         int nc = -1, cid = cu;
         bool to_body = false, skip = false;
         if (one) {
@@ -2108,11 +2098,12 @@ __global__ __launch_bounds__(64) void k_collide_tile_f64(Ctx C)
 }
 
 // Sort `a[0..p2)` ascending in LDS with a bitonic network (p2 a power of two).
+template <int NB>
 __device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
 {
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < p2; i += kBlock) {
+            for (int i = tid; i < p2; i += NB) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const int32_t x = a[i], y = a[ixj];
@@ -2128,17 +2119,25 @@ __device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
     }
 }
 
-// Cells denser than the tile kernel takes: one 256-thread block per cell.  The stages are
+// Largest cell of the block-per-cell kernel, and the size class below it (FP64): cells of up
+// to kCapBlockMid particles take 128-thread blocks, larger ones 256-thread blocks.  The FP64
+// kernel needs 256 registers a lane, so a 256-thread block fills a compute unit alone; two
+// 128-thread blocks per unit keep twice as many cells in flight.  Results do not depend on
+// the class.
+constexpr int kCapBlockMax = 2048;   // a power of two: the bitonic sort pads to one
+constexpr int kCapBlockMid = 512;
+
+// Cells denser than the tile kernel takes: one block per cell (its size class).  The stages are
 // those of k_cell_scalars and k_collide_tile with block-wide sums (every thread ends with the
 // same bits and derives the cell's scalars itself) and NTC rounds over the block.
-template <typename P, int CAPB>
-__global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
+template <typename P, int CAPB, int NB>
+__global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
 {
-    constexpr int KC = 2 * kBlock;             // NTC candidates per chunk (two per thread)
+    constexpr int KC = 2 * NB;             // NTC candidates per chunk (two per thread)
     static_assert(KC <= 1024, "candidate number fits the claim word");
     __shared__ int32_t s_src[CAPB];            // sources during the gather, then claim words
     __shared__ P s_v[3][CAPB];
-    __shared__ double s_red[(kBlock / 64) * 12];
+    __shared__ double s_red[(NB / 64) * 12];
     __shared__ unsigned long long s_obs, s_hash;
     __shared__ int s_nacc, s_left;
     __shared__ int32_t s_rel[3];
@@ -2162,9 +2161,10 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
         const int n = C.cstart[g + 1] - s0;
         const int cid = case_of(C, g);
         const CaseDev &cs = C.cases[cid];
+        if (n <= nmin) continue;               // a cell of the smaller size class
         if (n > CAPB) {
-            if (tid == 0) raise_error(G, kErrCellLimit);
-            continue;
+            if (CAPB >= kCapBlockMax && tid == 0) raise_error(G, kErrCellLimit);
+            continue;                          // else: a cell of the larger size class
         }
         if (tid == 0 && cid != my_case) {
             if (my_case >= 0) flush_counts(C, my_case, cc);
@@ -2173,10 +2173,10 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
         // stable order (sort of the source indices), gather, sorted state
         int p2 = 1;
         while (p2 < n) p2 <<= 1;
-        for (int k = tid; k < p2; k += kBlock) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
+        for (int k = tid; k < p2; k += NB) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
         __syncthreads();
-        if (use_perm) bitonic_sort(s_src, p2, tid);
-        for (int k = tid; k < n; k += kBlock) {
+        if (use_perm) bitonic_sort<NB>(s_src, p2, tid);
+        for (int k = tid; k < n; k += NB) {
             const int src = s_src[k];
             const size_t dst = (size_t)s0 + k;
             for (int a = 0; a < 3; ++a) if (a < cs.dim) Dd.pos[a][dst] = S.pos[a][src];
@@ -2187,7 +2187,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             s_v[2][k] = S.vel[2][src];
         }
         __syncthreads();
-        for (int k = tid; k < n; k += kBlock) s_claim[k] = 0u;
+        for (int k = tid; k < n; k += NB) s_claim[k] = 0u;
         if (tid == 0) {
             s_obs = 0ull;
             s_hash = 0ull;
@@ -2197,14 +2197,14 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
 
         // Eq. 31 moments
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = tid; k < n; k += kBlock) {
+        for (int k = tid; k < n; k += NB) {
             const double x = (double)s_v[0][k], y = (double)s_v[1][k], z = (double)s_v[2][k];
             s1[0] = s1[0] + x;
             s1[1] = s1[1] + y;
             s1[2] = s1[2] + z;
             s1[3] = s1[3] + (x * x + y * y + z * z);
         }
-        team_sum<kBlock, 4>(s1, s_red);
+        team_sum<NB, 4>(s1, s_red);
         double U[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) U[a] = s1[a] / (double)n;
@@ -2216,7 +2216,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 uf[a] = (float)U[a];
                 ud[a] = (float)(U[a] - (double)uf[a]);
             }
-            for (int k = tid; k < n; k += kBlock) {
+            for (int k = tid; k < n; k += NB) {
                 const float cx = (s_v[0][k] - uf[0]) - ud[0];
                 const float cy = (s_v[1][k] - uf[1]) - ud[1];
                 const float cz = (s_v[2][k] - uf[2]) - ud[2];
@@ -2227,7 +2227,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 s2[3] = s2[3] + (double)(c2 * cz);
             }
         } else {
-            for (int k = tid; k < n; k += kBlock) {
+            for (int k = tid; k < n; k += NB) {
                 const double cx = s_v[0][k] - U[0], cy = s_v[1][k] - U[1], cz = s_v[2][k] - U[2];
                 const double c2 = cx * cx + cy * cy + cz * cz;
                 s2[0] = s2[0] + c2;
@@ -2236,7 +2236,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 s2[3] = s2[3] + c2 * cz;
             }
         }
-        team_sum<kBlock, 4>(s2, s_red);
+        team_sum<NB, 4>(s2, s_red);
 
         // Eq. 10 / 25-28 split, N_col, Shakhov parameters (every thread alike)
         TraceDev *tr = (tid == 0 && tracing) ? &C.trace[g] : nullptr;
@@ -2328,7 +2328,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             bool pend[2];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int q = tid + kBlock * r;
+                const int q = tid + NB * r;
                 pend[r] = q < kn;
                 ci[r] = cj[r] = 0;
                 ck[r] = 0;
@@ -2358,7 +2358,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
             __syncthreads();
             for (;;) {
                 if (round == 0x3fffffu) {      // round counter exhausted: clear the claims
-                    for (int k = tid; k < n; k += kBlock) s_claim[k] = 0u;
+                    for (int k = tid; k < n; k += NB) s_claim[k] = 0u;
                     round = 0;
                     __syncthreads();
                 }
@@ -2366,7 +2366,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 uint32_t tag[2];
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
-                    tag[r] = (round << 10) | (uint32_t)(1023 - (tid + kBlock * r));
+                    tag[r] = (round << 10) | (uint32_t)(1023 - (tid + NB * r));
                     if (pend[r]) {
                         atomicMax(&s_claim[ci[r]], tag[r]);
                         atomicMax(&s_claim[cj[r]], tag[r]);
@@ -2423,17 +2423,17 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
         // SP-Shakhov relaxation (Eq. 16-18)
         if (pr > 0.0) {
             int nrel = 0, nar = 0, ncap = 0;
-            // decisions first (at most CAPB / kBlock particles per thread), then the draws
-            static_assert(CAPB / kBlock <= 32, "decision mask");
+            // decisions first (at most CAPB / NB particles per thread), then the draws
+            static_assert(CAPB / NB <= 32, "decision mask");
             uint32_t mask = 0u;
-            for (int k = tid, j = 0; k < n; k += kBlock, ++j) {
+            for (int k = tid, j = 0; k < n; k += NB, ++j) {
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 if (unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr) mask |= 1u << j;
             }
             while (mask) {
                 const int j = __ffs((int)mask) - 1;
                 mask &= mask - 1u;
-                const int k = tid + kBlock * j;
+                const int k = tid + NB * j;
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 P Cv[3];
                 int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, par, (P)(1.0 - gas.Pr), Cv);
@@ -2455,19 +2455,19 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
 
         // Eq. 19 rescale (each thread rescales the particles it summed), Step (5) sums
         double r1[3] = {0.0, 0.0, 0.0};
-        for (int k = tid; k < n; k += kBlock) {
+        for (int k = tid; k < n; k += NB) {
             r1[0] = r1[0] + (double)s_v[0][k];
             r1[1] = r1[1] + (double)s_v[1][k];
             r1[2] = r1[2] + (double)s_v[2][k];
         }
-        team_sum<kBlock, 3>(r1, s_red);
+        team_sum<NB, 3>(r1, s_red);
         const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
         double r2[1] = {0.0};
-        for (int k = tid; k < n; k += kBlock) {
+        for (int k = tid; k < n; k += NB) {
             const double cx = (double)s_v[0][k] - Up[0], cy = (double)s_v[1][k] - Up[1], cz = (double)s_v[2][k] - Up[2];
             r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
         }
-        team_sum<kBlock, 1>(r2, s_red);
+        team_sum<NB, 1>(r2, s_red);
         double f = 0.0;
         if (active) {
             const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(n - 1));
@@ -2478,7 +2478,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
         double sm[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) sm[j] = 0.0;
-        for (int k = tid; k < n; k += kBlock) {
+        for (int k = tid; k < n; k += NB) {
             double a = (double)s_v[0][k], bb = (double)s_v[1][k], c = (double)s_v[2][k];
             if (f > 0.0) {
                 a = U[0] + (a - Up[0]) * f;
@@ -2497,7 +2497,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_dense(Ctx C)
                 sm[9] += c2 * a; sm[10] += c2 * bb; sm[11] += c2 * c;
             }
         }
-        if (sums) team_sum<kBlock, 12>(sm, s_red);
+        if (sums) team_sum<NB, 12>(sm, s_red);
         if (tid == 0) {
             cc.relax += s_rel[0];
             cc.ar += s_rel[1];
@@ -2665,8 +2665,8 @@ __global__ void k_philox(uint64_t seed, uint32_t stream, uint64_t e0, uint32_t s
 // launchers
 // ------------------------------------------------------------------------------------
 
-constexpr int kCapBlock64 = 2048;   // powers of two: the bitonic sort pads to one
-constexpr int kCapBlock32 = 2048;
+constexpr int kCapBlock64 = kCapBlockMax;
+constexpr int kCapBlock32 = kCapBlockMax;
 
 static inline hipStream_t S_(void *s) { return (hipStream_t)s; }
 static inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
@@ -2771,8 +2771,14 @@ void Launch::collide(const Ctx &c, void *s)
 void Launch::dense(const Ctx &c, void *s)
 {
     const int gb = c.grid[HS_KERNEL_DENSE] > 0 ? c.grid[HS_KERNEL_DENSE] : std::max(1, std::min(c.ncells_total, 256 * 2));
-    if (c.precision == HS_FP64) hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64>), dim3(gb), dim3(kBlock), 0, S_(s), c);
-    else hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32>), dim3(gb), dim3(kBlock), 0, S_(s), c);
+    if (c.precision == HS_FP64) {
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMid, 128>), dim3(2 * gb), dim3(128), 0, S_(s), c, 0);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, kCapBlockMid);
+    } else {
+        // FP32 keeps one class: at 256 threads it already holds two blocks per compute unit,
+        // and 128-thread blocks measured slower
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 0);
+    }
 }
 void Launch::finish_step(const Ctx &c, void *s)
 {
