@@ -7,7 +7,10 @@
     python -m paper_2506_23917_amd.profile_workload --workload jets --warmup 2000 --steps 200
         the ragged batch of 32 planar jets (one launch per kernel for the whole batch, the
         step replayed from a captured graph); `--workload sphere` the 3-D Ma 10 sphere
-        (240 x 160 x 160).  Both print particle-steps/s of the timed steps.
+        (240 x 160 x 160); `--workload sod` 256 replicas of the Sod tube (200 cells, 160 / 20
+        particles per cell, graph replay); `--workload relax` the 0-D batch (4096 cells x 1000
+        particles from the skewed bi-Maxwellian state); `--workload ogrid` the batch of twelve
+        Ma 5 cylinder O-grids.  Each prints particle-steps/s of the timed steps.
     python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
         a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
         counters to bytes
@@ -29,7 +32,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere"])
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere", "sod", "relax", "ogrid"])
     args = ap.parse_args()
     import torch
     if args.copy_mib:
@@ -48,6 +51,23 @@ def main():
     if args.workload == "jets":
         cases = W.jets_2d()
         sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0", graph=True)
+    elif args.workload == "sod":
+        cases = [W.sod_1d(seed=1 + r, n_steady=0) for r in range(256)]
+        sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0", graph=True)
+    elif args.workload == "relax":
+        import numpy as np
+        case = W.relax_0d(n_steady=0)
+        cases = [case]
+        v, cell, ids = W.relax_0d_state(case)
+        sim = Sim(W.gas(), case, precision=args.precision, device="cuda:0", no_particles=True)
+        st0 = sim.export_state(0)
+        sim.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=len(ids),
+                                 step=0, sigc_max=st0["sigc_max"]))
+    elif args.workload == "ogrid":
+        cases = W.ogrid_batch()
+        for c in cases:
+            c["n_steady"] = args.warmup
+        sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0")
     else:
         case = W.cylinder_2d() if args.workload == "cylinder" else W.sphere_3d()
         case["n_steady"] = args.warmup
