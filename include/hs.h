@@ -10,7 +10,8 @@
  *   time-averaged sampling (Step 5).
  *
  * Conventions
- *  - SI units.  Cells of a case are numbered x-fastest; cell c = i + nx (j + ny k).
+ *  - SI units.  Cells of a grid case are numbered x-fastest, cell c = i + nx (j + ny k);
+ *    cells of a mesh case as in its hs_mesh.
  *  - Memory: the CALLER owns all device memory.  hs_plan() gives the workspace size; the
  *    caller allocates it (e.g. a torch uint8 tensor on the GPU) and passes it to
  *    hs_init_particles(), which carves every buffer out of it.  The workspace must
