@@ -203,3 +203,56 @@ def test_mesh_graph_resume_and_tuning_change_nothing(gas, prec):
     u = _sim(gas, case, precision=prec)
     u.step(rep["steps"] + 2)
     _same(t.export_state(0), u.export_state(0), prec + " tuned")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mesh_time_averages_agree_with_the_oracle(gas, prec):
+    """Small Ma 5 O-grid from the impulsive start, sampled from step 60 to 360: the GPU's
+    time-averaged n and T per cell against the oracle's (both from their pooled sums), in units
+    of the standard error of a difference of two such averages (from 10 batch means of the
+    oracle's run); cells with at least 20 samples in every batch."""
+    case = W.cylinder_ogrid(n_theta=48, first=0.02, growth=1.15, r_out=2.0, ppc_outer=60, seed=21,
+                            n_steady=60, n_surf=0)
+    ora = Oracle(gas, case)
+    ora.init_particles()
+    ora.step(60)
+    batches, prev = [], None
+    for _ in range(10):
+        ora.step(30)
+        acc = ora.get_cells(0)["acc"].copy()
+        batches.append(acc - (prev if prev is not None else 0.0))
+        prev = acc
+    vol = ora.get_cells(0)["vol"]
+    m = gas["m"]
+
+    def n_T(acc, nsamp):
+        N = acc[:, 0]
+        ok = N > 0
+        Ns = np.where(ok, N, 1.0)
+        n = np.where(ok, case["F_N"] * N / (nsamp * vol), 0.0)
+        cc = (acc[:, 4] + acc[:, 5] + acc[:, 6]) / Ns
+        uu = (acc[:, 1] ** 2 + acc[:, 2] ** 2 + acc[:, 3] ** 2) / Ns ** 2
+        return n, np.where(ok, m / (3 * W.K_BOLTZMANN) * (cc - uu), 0.0)
+
+    bn, bT = (np.array(x) for x in zip(*[n_T(a, 30) for a in batches]))
+    # the oracle's estimate from its pooled sums (as the GPU's), its spread from the batches
+    on, oT = n_T(prev, 300)
+    se_n = bn.std(0, ddof=1) / np.sqrt(10) * np.sqrt(2)
+    se_T = bT.std(0, ddof=1) / np.sqrt(10) * np.sqrt(2)
+    sim = _sim(gas, case, precision=prec)
+    sim.step(360)
+    g = sim.sample_moments(0, mode=0)
+    assert g["n_samples"] == 300
+    # cells with at least 20 samples in every batch (a batch mean of T over fewer, often one
+    # particle seen repeatedly, is no estimate of the cell's temperature)
+    nb_min = np.min([b[:, 0] for b in batches], axis=0)
+    sel = (nb_min >= 20) & (se_n > 0) & (se_T > 0)
+    assert sel.sum() > 0.5 * len(sel)
+    zn = (g["n"][sel] - on[sel]) / se_n[sel]
+    zT = (g["T"][sel] - oT[sel]) / se_T[sel]
+    print(prec, "mean z^2 n %.3f T %.3f" % ((zn ** 2).mean(), (zT ** 2).mean()))
+    # z of a difference over 10 batch means follows Student's t with 9 degrees of freedom:
+    # E z^2 = 9/7, P(|z| > 4) = 0.3%
+    for z in (zn, zT):
+        assert (z ** 2).mean() < 2.0
+        assert (abs(z) > 4).mean() < 0.02
