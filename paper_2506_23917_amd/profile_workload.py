@@ -11,6 +11,11 @@
         particles per cell, graph replay); `--workload relax` the 0-D batch (4096 cells x 1000
         particles from the skewed bi-Maxwellian state); `--workload ogrid` the batch of twelve
         Ma 5 cylinder O-grids.  Each prints particle-steps/s of the timed steps.
+    python -m paper_2506_23917_amd.profile_workload --workload sod --accuracy --warmup 40
+        FP32-mixed against FP64 from the same state: the FP64 path runs `warmup` steps, its
+        state is imported into an FP32-mixed sim (the first four cases of a batch), both take
+        one step with the same random numbers, and the relative L2 differences of the cells'
+        n, u, T, q (Eq. 31 estimators of the current particles) are printed
     python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
         a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
         counters to bytes
@@ -32,6 +37,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--accuracy", action="store_true")
     ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere", "sod", "relax", "ogrid"])
     args = ap.parse_args()
     import torch
@@ -48,6 +54,9 @@ def main():
     import time
     import workloads as W
     from paper_2506_23917_amd.hs import Sim
+    if args.accuracy:
+        paired_accuracy(args)
+        return
     if args.workload == "jets":
         cases = W.jets_2d()
         sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0", graph=True)
@@ -91,6 +100,60 @@ def main():
     n1 = sum(sim.num_particles(c) for c in range(nc))
     print("timed steps %d, particles %d, %.4f ms/step, %.4e particle-steps/s" %
           (args.steps, n1, 1e3 * dt / max(args.steps, 1), 0.5 * (n0 + n1) * args.steps / dt), flush=True)
+
+
+def _cases(name, warmup):
+    import workloads as W
+    if name == "cylinder":
+        return [W.cylinder_2d()]
+    if name == "sphere":
+        return [W.sphere_3d()]
+    if name == "jets":
+        return W.jets_2d()[:4]
+    if name == "sod":
+        return [W.sod_1d(seed=1 + r) for r in range(4)]
+    if name == "relax":
+        return [W.relax_0d()]
+    return W.ogrid_batch()[:4]
+
+
+def paired_accuracy(args):
+    import numpy as np
+    import workloads as W
+    from paper_2506_23917_amd.hs import Sim
+    gas = W.gas()
+    cases = _cases(args.workload, args.warmup)
+    if args.workload == "relax":
+        s64 = Sim(gas, cases, precision="fp64", device="cuda:0", no_particles=True)
+        v, cell, ids = W.relax_0d_state(cases[0])
+        st0 = s64.export_state(0)
+        s64.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=len(ids),
+                                 step=0, sigc_max=st0["sigc_max"]))
+    else:
+        s64 = Sim(gas, cases, precision="fp64", device="cuda:0")
+    done = 0
+    while done < args.warmup:
+        k = min(500, args.warmup - done)
+        s64.step(k)
+        s64.sync()
+        done += k
+    s32 = Sim(gas, cases, precision="fp32", device="cuda:0", no_particles=True)
+    for c in range(len(cases)):
+        s32.import_state(c, s64.export_state(c))
+    s64.step(1)
+    s32.step(1)
+    a = [s32.sample_moments(c, mode=1) for c in range(len(cases))]
+    b = [s64.sample_moments(c, mode=1) for c in range(len(cases))]
+    cat = lambda L, k: np.concatenate([np.asarray(x[k]).reshape(len(x["n"]), -1) for x in L])
+    n32, n64 = cat(a, "n"), cat(b, "n")
+    sel = (n64[:, 0] > 0)
+    rel = lambda x, y: float(np.sqrt(np.sum((x - y) ** 2)) / max(np.sqrt(np.sum(y ** 2)), 1e-300))
+    out = {k: rel(cat(a, k)[sel], cat(b, k)[sel]) for k in ("n", "T", "q")}
+    u32, u64, T64 = cat(a, "u")[sel], cat(b, "u")[sel], cat(b, "T")[sel]
+    scale = np.sqrt(np.sum(u64 ** 2) + np.sum(1.380649e-23 * np.maximum(T64, 0.0) / gas["m"]))
+    out["u"] = float(np.sqrt(np.sum((u32 - u64) ** 2)) / scale)
+    print("accuracy %s cases %d cells %d after %d FP64 steps: n %.3e u %.3e T %.3e q %.3e" %
+          (args.workload, len(cases), int(sel.sum()), args.warmup, out["n"], out["u"], out["T"], out["q"]), flush=True)
 
 
 if __name__ == "__main__":
