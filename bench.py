@@ -11,7 +11,8 @@ resident in HBM when the timed region starts (the state never leaves the device)
 The roofline object is for the dominant kernel (the tile collision kernel), timed with HIP
 events on the simulation's stream inside the timed region.  Its HBM traffic comes from a
 committed rocprofv3 counter summary and is reported only while the kernel sources are the
-ones it was measured on.
+ones it was measured on; so does `valu_active_frac`, the share of the kernel's time its SIMDs
+spend issuing vector-ALU instructions (SQ counters), which shows what bounds it instead of HBM.
 
 The FP64 run's developed state is then imported into an FP32-mixed sim and both take one step
 from it with the same random numbers: the relative L2 differences of the cell moments n, u, T, q
@@ -52,6 +53,7 @@ STEP_BYTES_PER_PARTICLE = 128
 # neighbours are per cell and stay in cache.
 MESH_MOVE_BYTES_PER_PARTICLE = 24 + 28
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_valu.txt")
 KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.hpp", "hs_common.hpp"]
 
 
@@ -78,6 +80,19 @@ def committed_traffic():
     if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
         return None
     return float(m_b.group(1))
+
+
+def committed_valu():
+    """Share of the tile kernel's time its SIMDs spend issuing VALU instructions, from the
+    committed SQ counter summary, if it was measured on the current kernel sources; else None."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    txt = open(VALU_FILE).read()
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    m_f = re.search(r"valu_active_frac:\s*([0-9.]+)", txt)
+    if not m_h or not m_f or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_f.group(1))
 
 
 def run_gpu(prec, case, gas, warmup, steps, timed_group="collide"):
@@ -246,7 +261,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_collide_tile<float> (NTC, Shakhov, rescale, sampling on LDS tiles)",
                      "kernel_ms": r32["tile_ms"], "launches_timed": r32["launches"],
-                     "algorithmic_bytes_per_launch": tile_bytes},
+                     "algorithmic_bytes_per_launch": tile_bytes,
+                     "valu_active_frac": committed_valu()},
         "step_roofline": {"bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
                           "achieved_GBs": STEP_BYTES_PER_PARTICLE * value / 1e9,
                           "frac": STEP_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS},
