@@ -25,8 +25,10 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
-        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
+        // one 32 x 32 -> 64-bit product per multiplier (a single v_mad_u64_u32) gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
         const uint32_t n0 = h1 ^ c1 ^ k0;
         const uint32_t n2 = h0 ^ c3 ^ k1;
         c0 = n0;
@@ -497,11 +499,6 @@ __device__ __forceinline__ void mesh_nodes(const Ctx &C, int g, double P[4][2])
         P[j][0] = p.x;
         P[j][1] = p.y;
     }
-}
-
-__device__ __forceinline__ double2 mesh_origin(const Ctx &C, int g)
-{
-    return ((const double2 *)C.mxy)[C.mquad[4 * (size_t)g]];
 }
 
 // Point of the bilinear map of a quad at (u, w) and the map's Jacobian (dX/du x dX/dw).
