@@ -202,3 +202,30 @@ def test_bad_meshes_are_rejected(what):
     case["mesh"] = m
     with pytest.raises(OracleError):
         Oracle(GAS, case)
+
+
+def test_mesh_cell_length_sets_the_adaptive_step():
+    """Eq. 25-26 on a jittered mesh: the next global step is the smallest L_k / (|U_k| +
+    sqrt(gamma R T_k)) over the cells with N >= 2, where L_k is the quad's area over its
+    longest edge computed here from the node coordinates, and U_k, T_k are the cells' Step 3
+    moments (the trace's pre-collision sums and temperature)."""
+    case = _base(seed=6)
+    case["bc"] = ("specular",) * 4 + ("outflow",) * 2
+    mc = W.mesh_twin(case, jitter=0.2)
+    mc["adapt_dt"] = True
+    o = Oracle(GAS, mc, trace=True)
+    o.init_particles()
+    o.step(1)
+    tr = o.trace(0)
+    xy, quad = mc["mesh"]["xy"], mc["mesh"]["quad"]
+    P = xy[quad]                                           # (cells, 4, 2)
+    e = np.roll(P, -1, axis=1) - P
+    longest = np.hypot(e[..., 0], e[..., 1]).max(axis=1)
+    d1, d2 = P[:, 2] - P[:, 0], P[:, 3] - P[:, 1]
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    np.testing.assert_allclose(o.get_cells(0)["vol"], area * mc["h"][2], rtol=1e-12)
+    act = (tr["n"] >= 2) & (tr["T"] > 0)
+    U = tr["pre_sum"][act, :3] / tr["n"][act, None]
+    R = W.K_BOLTZMANN / W.ARGON["m"]
+    dtc = (area / longest)[act] / (np.linalg.norm(U, axis=1) + np.sqrt(W.ARGON["gamma"] * R * tr["T"][act]))
+    assert abs(o.step_dt(0)[0] / dtc.min() - 1.0) < 1e-12
