@@ -343,10 +343,68 @@ static void mesh_cell_geometry(const hso_mesh *m, int64_t k, double *area, doubl
     *longest = lmax;
 }
 
+/* Hexahedra (3-D meshes): nodes 0-3 the bottom quad, counter-clockwise seen from above, nodes
+ * 4-7 above them; face f has the nodes HEX_FACE[f], counter-clockwise seen from outside. */
+static const int HEX_FACE[6][4] = { { 0, 3, 2, 1 }, { 4, 5, 6, 7 }, { 0, 1, 5, 4 },
+                                    { 1, 2, 6, 5 }, { 2, 3, 7, 6 }, { 3, 0, 4, 7 } };
+
+static void hex_node(const hso_mesh *m, int64_t k, int j, double P[3])
+{
+    int32_t n = m->quad[8 * k + j];
+    for (int a = 0; a < 3; ++a) P[a] = m->xy[3 * n + a];
+}
+
+/* Face f of hexahedron k: its first node A and the cross product of its diagonals,
+ * nf = (P2 - P0) x (P3 - P1), which for a planar face is the outward normal times twice its
+ * area (a face collapsed to a segment gives 0). */
+static void hex_face(const hso_mesh *m, int64_t k, int f, double A[3], double nf[3])
+{
+    double P[4][3];
+    for (int j = 0; j < 4; ++j) hex_node(m, k, HEX_FACE[f][j], P[j]);
+    double d1[3], d2[3];
+    for (int a = 0; a < 3; ++a) {
+        A[a] = P[0][a];
+        d1[a] = P[2][a] - P[0][a];
+        d2[a] = P[3][a] - P[1][a];
+    }
+    nf[0] = d1[1] * d2[2] - d1[2] * d2[1];
+    nf[1] = d1[2] * d2[0] - d1[0] * d2[2];
+    nf[2] = d1[0] * d2[1] - d1[1] * d2[0];
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Volume as six pyramids from the mean of the nodes, and the largest face area. */
+static void hex_geometry(const hso_mesh *m, int64_t k, double *vol, double *amax)
+{
+    double xc[3] = { 0.0, 0.0, 0.0 }, P[3];
+    for (int j = 0; j < 8; ++j) {
+        hex_node(m, k, j, P);
+        for (int a = 0; a < 3; ++a) xc[a] = xc[a] + P[a];
+    }
+    for (int a = 0; a < 3; ++a) xc[a] = 0.125 * xc[a];
+    double v = 0.0, am = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        double A[3], nf[3], d[3];
+        hex_face(m, k, f, A, nf);
+        for (int a = 0; a < 3; ++a) d[a] = A[a] - xc[a];
+        v = v + dot3(d, nf) / 6.0;
+        double ar = 0.5 * sqrt(dot3(nf, nf));
+        if (ar > am) am = ar;
+    }
+    *vol = v;
+    *amax = am;
+}
+
 /* Eq. 25's L_cell (reading: the cell's thickness): the smallest edge of a grid cell; a mesh
  * quad's area over its longest edge, which is the same for a rectangle. */
 static double cell_length(const hso_case *c, int64_t k)
 {
+    if (c->mesh && c->dim == 3) {
+        double v, am;
+        hex_geometry(c->mesh, k, &v, &am);
+        return v / am;                  /* volume over the largest face: a box's smallest edge */
+    }
     if (c->mesh) {
         double a, l;
         mesh_cell_geometry(c->mesh, k, &a, &l);
@@ -359,6 +417,11 @@ static double cell_length(const hso_case *c, int64_t k)
 
 static double cell_volume(const hso_case *c, int64_t k)
 {
+    if (c->mesh && c->dim == 3) {
+        double v, am;
+        hex_geometry(c->mesh, k, &v, &am);
+        return v;
+    }
     if (c->mesh) {
         double a, l;
         mesh_cell_geometry(c->mesh, k, &a, &l);
@@ -434,8 +497,73 @@ static int validate_mesh(const hso_case *c)
     return HSO_OK;
 }
 
+/* A hexahedral mesh: node ids in range, planar faces (a face may collapse to a triangle or a
+ * segment), every node on the inner side of every face (convex cells) and a positive volume;
+ * neighbours name each other across faces with the same four nodes; boundary codes as for
+ * quads.  Tolerances are 1e-9 of the cell's size. */
+static int validate_hex(const hso_case *c)
+{
+    const hso_mesh *m = c->mesh;
+    if (m->n_cells <= 0 || m->n_nodes <= 0 || !m->xy || !m->quad || !m->nbr) return HSO_EARG;
+    if (c->body == HSO_BODY_CYLINDER) return HSO_EARG;
+    for (int64_t k = 0; k < m->n_cells; ++k) {
+        for (int j = 0; j < 8; ++j)
+            if (m->quad[8 * k + j] < 0 || m->quad[8 * k + j] >= m->n_nodes) return HSO_EARG;
+        double v, am;
+        hex_geometry(m, k, &v, &am);
+        if (!(v > 0.0)) return HSO_EARG;
+        double size = cbrt(v);
+        for (int f = 0; f < 6; ++f) {
+            double A[3], nf[3];
+            hex_face(m, k, f, A, nf);
+            double ln = sqrt(dot3(nf, nf));
+            if (ln > 0.0) {
+                for (int j = 0; j < 8; ++j) {
+                    double P[3], d[3];
+                    hex_node(m, k, j, P);
+                    for (int a = 0; a < 3; ++a) d[a] = A[a] - P[a];
+                    double sd = dot3(d, nf) / ln;       /* >= 0 inside, 0 on the face */
+                    int on_face = 0;
+                    for (int i = 0; i < 4; ++i) on_face |= HEX_FACE[f][i] == j;
+                    if (on_face ? fabs(sd) > 1e-9 * size : sd < -1e-9 * size) return HSO_EARG;
+                }
+            }
+            int32_t nb = m->nbr[6 * k + f];
+            if (nb >= 0) {
+                if (nb >= m->n_cells) return HSO_EARG;
+                int back = 0;
+                for (int i = 0; i < 6 && !back; ++i) {
+                    if (m->nbr[6 * (int64_t)nb + i] != (int32_t)k) continue;
+                    int same = 1;
+                    for (int a = 0; a < 4; ++a) {
+                        int found = 0;
+                        for (int b = 0; b < 4; ++b)
+                            found |= m->quad[8 * (int64_t)nb + HEX_FACE[i][b]] == m->quad[8 * k + HEX_FACE[f][a]];
+                        same &= found;
+                    }
+                    back = same;
+                }
+                if (!back) return HSO_EARG;
+            } else if (nb == HSO_EDGE_WALL) {
+                if (!(c->body_T > 0.0)) return HSO_EARG;
+            } else if (nb == HSO_EDGE_INFLOW) {
+                if (!(c->inflow.T > 0.0) || c->inflow.n < 0.0) return HSO_EARG;
+            } else if (nb != HSO_EDGE_OUTFLOW && nb != HSO_EDGE_SPECULAR) {
+                return HSO_EARG;
+            }
+        }
+    }
+    if (c->n_surf > 0 && (c->body != HSO_BODY_SPHERE || !(c->body_r > 0.0))) return HSO_EARG;
+    return HSO_OK;
+}
+
 static int validate_case(const hso_case *c)
 {
+    if (c->mesh && c->dim == 3) {
+        for (int a = 0; a < 3; ++a) if (!(c->h[a] > 0.0)) return HSO_EARG;
+        if (!(c->F_N > 0.0) || !(c->T_sigma > 0.0) || c->capacity < 0 || !(c->dt_G > 0.0)) return HSO_EARG;
+        return validate_hex(c);
+    }
     if (c->mesh) {
         for (int a = 0; a < 3; ++a) if (!(c->h[a] > 0.0)) return HSO_EARG;
         if (!(c->F_N > 0.0) || !(c->T_sigma > 0.0) || c->capacity < 0 || !(c->dt_G > 0.0)) return HSO_EARG;
@@ -515,10 +643,36 @@ static int build_mesh_faces(const hso_gas *g, ocase *oc)
     return HSO_OK;
 }
 
+/* Inflow faces of a hexahedral mesh, in cell and face order: area |nf| / 2, inward unit
+ * normal -nf / |nf| (faces collapsed to a segment take no inflow). */
+static int build_hex_faces(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    oc->faces = calloc((size_t)m->n_cells * 6, sizeof(face_t));
+    if (!oc->faces) return HSO_ECAP;
+    for (int64_t k = 0; k < m->n_cells; ++k)
+        for (int f = 0; f < 6; ++f) {
+            if (m->nbr[6 * k + f] != HSO_EDGE_INFLOW) continue;
+            double A[3], nf[3];
+            hex_face(m, k, f, A, nf);
+            double ln = sqrt(dot3(nf, nf));
+            if (!(ln > 0.0)) continue;
+            double nrm[3] = { -nf[0] / ln, -nf[1] / ln, -nf[2] / ln };
+            double flux = hso_inflow_number_flux(g, &c->inflow, nrm);
+            face_t *fc = &oc->faces[oc->nfaces++];
+            fc->cell = (int32_t)k;
+            fc->side = f;
+            fc->lambda = flux * (0.5 * ln) * c->dt_G / c->F_N;
+        }
+    return HSO_OK;
+}
+
 static int build_faces(const hso_gas *g, ocase *oc)
 {
     const hso_case *c = &oc->p;
     oc->nfaces = 0;
+    if (c->mesh && c->dim == 3) return build_hex_faces(g, oc);
     if (c->mesh) return build_mesh_faces(g, oc);
     if (c->dim == 0) return HSO_OK;
     int64_t n[3] = { c->nx, c->dim >= 2 ? c->ny : 1, c->dim >= 3 ? c->nz : 1 };
@@ -593,13 +747,15 @@ int hso_create(const hso_gas *gas, const hso_case *cases, int n_cases, int trace
         oc->p.region_state = oc->region_state;
         if (c->mesh) {
             const hso_mesh *m = c->mesh;
-            oc->mxy = malloc(sizeof(double) * 2 * (size_t)m->n_nodes);
-            oc->mquad = malloc(sizeof(int32_t) * 4 * (size_t)m->n_cells);
-            oc->mnbr = malloc(sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            /* per node 2 or 3 coordinates; per cell 4 or 8 nodes and 4 or 6 neighbours */
+            size_t dn = c->dim == 3 ? 3 : 2, vn = c->dim == 3 ? 8 : 4, fn = c->dim == 3 ? 6 : 4;
+            oc->mxy = malloc(sizeof(double) * dn * (size_t)m->n_nodes);
+            oc->mquad = malloc(sizeof(int32_t) * vn * (size_t)m->n_cells);
+            oc->mnbr = malloc(sizeof(int32_t) * fn * (size_t)m->n_cells);
             if (!oc->mxy || !oc->mquad || !oc->mnbr) { hso_destroy(s); return HSO_ECAP; }
-            memcpy(oc->mxy, m->xy, sizeof(double) * 2 * (size_t)m->n_nodes);
-            memcpy(oc->mquad, m->quad, sizeof(int32_t) * 4 * (size_t)m->n_cells);
-            memcpy(oc->mnbr, m->nbr, sizeof(int32_t) * 4 * (size_t)m->n_cells);
+            memcpy(oc->mxy, m->xy, sizeof(double) * dn * (size_t)m->n_nodes);
+            memcpy(oc->mquad, m->quad, sizeof(int32_t) * vn * (size_t)m->n_cells);
+            memcpy(oc->mnbr, m->nbr, sizeof(int32_t) * fn * (size_t)m->n_cells);
             oc->mesh.n_nodes = m->n_nodes;
             oc->mesh.n_cells = m->n_cells;
             oc->mesh.xy = oc->mxy;
@@ -674,7 +830,16 @@ static const hso_state *region_of(const hso_case *c, int64_t k)
     if (c->dim == 0) return &c->region_state[0];
     int64_t ijk[3];
     double mc[2] = { 0.0, 0.0 };
-    if (c->mesh) {
+    double mc3[3] = { 0.0, 0.0, 0.0 };
+    if (c->mesh && c->dim == 3) {
+        /* a hexahedron's centre: the mean of its eight nodes */
+        for (int j = 0; j < 8; ++j) {
+            double P[3];
+            hex_node(c->mesh, k, j, P);
+            for (int a = 0; a < 3; ++a) mc3[a] = mc3[a] + P[a];
+        }
+        for (int a = 0; a < 3; ++a) mc3[a] = 0.125 * mc3[a];
+    } else if (c->mesh) {
         /* a mesh cell's centre: the mean of its four nodes */
         for (int j = 0; j < 4; ++j) {
             double P[2];
@@ -691,7 +856,7 @@ static const hso_state *region_of(const hso_case *c, int64_t k)
         const double *b = &c->region_box[6 * r];
         int in = 1;
         for (int a = 0; a < c->dim; ++a) {
-            double ctr = c->mesh ? mc[a] : c->lo[a] + ((double)ijk[a] + 0.5) * c->h[a];
+            double ctr = (c->mesh && c->dim == 3) ? mc3[a] : c->mesh ? mc[a] : c->lo[a] + ((double)ijk[a] + 0.5) * c->h[a];
             if (!(ctr >= b[a] && ctr < b[3 + a])) in = 0;
         }
         if (in) return &c->region_state[r];
@@ -743,6 +908,40 @@ static void mesh_place(const hso_mesh *m, int64_t k, uint64_t seed, int64_t q, d
     x[1] = X[1];
 }
 
+/* Step (1) in a hexahedron: a point uniform in its bounding box (draw words 0-2, as the grid
+ * cell's), accepted when it lies on the inner side of every face; after MAX_POS_TRY
+ * rejections the mean of the nodes. */
+static void hex_place(const hso_mesh *m, int64_t k, uint64_t seed, int64_t q, double x[3])
+{
+    double lo[3], hi[3], P[3], xc[3] = { 0.0, 0.0, 0.0 };
+    for (int j = 0; j < 8; ++j) {
+        hex_node(m, k, j, P);
+        for (int a = 0; a < 3; ++a) {
+            if (j == 0 || P[a] < lo[a]) lo[a] = P[a];
+            if (j == 0 || P[a] > hi[a]) hi[a] = P[a];
+            xc[a] = xc[a] + P[a];
+        }
+    }
+    for (int t = 0; t < MAX_POS_TRY; ++t) {
+        uint32_t w[4];
+        hso_draw(seed, ST_INIT, (uint64_t)k, 0, (uint32_t)(1 + 128 * q + t), w);
+        double X[3];
+        for (int a = 0; a < 3; ++a) X[a] = lo[a] + hso_uniform(w[a]) * (hi[a] - lo[a]);
+        int in = 1;
+        for (int f = 0; f < 6 && in; ++f) {
+            double A[3], nf[3], d[3];
+            hex_face(m, k, f, A, nf);
+            for (int a = 0; a < 3; ++a) d[a] = A[a] - X[a];
+            if (dot3(d, nf) < 0.0) in = 0;
+        }
+        if (in) {
+            for (int a = 0; a < 3; ++a) x[a] = X[a];
+            return;
+        }
+    }
+    for (int a = 0; a < 3; ++a) x[a] = 0.125 * xc[a];
+}
+
 /* Step (1): particles uniformly at random inside each cell's fluid part, velocities
  * U + C with C from Eq. 17.  N_k = floor(n V_k / F_N + u). Ids run in cell order. */
 static int init_case(const hso_gas *g, ocase *oc)
@@ -772,7 +971,9 @@ static int init_case(const hso_gas *g, ocase *oc)
             int64_t i = oc->np++;
             double *x = &oc->x[3 * i];
             x[0] = x[1] = x[2] = 0.0;
-            if (c->mesh) {
+            if (c->mesh && c->dim == 3) {
+                hex_place(c->mesh, k, c->seed, q, x);
+            } else if (c->mesh) {
                 mesh_place(c->mesh, k, c->seed, q, x);
             } else if (c->dim > 0) {
                 int placed = 0;
@@ -889,9 +1090,113 @@ static int inject_mesh(const hso_gas *g, ocase *oc)
     return HSO_OK;
 }
 
+/* Inflow through a hexahedron's face: the grid face's draws in the face's frame.  n is the
+ * inward unit normal; the tangents t1, t2 come from the two coordinate axes other than the
+ * one n is most aligned with (lower index first), by Gram-Schmidt (for an axis-aligned face:
+ * the grid face's two tangential axes).  The point is the face's bilinear map from the corner
+ * of smallest t1 + t2 coordinate, u towards its neighbour of larger t1 coordinate, accepted
+ * with probability J / J_max (draw words 0, 1 the coordinates, word 2 the test; retries at
+ * draws +66 + r).  c = n z_n / beta + t1 (U.t1 + a cos(2 pi R1) sqrt(-ln R2)) +
+ * t2 (U.t2 + a sin(2 pi R1) sqrt(-ln R2)). */
+static int inject_hex(const hso_gas *g, ocase *oc)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    double beta = 1.0 / sqrt(2.0 * R * c->inflow.T);
+    for (int64_t f = 0; f < oc->nfaces; ++f) {
+        const face_t *fc = &oc->faces[f];
+        uint32_t w[4];
+        hso_draw(c->seed, ST_FACE, (uint64_t)f, st, 0, w);
+        double lam = c->adapt_dt ? fc->lambda * (oc->dt_cur / c->dt_G) : fc->lambda;
+        int64_t nf = (int64_t)floor(lam + hso_uniform(w[0]));
+        double P[4][3], A[3], nfv[3];
+        for (int j = 0; j < 4; ++j) hex_node(m, fc->cell, HEX_FACE[fc->side][j], P[j]);
+        hex_face(m, fc->cell, fc->side, A, nfv);
+        double ln = sqrt(dot3(nfv, nfv));
+        double n[3] = { -nfv[0] / ln, -nfv[1] / ln, -nfv[2] / ln };
+        int ax = 0;
+        for (int a = 1; a < 3; ++a) if (fabs(n[a]) > fabs(n[ax])) ax = a;
+        int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+        double t1[3] = { 0.0, 0.0, 0.0 }, t2[3] = { 0.0, 0.0, 0.0 };
+        t1[a1] = 1.0;
+        t2[a2] = 1.0;
+        double p1 = n[a1];
+        for (int a = 0; a < 3; ++a) t1[a] = t1[a] - p1 * n[a];
+        double l1 = sqrt(dot3(t1, t1));
+        for (int a = 0; a < 3; ++a) t1[a] = t1[a] / l1;
+        double q2 = n[a2], r2 = t1[a2];
+        for (int a = 0; a < 3; ++a) t2[a] = t2[a] - q2 * n[a] - r2 * t1[a];
+        double l2 = sqrt(dot3(t2, t2));
+        for (int a = 0; a < 3; ++a) t2[a] = t2[a] / l2;
+        int o = 0;
+        for (int j = 1; j < 4; ++j)
+            if (dot3(t1, P[j]) + dot3(t2, P[j]) < dot3(t1, P[o]) + dot3(t2, P[o])) o = j;
+        int ju = (o + 1) & 3, jv = (o + 3) & 3;
+        if (dot3(t1, P[jv]) > dot3(t1, P[ju])) { int tmp = ju; ju = jv; jv = tmp; }
+        const double *Po = P[o], *Pu = P[ju], *Pv = P[jv], *Pw = P[(o + 2) & 3];
+        double jmax = 0.0;
+        for (int cu = 0; cu < 2; ++cu)
+            for (int cv = 0; cv < 2; ++cv) {
+                double du[3], dv[3], cr[3];
+                for (int a = 0; a < 3; ++a) {
+                    du[a] = (1.0 - cv) * (Pu[a] - Po[a]) + cv * (Pw[a] - Pv[a]);
+                    dv[a] = (1.0 - cu) * (Pv[a] - Po[a]) + cu * (Pw[a] - Pu[a]);
+                }
+                cr[0] = du[1] * dv[2] - du[2] * dv[1];
+                cr[1] = du[2] * dv[0] - du[0] * dv[2];
+                cr[2] = du[0] * dv[1] - du[1] * dv[0];
+                double jc = sqrt(dot3(cr, cr));
+                if (jc > jmax) jmax = jc;
+            }
+        double sn = dot3(c->inflow.u, n) * beta;
+        double ut1 = dot3(c->inflow.u, t1), ut2 = dot3(c->inflow.u, t2);
+        for (int64_t q = 0; q < nf; ++q) {
+            if (oc->np >= oc->cap) return HSO_ECAP;
+            int64_t i = oc->np++;
+            double *x = &oc->x[3 * i], *v = &oc->v[3 * i];
+            uint32_t base = (uint32_t)(1 + 128 * q);
+            double u = 0.5, vv = 0.5;
+            for (int r = 0; r < 32; ++r) {
+                hso_draw(c->seed, ST_FACE, (uint64_t)f, st, r == 0 ? base : base + 66 + (uint32_t)r, w);
+                double uu = hso_uniform(w[0]), vq = hso_uniform(w[1]);
+                double du[3], dv[3], cr[3];
+                for (int a = 0; a < 3; ++a) {
+                    du[a] = (1.0 - vq) * (Pu[a] - Po[a]) + vq * (Pw[a] - Pv[a]);
+                    dv[a] = (1.0 - uu) * (Pv[a] - Po[a]) + uu * (Pw[a] - Pu[a]);
+                }
+                cr[0] = du[1] * dv[2] - du[2] * dv[1];
+                cr[1] = du[2] * dv[0] - du[0] * dv[2];
+                cr[2] = du[0] * dv[1] - du[1] * dv[0];
+                if (hso_uniform(w[2]) * jmax < sqrt(dot3(cr, cr))) { u = uu; vv = vq; break; }
+            }
+            for (int a = 0; a < 3; ++a)
+                x[a] = (1.0 - u) * (1.0 - vv) * Po[a] + u * (1.0 - vv) * Pu[a] + u * vv * Pw[a] + (1.0 - u) * vv * Pv[a];
+            hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 1, w);
+            double at = sqrt(2.0 * R * c->inflow.T);
+            double rr = sqrt(-log(hso_uniform(w[1])));
+            double v1 = ut1 + at * cos(2.0 * PI * hso_uniform(w[0])) * rr;
+            double v2 = ut2 + at * sin(2.0 * PI * hso_uniform(w[0])) * rr;
+            uint32_t ws[4 * MAX_INJ_AR];
+            for (int att = 0; att < MAX_INJ_AR; ++att)
+                hso_draw(c->seed, ST_FACE, (uint64_t)f, st, base + 2 + (uint32_t)att, &ws[4 * att]);
+            int used;
+            double z = hso_sample_normal_speed(sn, ws, MAX_INJ_AR, &used);
+            if (used < 0) oc->cnt.inject_cap++;
+            for (int a = 0; a < 3; ++a) v[a] = n[a] * z / beta + t1[a] * v1 + t2[a] * v2;
+            oc->cell[i] = fc->cell;
+            oc->id[i] = oc->next_id++;
+            oc->cnt.injected++;
+        }
+    }
+    return HSO_OK;
+}
+
 static int inject(const hso_gas *g, ocase *oc)
 {
     const hso_case *c = &oc->p;
+    if (c->mesh && c->dim == 3) return inject_hex(g, oc);
     if (c->mesh) return inject_mesh(g, oc);
     double R = KB / g->m;
     uint32_t st = (uint32_t)oc->step;
@@ -986,7 +1291,7 @@ static void diffuse_reflect_n(const hso_case *c, double R, const double nrm[3], 
                               double v[3])
 {
     double t1[3] = { 0.0, 0.0, 0.0 }, t2[3] = { 0.0, 0.0, 0.0 };
-    if (c->mesh || c->body == HSO_BODY_CYLINDER) {
+    if ((c->mesh && c->dim == 2) || c->body == HSO_BODY_CYLINDER) {
         t1[0] = -nrm[1]; t1[1] = nrm[0];
         t2[2] = 1.0;
     } else {
@@ -1172,6 +1477,66 @@ static int32_t move_mesh(const hso_gas *g, ocase *oc, int32_t k, double *x, doub
             double vn = v[0] * nrm[0] + v[1] * nrm[1];
             v[0] = v[0] - 2.0 * vn * nrm[0];
             v[1] = v[1] - 2.0 * vn * nrm[1];
+            continue;
+        }
+        oc->cnt.wall_hits++;
+        if (bounce == MAX_BOUNCE) { oc->cnt.bounce_cap++; return k; }
+        uint32_t w[4];
+        hso_draw(c->seed, ST_PARTICLE, (uint64_t)id, st, (uint32_t)(DRAW_BOUNCE + bounce), w);
+        ++bounce;
+        double vin[3] = { v[0], v[1], v[2] };
+        diffuse_reflect_n(c, R, nrm, w, v);
+        if (oc->surf && oc->step >= c->n_steady) surface_hit(g, oc, nrm, vin, v);
+    }
+}
+
+/* Free transport in a hexahedral mesh: as move_mesh, with the six planar faces of the cell
+ * (outward normal nf, the diagonals' cross product; faces collapsed to a segment are never
+ * left through) and the sphere's tangent frame for wall re-emission. */
+static int32_t move_hex(const hso_gas *g, ocase *oc, int32_t k, double *x, double *v, int64_t id,
+                        double t)
+{
+    const hso_case *c = &oc->p;
+    const hso_mesh *m = c->mesh;
+    double R = KB / g->m;
+    uint32_t st = (uint32_t)oc->step;
+    int bounce = 0, cross = 0;
+    for (;;) {
+        double tmin = t;
+        int fmin = -1;
+        for (int f = 0; f < 6; ++f) {
+            double A[3], nf[3];
+            hex_face(m, k, f, A, nf);
+            double vn = dot3(v, nf);
+            if (!(vn > 0.0)) continue;
+            double d[3] = { A[0] - x[0], A[1] - x[1], A[2] - x[2] };
+            double tf = dot3(d, nf) / vn;
+            if (tf < 0.0) tf = 0.0;
+            if (tf < tmin) { tmin = tf; fmin = f; }
+        }
+        if (fmin < 0) {
+            for (int a = 0; a < 3; ++a) x[a] = x[a] + v[a] * t;
+            return k;
+        }
+        for (int a = 0; a < 3; ++a) x[a] = x[a] + v[a] * tmin;
+        t = t - tmin;
+        int32_t nb = m->nbr[6 * (int64_t)k + fmin];
+        if (nb >= 0) {
+            if (cross == MAX_CROSS) { oc->cnt.bounce_cap++; return k; }
+            ++cross;
+            k = nb;
+            continue;
+        }
+        if (nb == HSO_EDGE_OUTFLOW || nb == HSO_EDGE_INFLOW) return -1;
+        double A[3], nf[3];
+        hex_face(m, k, fmin, A, nf);
+        double ln = sqrt(dot3(nf, nf));
+        double nrm[3] = { -nf[0] / ln, -nf[1] / ln, -nf[2] / ln };     /* into the cell */
+        if (nb == HSO_EDGE_SPECULAR) {
+            if (cross == MAX_CROSS) { oc->cnt.bounce_cap++; return k; }
+            ++cross;
+            double vn = dot3(v, nrm);
+            for (int a = 0; a < 3; ++a) v[a] = v[a] - 2.0 * vn * nrm[a];
             continue;
         }
         oc->cnt.wall_hits++;
@@ -1443,7 +1808,9 @@ static int step_case(const hso_gas *g, ocase *oc, int trace_on)
                 hso_draw(c->seed, ST_PARTICLE, (uint64_t)oc->id[i], (uint32_t)oc->step, DRAW_INJ_TIME, w);
                 t = oc->dt_cur * hso_uniform(w[0]);
             }
-            if (c->mesh)
+            if (c->mesh && c->dim == 3)
+                oc->cell[i] = move_hex(g, oc, oc->cell[i], &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
+            else if (c->mesh)
                 oc->cell[i] = move_mesh(g, oc, oc->cell[i], &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);
             else
                 oc->cell[i] = move_particle(g, oc, &oc->x[3 * i], &oc->v[3 * i], oc->id[i], t);

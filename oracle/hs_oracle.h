@@ -35,16 +35,19 @@ typedef struct {
     double n, u[3], T;
 } hso_state;
 
-/* A body-fitted 2-D mesh of convex quadrilaterals (the paper's unstructured meshes,
- * Sec. 4.2 and 4.4).  Cell k has nodes quad[4k..4k+3] counter-clockwise; edge j runs from
- * node j to node (j+1) mod 4 and nbr[4k+j] is the cell across it, or an HSO_EDGE_* code:
- * OUTFLOW removes particles that cross it, INFLOW also feeds the inflow state's one-way
- * flux through it, WALL reflects diffusely at body_T, SPECULAR mirrors. */
+/* A body-fitted mesh (the paper's unstructured meshes, Sec. 4.2-4.5).  In 2-D, convex
+ * quadrilaterals: cell k has nodes quad[4k..4k+3] counter-clockwise; edge j runs from node j
+ * to node (j+1) mod 4 and nbr[4k+j] is the cell across it.  In 3-D, convex hexahedra with
+ * planar faces: nodes quad[8k..8k+7], 0-3 the bottom face counter-clockwise seen from above,
+ * 4-7 above them; faces (0,3,2,1), (4,5,6,7), (0,1,5,4), (1,2,6,5), (2,3,7,6), (3,0,4,7) and
+ * nbr[6k+f] across face f.  Across a boundary: an HSO_EDGE_* code: OUTFLOW removes particles
+ * that cross it, INFLOW also feeds the inflow state's one-way flux through it, WALL reflects
+ * diffusely at body_T, SPECULAR mirrors. */
 typedef struct {
     int32_t n_nodes, n_cells;
-    const double *xy;                /* 2 per node                                     */
-    const int32_t *quad;             /* 4 per cell                                     */
-    const int32_t *nbr;              /* 4 per cell                                     */
+    const double *xy;                /* 2 (2-D) or 3 (3-D) per node                    */
+    const int32_t *quad;             /* 4 or 8 per cell                                */
+    const int32_t *nbr;              /* 4 or 6 per cell                                */
 } hso_mesh;
 
 /* One flow case on a uniform Cartesian grid (cells x-fastest).  dim = 0 is the
@@ -66,11 +69,11 @@ typedef struct {
     int64_t n_steady, capacity;
     int32_t n_surf;                  /* body surface elements sampled (0: none)        */
     int32_t adapt_dt;                /* 1: Eq. 26 global step, min of Eq. 25 over cells */
-    const hso_mesh *mesh;            /* NULL: the grid above; else an hso_mesh (dim 2): the
-                                        cells are its quads, h[2] the depth; nx, ny, lo,
-                                        h[0..1], bc and the slot are unused; body only
-                                        frames the surface elements (its wall is the WALL
-                                        edges) */
+    const hso_mesh *mesh;            /* NULL: the grid above; else an hso_mesh (dim 2 or 3):
+                                        the cells are its quads (h[2] the depth) or
+                                        hexahedra; nx, ny, nz, lo, the in-plane h, bc and
+                                        the slot are unused; body only frames the surface
+                                        elements (its wall is the WALL edges or faces) */
 } hso_case;
 
 typedef struct hso_sim hso_sim;

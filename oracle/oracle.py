@@ -203,7 +203,8 @@ class _CaseHolder:
             self.mnbr = np.ascontiguousarray(np.array(
                 [EDGE[v] if isinstance(v, str) else int(v) for v in np.asarray(m["nbr"]).reshape(-1)],
                 dtype=np.int32))
-            self.mesh = Mesh(self.mxy.size // 2, self.mquad.size // 4, _dp(self.mxy),
+            dn, vn = (3, 8) if int(d["dim"]) == 3 else (2, 4)      # coordinates, nodes per cell
+            self.mesh = Mesh(self.mxy.size // dn, self.mquad.size // vn, _dp(self.mxy),
                              self.mquad.ctypes.data_as(C.POINTER(C.c_int32)),
                              self.mnbr.ctypes.data_as(C.POINTER(C.c_int32)))
             c.mesh = C.pointer(self.mesh)

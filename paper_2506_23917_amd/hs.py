@@ -180,7 +180,8 @@ class _Cases:
                 nbr = np.ascontiguousarray(np.array(
                     [EDGE[v] if isinstance(v, str) else int(v) for v in np.asarray(m["nbr"]).reshape(-1)],
                     np.int32))
-                hm = HsMesh(xy.size // 2, quad.size // 4, xy.ctypes.data_as(C.POINTER(C.c_double)),
+                dn, vn = (3, 8) if int(d["dim"]) == 3 else (2, 4)   # coordinates, nodes per cell
+                hm = HsMesh(xy.size // dn, quad.size // vn, xy.ctypes.data_as(C.POINTER(C.c_double)),
                             quad.ctypes.data_as(C.POINTER(C.c_int32)), nbr.ctypes.data_as(C.POINTER(C.c_int32)))
                 self.keep += [xy, quad, nbr, hm]
                 c.mesh = C.pointer(hm)

@@ -332,3 +332,119 @@ def ogrid_batch(n_cases=12, seed0=300):
     with outer radius 3 R; cases cycle through the three."""
     kinds = [dict(growth=1.1, kn=0.01), dict(growth=1.05, kn=0.01), dict(growth=1.1, kn=0.1)]
     return [cylinder_ogrid(seed=seed0 + i, **kinds[i % 3]) for i in range(n_cases)]
+
+
+def hex_box_mesh(nx, ny, nz, lo=(0.0, 0.0, 0.0), h=(1.0, 1.0, 1.0), sides=("outflow",) * 6, jitter=0.0,
+                 jitter_seed=5):
+    """Structured hexahedra of the box lo + [0, nx h0] x [0, ny h1] x [0, nz h2], cells
+    x-fastest like the grid's; sides = codes of the -x, +x, -y, +y, -z, +z boundaries.  Nodes
+    0-3 of a cell are its bottom (-z) face counter-clockwise seen from above, 4-7 the top.
+    jitter > 0 shifts interior node planes (whole i, j or k planes by up to jitter * h, so
+    every face stays planar)."""
+    assert 0.0 <= jitter < 0.25
+    rng = np.random.default_rng(jitter_seed)
+    coords = []
+    for n, l0, hh in ((nx, lo[0], h[0]), (ny, lo[1], h[1]), (nz, lo[2], h[2])):
+        c = l0 + np.arange(n + 1) * hh
+        if jitter > 0.0:
+            c[1:-1] += jitter * hh * rng.uniform(-1.0, 1.0, n - 1)
+        coords.append(c)
+    X, Y, Z = np.meshgrid(coords[0], coords[1], coords[2], indexing="ij")
+    node = lambda i, j, k: i + (nx + 1) * (j + (ny + 1) * k)
+    xy = np.zeros(((nx + 1) * (ny + 1) * (nz + 1), 3))
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    xy[node(ii, jj, kk).reshape(-1)] = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci, cj, ck = (a.transpose(2, 1, 0).reshape(-1) for a in (ci, cj, ck))      # x-fastest
+    quad = np.stack([node(ci, cj, ck), node(ci + 1, cj, ck), node(ci + 1, cj + 1, ck), node(ci, cj + 1, ck),
+                     node(ci, cj, ck + 1), node(ci + 1, cj, ck + 1), node(ci + 1, cj + 1, ck + 1),
+                     node(ci, cj + 1, ck + 1)], axis=1)
+    cell = lambda i, j, k: i + nx * (j + ny * k)
+    # faces: bottom (-z), top (+z), -y, +x, +y, -x
+    nbr = np.stack([np.where(ck > 0, cell(ci, cj, ck - 1), -15),
+                    np.where(ck < nz - 1, cell(ci, cj, ck + 1), -16),
+                    np.where(cj > 0, cell(ci, cj - 1, ck), -13),
+                    np.where(ci < nx - 1, cell(ci + 1, cj, ck), -12),
+                    np.where(cj < ny - 1, cell(ci, cj + 1, ck), -14),
+                    np.where(ci > 0, cell(ci - 1, cj, ck), -11)], axis=1)
+    codes = {-11: sides[0], -12: sides[1], -13: sides[2], -14: sides[3], -15: sides[4], -16: sides[5]}
+    return dict(xy=xy, quad=quad.astype(np.int32), nbr=_edge_codes(nbr, codes))
+
+
+def mesh_twin_3d(case, jitter=0.0):
+    """The 3-D grid case `case` (no body) as a hexahedral mesh of the same cells."""
+    assert case["dim"] == 3 and case["body"] == "none"
+    m = hex_box_mesh(case["nx"], case["ny"], case["nz"], lo=case["lo"], h=case["h"], sides=tuple(case["bc"]),
+                     jitter=jitter)
+    out = dict(case)
+    out["mesh"] = m
+    return out
+
+
+def sphere_shell_mesh(R=1.0, r_out=3.0, n_r=20, growth=1.1, n_theta=18, n_phi=36, inner="wall",
+                      outer="inflow", axis="pole_z"):
+    """Hexahedra between spheres of radius R and r_out: radii growing by `growth` from the
+    wall, n_theta bands of polar angle from the +z axis and n_phi of azimuth.  The faces of
+    such cells are planar (equal-radius chords at two latitudes are parallel).  Cells touching
+    a pole collapse one face to a segment; that face is marked specular and is never crossed.
+    Cells: azimuth fastest, then polar band, then radius."""
+    q = growth ** np.arange(n_r)
+    r = R + (r_out - R) * np.concatenate([[0.0], np.cumsum(q) / q.sum()])
+    th = np.pi * np.arange(n_theta + 1) / n_theta
+    ph = 2.0 * np.pi * np.arange(n_phi) / n_phi
+    # nodes: one per (r, theta, phi), the poles shared
+    ids = {}
+    xyz = []
+    def nid(kr, kt, kp):
+        key = (kr, kt, 0 if kt in (0, n_theta) else kp % n_phi)
+        if key not in ids:
+            ids[key] = len(xyz)
+            rr, t, p = r[kr], th[kt], ph[key[2]]
+            xyz.append((rr * np.sin(t) * np.cos(p), rr * np.sin(t) * np.sin(p), rr * np.cos(t)))
+        return ids[key]
+    quad, cells = [], {}
+    for kr in range(n_r):
+        for kt in range(n_theta):
+            for kp in range(n_phi):
+                cells[(kr, kt, kp)] = len(quad)
+                # bottom face = inner radius, counter-clockwise seen from outside the sphere
+                # (from larger r): (t, p), (t, p+1), (t+1, p+1), (t+1, p) ... oriented below
+                a = [nid(kr, kt, kp), nid(kr, kt + 1, kp), nid(kr, kt + 1, kp + 1), nid(kr, kt, kp + 1)]
+                b = [nid(kr + 1, kt, kp), nid(kr + 1, kt + 1, kp), nid(kr + 1, kt + 1, kp + 1), nid(kr + 1, kt, kp + 1)]
+                quad.append(a + b)
+    # neighbours per face from shared node sets
+    face_nodes = [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]
+    owner = {}
+    nbr = np.zeros((len(quad), 6), dtype=object)
+    for c, nodes in enumerate(quad):
+        for f, fn in enumerate(face_nodes):
+            key = frozenset(nodes[j] for j in fn)
+            if len(key) < 3:
+                nbr[c, f] = "specular"          # collapsed at a pole
+                continue
+            if key in owner:
+                c2, f2 = owner.pop(key)
+                nbr[c, f] = c2
+                nbr[c2, f2] = c
+            else:
+                owner[key] = (c, f)
+    for (c, f) in owner.values():
+        kr = c // (n_theta * n_phi)
+        nbr[c, f] = inner if (f == 0 and kr == 0) else outer
+    return dict(xy=np.array(xyz), quad=np.array(quad, dtype=np.int32), nbr=nbr, radii=r)
+
+
+def free_molecular_sphere_mesh(s=1.0, T=300.0, T_w=500.0, n=1.0e13, R=0.35, r_out=1.0, n_r=8, n_theta=12,
+                               n_phi=24, total=20000, n_surf=4, seed=13):
+    """free_molecular_body's sphere on a body-fitted hexahedral shell (planar faces; poles on
+    the z axis, the stream along +x): every outer face a freestream face, every step sampled."""
+    m = sphere_shell_mesh(R=R, r_out=r_out, n_r=n_r, n_theta=n_theta, n_phi=n_phi)
+    U = s * math.sqrt(2.0 * R_ARGON * T)
+    st = dict(n=n, u=(U, 0.0, 0.0), T=T)
+    fn = n * 4.0 / 3.0 * math.pi * (r_out ** 3 - R ** 3) / total
+    dr = m["radii"][1] - m["radii"][0]
+    big = r_out + 1.0
+    return _case(dim=3, h=(1.0, 1.0, 1.0), inflow=st, body="sphere", body_r=R, body_T=T_w,
+                 regions=[((-big, -big, -big, big, big, big), st)], F_N=fn,
+                 dt_G=0.5 * dr / (U + 3.0 * math.sqrt(R_ARGON * T)), T_sigma=T, seed=seed, n_steady=0,
+                 capacity=int(2 * total) + 4096, n_surf=n_surf, mesh=m)
