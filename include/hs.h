@@ -91,14 +91,20 @@ typedef struct {
     double n, u[3], T;
 } hs_state;
 
-/* A body-fitted 2-D mesh of convex quadrilaterals, the paper's unstructured meshes of
- * Sec. 4.2 (the cylinder's O-grid) and Sec. 4.3 (the jet's quads), tracked face to face.
- *  xy: 2 doubles per node (m).  quad: 4 node ids per cell, counter-clockwise.
- *  nbr: 4 per cell; entry j is what lies across edge j (node j -> node (j+1) mod 4): the
- *    neighbour cell, which must name this cell back across the same two nodes, or an
- *    hs_edge code: OUTFLOW removes particles that cross it; INFLOW removes them and feeds
- *    the case's inflow state's one-way flux through the edge; WALL re-emits them diffusely
- *    at body_T about the edge's normal; SPECULAR mirrors them.
+/* A body-fitted mesh, the paper's unstructured meshes (Sec. 4.2 the cylinder's O-grid,
+ * Sec. 4.3 the jet's quads, Sec. 4.4 the sphere's hexahedra), tracked face to face.
+ *  2-D (case dim 2), convex quadrilaterals: xy has 2 doubles per node (m); quad 4 node ids
+ *    per cell, counter-clockwise; nbr 4 per cell, entry j across edge j (node j -> node
+ *    (j+1) mod 4).
+ *  3-D (case dim 3), convex hexahedra with planar faces (a face may collapse to a triangle
+ *    or, never crossed, to a segment): xy has 3 doubles per node; quad 8 node ids per cell,
+ *    0-3 the bottom face counter-clockwise seen from above and 4-7 above them; nbr 6 per
+ *    cell, entry f across face f with nodes (0,3,2,1), (4,5,6,7), (0,1,5,4), (1,2,6,5),
+ *    (2,3,7,6), (3,0,4,7).
+ *  Across an edge or face: the neighbour cell, which must name this cell back across the
+ *    same nodes, or an hs_edge code: OUTFLOW removes particles that cross it; INFLOW removes
+ *    them and feeds the case's inflow state's one-way flux through it; WALL re-emits them
+ *    diffusely at body_T about its normal; SPECULAR mirrors them.
  * Arrays are host memory, read and copied at init (the caller keeps ownership). */
 typedef struct {
     int32_t n_nodes, n_cells;
@@ -132,12 +138,13 @@ typedef struct {
  *    local step from step s's Step (3) moments, the first step uses dt_G, a step without
  *    active cells keeps the last value, and inflow counts scale with the step (dim >= 1;
  *    see hs_step_dt).
- *  mesh: NULL for the grid; else dim must be 2 and the cells are the mesh's quads, numbered
- *    as in the mesh, with volume = area x h[2] (h[2] the depth) and Eq. 25's L_cell = area /
- *    longest edge; nx, ny, nz, lo, h[0..1], bc and the slot are ignored; regions select
- *    cells by the mean of their four nodes; body may be NONE or CYLINDER and only frames
- *    the surface elements (polar-angle bands about the WALL edges' normals; body_r sets the
- *    element areas and A_ref), the wall itself being the WALL edges at body_T. */
+ *  mesh: NULL for the grid; else the cells are the mesh's quads (dim 2; volume = area x h[2],
+ *    h[2] the depth; Eq. 25's L_cell = area / longest edge) or hexahedra (dim 3; L_cell =
+ *    volume / largest face area), numbered as in the mesh; nx, ny, nz, lo, the in-plane h,
+ *    bc and the slot are ignored; regions select cells by the mean of their nodes; body may
+ *    be NONE or CYLINDER (2-D) / SPHERE (3-D) and only frames the surface elements
+ *    (polar-angle bands about the WALL edges' or faces' normals; body_r sets the element
+ *    areas and A_ref), the wall itself being the WALL edges or faces at body_T. */
 typedef struct {
     int32_t dim, nx, ny, nz;
     double lo[3], h[3];
@@ -208,8 +215,8 @@ hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, doubl
 /* Checkpoint of one case (native precision, bit-exact resume).  Layout: hs_state_header
  * (version 2; only that version is accepted),
  * then pos[3][np], vel[3][np] (element size 8 for HS_FP64, 4 for HS_FP32_MIXED; pos is
- * the cell-relative position in [0,1) per axis; on a mesh, x and y relative to the cell's
- * first node, in m), cell[np] (int32, case-local),
+ * the cell-relative position in [0,1) per axis; on a mesh, the position relative to the
+ * cell's first node, in m), cell[np] (int32, case-local),
  * id[np] (int64), sigc_max[ncells], acc[ncells][13] (double).  Particles are sorted by
  * cell.  hs_state_bytes gives the size.  Importing requires cells non-decreasing; it sets
  * the sim's step counter (shared by all cases). */

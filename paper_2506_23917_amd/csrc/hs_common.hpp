@@ -136,6 +136,10 @@ struct Ctx {
     const double *mxy;
     const int32_t *mquad, *mnbr;
     const double *mgeo;
+    // hexahedral meshes (nullptr without one): node coordinates (3 per node), per global cell
+    // its 8 global node ids and 8 neighbour words (faces 0-5, then 2 unused)
+    const double *hxyz;
+    const int32_t *hnode, *hnbr;
     Globals *g;
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
     int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension

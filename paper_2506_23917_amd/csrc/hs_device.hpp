@@ -232,7 +232,7 @@ __device__ inline void diffuse_reflect_n(const GasDev &gas, const CaseDev &cs, c
                                          double V[3])
 {
     double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
-    if (cs.mesh || cs.body == HS_BODY_CYLINDER) {
+    if ((cs.mesh && cs.dim == 2) || cs.body == HS_BODY_CYLINDER) {
         t1[0] = -nr[1];
         t1[1] = nr[0];
         t2[2] = 1.0;
@@ -586,6 +586,106 @@ __device__ inline int move_mesh(const Ctx &C, const CaseDev &cs, int g, P xr[3],
     }
     xr[0] = (P)(X[0] - Pn[0][0]);
     xr[1] = (P)(X[1] - Pn[0][1]);
+    for (int a = 0; a < 3; ++a) v[a] = (P)V[a];
+    return g;
+}
+
+// Hexahedra: nodes 0-3 the bottom face counter-clockwise seen from above, 4-7 above them;
+// face f has the nodes kHexFace[f], counter-clockwise seen from outside.
+__constant__ const int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4},
+                                         {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+
+// The eight nodes of global hexahedron g.
+__device__ __forceinline__ void hex_nodes(const Ctx &C, int g, double P[8][3])
+{
+    const int4 q0 = ((const int4 *)C.hnode)[2 * (size_t)g], q1 = ((const int4 *)C.hnode)[2 * (size_t)g + 1];
+    const int id[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) P[j][a] = C.hxyz[3 * (size_t)id[j] + a];
+}
+
+// Face f: its first node A and nf = (P2 - P0) x (P3 - P1), the outward normal times twice the
+// area of a planar face (0 for a face collapsed to a segment).
+__device__ __forceinline__ void hex_face(const double P[8][3], int f, const double *&A, double nf[3])
+{
+    const double *P0 = P[kHexFace[f][0]], *P1 = P[kHexFace[f][1]], *P2 = P[kHexFace[f][2]], *P3 = P[kHexFace[f][3]];
+    A = P0;
+    const double d1[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+    const double d2[3] = {P3[0] - P1[0], P3[1] - P1[1], P3[2] - P1[2]};
+    nf[0] = d1[1] * d2[2] - d1[2] * d2[1];
+    nf[1] = d1[2] * d2[0] - d1[0] * d2[2];
+    nf[2] = d1[0] * d2[1] - d1[1] * d2[0];
+}
+
+__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Face-to-face tracking through hexahedra with planar faces: as move_mesh, over the six faces
+// (a face collapsed to a segment is never left through), the sphere's tangent frame for wall
+// re-emission.  Position stored relative to the cell's node 0.  Returns the new global cell
+// or -1.
+template <typename P>
+__device__ inline int move_hex(const Ctx &C, const CaseDev &cs, int g, P xr[3], P v[3], int64_t &id,
+                               const int64_t *idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
+{
+    double Pn[8][3];
+    hex_nodes(C, g, Pn);
+    double X[3] = {Pn[0][0] + (double)xr[0], Pn[0][1] + (double)xr[1], Pn[0][2] + (double)xr[2]};
+    double V[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    int bounce = 0, cross = 0;
+    for (;;) {
+        double tmin = t;
+        int fmin = -1;
+        for (int f = 0; f < 6; ++f) {
+            const double *A;
+            double nf[3];
+            hex_face(Pn, f, A, nf);
+            const double vn = dot3(V, nf);
+            if (!(vn > 0.0)) continue;
+            const double d[3] = {A[0] - X[0], A[1] - X[1], A[2] - X[2]};
+            double tf = dot3(d, nf) / vn;
+            if (tf < 0.0) tf = 0.0;
+            if (tf < tmin) { tmin = tf; fmin = f; }
+        }
+        if (fmin < 0) {
+            for (int a = 0; a < 3; ++a) X[a] = X[a] + V[a] * t;
+            break;
+        }
+        for (int a = 0; a < 3; ++a) X[a] = X[a] + V[a] * tmin;
+        t = t - tmin;
+        const int nb = C.hnbr[8 * (size_t)g + fmin];
+        if (nb >= 0) {
+            if (cross == kMaxCross) { ms.capped++; break; }
+            ++cross;
+            g = nb;
+            hex_nodes(C, g, Pn);
+            continue;
+        }
+        if (nb == HS_EDGE_OUTFLOW || nb == HS_EDGE_INFLOW) return -1;
+        const double *A;
+        double nf[3];
+        hex_face(Pn, fmin, A, nf);
+        const double ln = sqrt(dot3(nf, nf));
+        const double nr[3] = {-nf[0] / ln, -nf[1] / ln, -nf[2] / ln};
+        if (nb == HS_EDGE_SPECULAR) {
+            if (cross == kMaxCross) { ms.capped++; break; }
+            ++cross;
+            const double vn = dot3(V, nr);
+            for (int a = 0; a < 3; ++a) V[a] = V[a] - 2.0 * vn * nr[a];
+            continue;
+        }
+        ms.hits++;
+        if (bounce == kMaxBounce) { ms.capped++; break; }
+        if (id < 0) id = *idsrc;
+        const W4 w = draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + bounce);
+        ++bounce;
+        const double Vin[3] = {V[0], V[1], V[2]};
+        diffuse_reflect_n(C.gas, cs, nr, w, V);
+        if (surf) surface_hit_n(C.gas, cs, nr, Vin, V, surf);
+    }
+    for (int a = 0; a < 3; ++a) xr[a] = (P)(X[a] - Pn[0][a]);
     for (int a = 0; a < 3; ++a) v[a] = (P)V[a];
     return g;
 }

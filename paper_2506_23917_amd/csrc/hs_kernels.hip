@@ -168,10 +168,29 @@ __device__ inline const StateDev *region_of(const Ctx &C, const CaseDev &cs, con
     return nullptr;
 }
 
+// Region of a hexahedron: the first box holding the mean of its eight nodes.
+__device__ inline const StateDev *region_of_hex(const Ctx &C, const CaseDev &cs, int g)
+{
+    if (cs.nregions <= 0) return nullptr;
+    double P[8][3];
+    hex_nodes(C, g, P);
+    double mc[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) mc[a] = mc[a] + P[j][a];
+    for (int a = 0; a < 3; ++a) mc[a] = 0.125 * mc[a];
+    for (int r = 0; r < cs.nregions; ++r) {
+        const double *b = &C.region_box[6 * (cs.region0 + r)];
+        if (mc[0] >= b[0] && mc[0] < b[3] && mc[1] >= b[1] && mc[1] < b[4] && mc[2] >= b[2] && mc[2] < b[5])
+            return &C.region_state[cs.region0 + r];
+    }
+    return nullptr;
+}
+
 // Region of a mesh cell: the first box holding the mean of its four nodes.
 __device__ inline const StateDev *region_of_mesh(const Ctx &C, const CaseDev &cs, int g)
 {
     if (cs.nregions <= 0) return nullptr;
+    if (cs.dim == 3) return region_of_hex(C, cs, g);
     double P[4][2];
     mesh_nodes(C, g, P);
     double mc[2] = {0.0, 0.0};
@@ -236,7 +255,7 @@ __global__ void k_init_fill(Ctx C)
     const int64_t id0 = (int64_t)s - C.cstart[cs.cell0];
     const double a = sqrt(2.0 * C.gas.R * st->T);
     double Pq[4][2], jmax = 0.0;
-    if (cs.mesh) {
+    if (cs.mesh && cs.dim == 2) {
         mesh_nodes(C, g, Pq);
         for (int cu = 0; cu < 2; ++cu)
             for (int cw = 0; cw < 2; ++cw) {
@@ -247,7 +266,34 @@ __global__ void k_init_fill(Ctx C)
     }
     for (int q = 0; q < N; ++q) {
         double xr[3] = {0.0, 0.0, 0.0};
-        if (cs.mesh) {
+        if (cs.mesh && cs.dim == 3) {
+            // uniform in the hexahedron: uniform in its bounding box, kept when inside every face
+            double Ph[8][3], lo[3], hi[3], xc[3] = {0.0, 0.0, 0.0}, X[3];
+            hex_nodes(C, g, Ph);
+            for (int j = 0; j < 8; ++j)
+                for (int a = 0; a < 3; ++a) {
+                    if (j == 0 || Ph[j][a] < lo[a]) lo[a] = Ph[j][a];
+                    if (j == 0 || Ph[j][a] > hi[a]) hi[a] = Ph[j][a];
+                    xc[a] = xc[a] + Ph[j][a];
+                }
+            bool placed = false;
+            for (int t = 0; t < kMaxPosTry && !placed; ++t) {
+                const W4 w = draw(cs, kStreamInit, (uint64_t)lc, 0, (uint32_t)(1 + 128 * q + t));
+                const uint32_t ww[3] = {w.x, w.y, w.z};
+                for (int a = 0; a < 3; ++a) X[a] = lo[a] + unid(ww[a]) * (hi[a] - lo[a]);
+                placed = true;
+                for (int f = 0; f < 6 && placed; ++f) {
+                    const double *A;
+                    double nf[3];
+                    hex_face(Ph, f, A, nf);
+                    const double d[3] = {A[0] - X[0], A[1] - X[1], A[2] - X[2]};
+                    if (dot3(d, nf) < 0.0) placed = false;
+                }
+            }
+            if (!placed)
+                for (int a = 0; a < 3; ++a) X[a] = 0.125 * xc[a];
+            for (int a = 0; a < 3; ++a) xr[a] = X[a] - Ph[0][a];
+        } else if (cs.mesh) {
             // uniform in the quad: the bilinear map accepted with probability J / J_max
             double X[2];
             bool placed = false;
@@ -556,7 +602,86 @@ __global__ void k_inject_fill(Ctx C)
     const int64_t slot0 = (int64_t)C.g->n_live + C.face_start[f];
     const int64_t id0 = C.g->inj_id_base[fd.case_id] + (C.face_start[f] - C.face_start[cs.face0]);
     long long capped = 0;
-    if (cs.mesh) {
+    if (cs.mesh && cs.dim == 3) {
+        // a hexahedron's face: inward normal n = -nf / |nf|; tangents t1, t2 by Gram-Schmidt
+        // from the two axes other than the one n is most aligned with; points from the face's
+        // bilinear map (origin: the corner of smallest t1 + t2 coordinate, u towards its
+        // neighbour of larger t1 coordinate) accepted with probability J / J_max
+        double Ph[8][3], Pf[4][3];
+        hex_nodes(C, fd.cell, Ph);
+        for (int j = 0; j < 4; ++j)
+            for (int a = 0; a < 3; ++a) Pf[j][a] = Ph[kHexFace[fd.side][j]][a];
+        const double *A;
+        double nfv[3];
+        hex_face(Ph, fd.side, A, nfv);
+        const double ln = sqrt(dot3(nfv, nfv));
+        const double n[3] = {-nfv[0] / ln, -nfv[1] / ln, -nfv[2] / ln};
+        int ax = 0;
+        for (int a = 1; a < 3; ++a) if (fabs(n[a]) > fabs(n[ax])) ax = a;
+        const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+        double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+        t1[a1] = 1.0;
+        t2[a2] = 1.0;
+        const double p1 = n[a1];
+        for (int a = 0; a < 3; ++a) t1[a] = t1[a] - p1 * n[a];
+        const double l1 = sqrt(dot3(t1, t1));
+        for (int a = 0; a < 3; ++a) t1[a] = t1[a] / l1;
+        const double q2 = n[a2], r2 = t1[a2];
+        for (int a = 0; a < 3; ++a) t2[a] = t2[a] - q2 * n[a] - r2 * t1[a];
+        const double l2 = sqrt(dot3(t2, t2));
+        for (int a = 0; a < 3; ++a) t2[a] = t2[a] / l2;
+        int o = 0;
+        for (int j = 1; j < 4; ++j)
+            if (dot3(t1, Pf[j]) + dot3(t2, Pf[j]) < dot3(t1, Pf[o]) + dot3(t2, Pf[o])) o = j;
+        int ju = (o + 1) & 3, jv = (o + 3) & 3;
+        if (dot3(t1, Pf[jv]) > dot3(t1, Pf[ju])) { const int tmp = ju; ju = jv; jv = tmp; }
+        const double *Po = Pf[o], *Pu = Pf[ju], *Pv = Pf[jv], *Pw = Pf[(o + 2) & 3];
+        auto jac = [&](double uu, double vq) {
+            double du[3], dv[3];
+            for (int a = 0; a < 3; ++a) {
+                du[a] = (1.0 - vq) * (Pu[a] - Po[a]) + vq * (Pw[a] - Pv[a]);
+                dv[a] = (1.0 - uu) * (Pv[a] - Po[a]) + uu * (Pw[a] - Pu[a]);
+            }
+            const double cr[3] = {du[1] * dv[2] - du[2] * dv[1], du[2] * dv[0] - du[0] * dv[2],
+                                  du[0] * dv[1] - du[1] * dv[0]};
+            return sqrt(dot3(cr, cr));
+        };
+        double jmax = 0.0;
+        for (int cu = 0; cu < 2; ++cu)
+            for (int cv = 0; cv < 2; ++cv) {
+                const double jc = jac((double)cu, (double)cv);
+                if (jc > jmax) jmax = jc;
+            }
+        const double snm = dot3(cs.in_u, n) * beta;
+        const double ut1 = dot3(cs.in_u, t1), ut2 = dot3(cs.in_u, t2);
+        for (int q = lane; q < cnt; q += 64) {
+            const uint32_t base = (uint32_t)(1 + 128 * q);
+            double u = 0.5, vv = 0.5;
+            for (int r = 0; r < 32; ++r) {
+                const W4 wp = draw(cs, kStreamFace, (uint64_t)fd.local, st, r == 0 ? base : base + 66 + (uint32_t)r);
+                const double uu = unid(wp.x), vq = unid(wp.y);
+                if (unid(wp.z) * jmax < jac(uu, vq)) { u = uu; vv = vq; break; }
+            }
+            double X[3];
+            for (int a = 0; a < 3; ++a)
+                X[a] = (1.0 - u) * (1.0 - vv) * Po[a] + u * (1.0 - vv) * Pu[a] + u * vv * Pw[a] + (1.0 - u) * vv * Pv[a];
+            const W4 wv = draw(cs, kStreamFace, (uint64_t)fd.local, st, base + 1);
+            const double rr = sqrt(-log(unid(wv.y)));
+            double sn2, cs2;
+            sincospi(2.0 * unid(wv.x), &sn2, &cs2);
+            const double v1 = ut1 + ath * cs2 * rr, v2 = ut2 + ath * sn2 * rr;
+            int used;
+            const double z = normal_speed(cs, (uint32_t)fd.local, st, base + 2, snm, used);
+            if (used < 0) ++capped;
+            const size_t i = (size_t)(slot0 + q);
+            for (int a = 0; a < 3; ++a) {
+                S.pos[a][i] = (P)(X[a] - Ph[0][a]);
+                S.vel[a][i] = (P)(n[a] * z / beta + t1[a] * v1 + t2[a] * v2);
+            }
+            S.cell[i] = fd.cell;
+            S.id[i] = id0 + q;
+        }
+    } else if (cs.mesh) {
         // a mesh edge: inward normal n = (-e_y, e_x) / |e|, in-plane tangent t = (-n_y, n_x)
         // or its opposite (t_x + t_y >= 0), points along +t from the end of smaller t.x
         double Pq[4][2];
@@ -782,10 +907,16 @@ __global__ __launch_bounds__(kBlock) void k_move_mesh(Ctx C)
             }
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
                                ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
-            nc = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+            if (cs.dim == 3) {
+                xr[2] = S.pos[2][i];
+                nc = move_hex<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+            } else {
+                nc = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+            }
             if (nc >= 0) {
                 S.pos[0][i] = xr[0];
                 S.pos[1][i] = xr[1];
+                if (cs.dim == 3) S.pos[2][i] = xr[2];
                 for (int a = 0; a < 3; ++a) S.vel[a][i] = v[a];
             }
             C.newcell[i] = nc;
@@ -2723,11 +2854,11 @@ void Launch::move_count(const Ctx &c, void *s, int any_body)
     // their own kernel over the whole particle array
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL(k_move_fast<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (c.mxy) hipLaunchKernelGGL(k_move_mesh<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (c.mxy || c.hxyz) hipLaunchKernelGGL(k_move_mesh<double>, dim3(grid), dim3(kBlock), 0, S_(s), c);
         if (any_body) hipLaunchKernelGGL(k_move_body<double>, dim3(256), dim3(kBlock), 0, S_(s), c);
     } else {
         hipLaunchKernelGGL(k_move_fast<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
-        if (c.mxy) hipLaunchKernelGGL(k_move_mesh<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
+        if (c.mxy || c.hxyz) hipLaunchKernelGGL(k_move_mesh<float>, dim3(grid), dim3(kBlock), 0, S_(s), c);
         if (any_body) hipLaunchKernelGGL(k_move_body<float>, dim3(256), dim3(kBlock), 0, S_(s), c);
     }
 }

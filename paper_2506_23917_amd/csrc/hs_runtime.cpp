@@ -25,7 +25,7 @@ struct Layout {
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
     size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, surf, trace, out;
-    size_t mxy = 0, mquad = 0, mnbr = 0, mgeo = 0;
+    size_t mxy = 0, mquad = 0, mnbr = 0, mgeo = 0, hxyz = 0, hnode = 0, hnbr = 0;
     size_t surf_bytes = 0;
 };
 
@@ -40,6 +40,11 @@ struct Plan {
     // (volume, L_cell)
     std::vector<double> mxy, mgeo;
     std::vector<int32_t> mquad, mnbr;
+    // hexahedral meshes: node coordinates (3 per node), 8 node ids and 8 neighbour words
+    // (faces 0-5, 2 unused) per global cell
+    std::vector<double> hxyz;
+    std::vector<int32_t> hnode, hnbr;
+    bool any_quad = false, any_hex = false;
     int64_t ncells = 0, capacity = 0;
     int dim_max = 0;
     bool any_spatial = false, any_0d = false, any_body = false, any_mesh = false;
@@ -55,10 +60,120 @@ double cross2(const double *a0, const double *a1, const double *b0, const double
 
 // A mesh: node ids in range, convex counter-clockwise quads, neighbours that name the cell
 // back across the same two nodes, boundary codes with what they need.
+constexpr int kHexFaceH[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+
+double dot3h(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Face f of a hexahedron with nodes P: first node and the diagonals' cross product.
+void hex_face_h(const double P[8][3], int f, const double *&A, double nf[3])
+{
+    const double *P0 = P[kHexFaceH[f][0]], *P1 = P[kHexFaceH[f][1]], *P2 = P[kHexFaceH[f][2]], *P3 = P[kHexFaceH[f][3]];
+    A = P0;
+    const double d1[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+    const double d2[3] = {P3[0] - P1[0], P3[1] - P1[1], P3[2] - P1[2]};
+    nf[0] = d1[1] * d2[2] - d1[2] * d2[1];
+    nf[1] = d1[2] * d2[0] - d1[0] * d2[2];
+    nf[2] = d1[0] * d2[1] - d1[1] * d2[0];
+}
+
+void hex_nodes_h(const hs_mesh *m, int64_t k, double P[8][3])
+{
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) P[j][a] = m->xy[3 * (size_t)m->quad[8 * k + j] + a];
+}
+
+// Volume (six pyramids from the mean of the nodes) and the largest face area.
+void hex_geometry_h(const double P[8][3], double &vol, double &amax)
+{
+    double xc[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) xc[a] = xc[a] + P[j][a];
+    for (int a = 0; a < 3; ++a) xc[a] = 0.125 * xc[a];
+    double v = 0.0, am = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        const double *A;
+        double nf[3];
+        hex_face_h(P, f, A, nf);
+        const double d[3] = {A[0] - xc[0], A[1] - xc[1], A[2] - xc[2]};
+        v = v + dot3h(d, nf) / 6.0;
+        const double ar = 0.5 * std::sqrt(dot3h(nf, nf));
+        if (ar > am) am = ar;
+    }
+    vol = v;
+    amax = am;
+}
+
+// A hexahedral mesh: node ids in range, planar faces, every node on the inner side of every
+// face (tolerance 1e-9 of the cell size), positive volume, neighbours across faces with the
+// same four nodes, boundary codes with what they need.
+bool valid_hex(const hs_case &c, std::string &why)
+{
+    const hs_mesh *m = c.mesh;
+    if (m->n_cells <= 0 || m->n_nodes <= 0 || !m->xy || !m->quad || !m->nbr) { why = "mesh arrays"; return false; }
+    if (c.body == HS_BODY_CYLINDER) { why = "a hexahedral mesh has no cylinder"; return false; }
+    for (int64_t k = 0; k < m->n_cells; ++k) {
+        for (int j = 0; j < 8; ++j)
+            if (m->quad[8 * k + j] < 0 || m->quad[8 * k + j] >= m->n_nodes) { why = "mesh node id out of range"; return false; }
+        double P[8][3], v, am;
+        hex_nodes_h(m, k, P);
+        hex_geometry_h(P, v, am);
+        if (!(v > 0.0)) { why = "hexahedra must have a positive volume"; return false; }
+        const double size = std::cbrt(v);
+        for (int f = 0; f < 6; ++f) {
+            const double *A;
+            double nf[3];
+            hex_face_h(P, f, A, nf);
+            const double ln = std::sqrt(dot3h(nf, nf));
+            if (ln > 0.0) {
+                for (int j = 0; j < 8; ++j) {
+                    const double d[3] = {A[0] - P[j][0], A[1] - P[j][1], A[2] - P[j][2]};
+                    const double sd = dot3h(d, nf) / ln;
+                    bool on_face = false;
+                    for (int i = 0; i < 4; ++i) on_face |= kHexFaceH[f][i] == j;
+                    if (on_face ? std::fabs(sd) > 1e-9 * size : sd < -1e-9 * size) {
+                        why = "hexahedra must be convex with planar faces";
+                        return false;
+                    }
+                }
+            }
+            const int32_t nb = m->nbr[6 * k + f];
+            if (nb >= 0) {
+                if (nb >= m->n_cells) { why = "mesh neighbour out of range"; return false; }
+                bool back = false;
+                for (int i = 0; i < 6 && !back; ++i) {
+                    if (m->nbr[6 * (int64_t)nb + i] != (int32_t)k) continue;
+                    bool same = true;
+                    for (int a = 0; a < 4; ++a) {
+                        bool found = false;
+                        for (int b = 0; b < 4; ++b)
+                            found |= m->quad[8 * (int64_t)nb + kHexFaceH[i][b]] == m->quad[8 * k + kHexFaceH[f][a]];
+                        same &= found;
+                    }
+                    back = same;
+                }
+                if (!back) { why = "mesh neighbours must name each other across the same face"; return false; }
+            } else if (nb == HS_EDGE_WALL) {
+                if (!(c.body_T > 0)) { why = "WALL faces need body_T"; return false; }
+            } else if (nb == HS_EDGE_INFLOW) {
+                if (!(c.inflow.T > 0 && c.inflow.n >= 0)) { why = "inflow state"; return false; }
+            } else if (nb != HS_EDGE_OUTFLOW && nb != HS_EDGE_SPECULAR) {
+                why = "unknown mesh face code";
+                return false;
+            }
+        }
+    }
+    if (c.n_surf > 0 && (c.body != HS_BODY_SPHERE || !(c.body_r > 0))) {
+        why = "hexahedral surface elements need a sphere frame (body_r)";
+        return false;
+    }
+    return true;
+}
+
 bool valid_mesh(const hs_case &c, std::string &why)
 {
     const hs_mesh *m = c.mesh;
-    if (c.dim != 2) { why = "a mesh case needs dim 2"; return false; }
+    if (c.dim == 3) return valid_hex(c, why);
+    if (c.dim != 2) { why = "a mesh case needs dim 2 or 3"; return false; }
     if (m->n_cells <= 0 || m->n_nodes <= 0 || !m->xy || !m->quad || !m->nbr) { why = "mesh arrays"; return false; }
     if (c.body == HS_BODY_SPHERE) { why = "a mesh case has no sphere"; return false; }
     for (int64_t k = 0; k < m->n_cells; ++k) {
@@ -183,6 +298,15 @@ double face_flux(const hs_gas *g, const hs_state &st, int a, double sg)
     return st.n * (std::exp(-s * s) + std::sqrt(kPi_h) * s * (1.0 + std::erf(s))) / (2.0 * beta * std::sqrt(kPi_h));
 }
 
+// One-way number flux of the inflow state through a face with 3-D inward unit normal nrm.
+double edge_flux3(const hs_gas *g, const hs_state &st, const double nrm[3])
+{
+    const double R = kKB_h / g->m;
+    const double beta = 1.0 / std::sqrt(2.0 * R * st.T);
+    const double s = beta * (st.u[0] * nrm[0] + st.u[1] * nrm[1] + st.u[2] * nrm[2]);
+    return st.n * (std::exp(-s * s) + std::sqrt(kPi_h) * s * (1.0 + std::erf(s))) / (2.0 * beta * std::sqrt(kPi_h));
+}
+
 // One-way number flux of the inflow state through a face with inward unit normal nrm.
 double edge_flux(const hs_gas *g, const hs_state &st, const double nrm[2])
 {
@@ -206,6 +330,8 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
     int64_t cell0 = 0;
     for (int i = 0; i < n; ++i) if (cs[i].dim == 0) P.any_0d = true;
     for (int i = 0; i < n; ++i) if (cs[i].mesh) P.any_mesh = true;
+    for (int i = 0; i < n; ++i) if (cs[i].mesh && cs[i].dim == 2) P.any_quad = true;
+    for (int i = 0; i < n; ++i) if (cs[i].mesh && cs[i].dim == 3) P.any_hex = true;
     for (int i = 0; i < n; ++i) {
         const hs_case &c = cs[i];
         CaseDev d;
@@ -214,7 +340,7 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         d.mesh = c.mesh ? 1 : 0;
         d.n[0] = c.mesh ? c.mesh->n_cells : c.nx;
         d.n[1] = c.dim >= 2 && !c.mesh ? c.ny : 1;
-        d.n[2] = c.dim >= 3 ? c.nz : 1;
+        d.n[2] = c.dim >= 3 && !c.mesh ? c.nz : 1;
         const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
         d.cell0 = (int32_t)cell0;
         d.ncells = (int32_t)nc;
@@ -276,12 +402,49 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
         // inflow faces: sides -x,+x,-y,+y,-z,+z; boundary cells x-fastest; slot filter
         // (a mesh: its INFLOW edges, in cell and edge order)
         d.face0 = (int32_t)P.faces.size();
-        if (P.any_mesh) {
+        if (P.any_mesh) P.mgeo.resize(2 * (size_t)(cell0 + nc), 0.0);
+        if (P.any_hex) {
+            const int32_t hnode0 = (int32_t)(P.hxyz.size() / 3);
+            P.hnode.resize(8 * (size_t)(cell0 + nc), 0);
+            P.hnbr.resize(8 * (size_t)(cell0 + nc), HS_EDGE_OUTFLOW);
+            if (c.mesh && c.dim == 3) {
+                const hs_mesh *m = c.mesh;
+                P.hxyz.insert(P.hxyz.end(), m->xy, m->xy + 3 * (size_t)m->n_nodes);
+                for (int64_t k = 0; k < nc; ++k) {
+                    for (int j = 0; j < 8; ++j) P.hnode[8 * (cell0 + k) + j] = hnode0 + m->quad[8 * k + j];
+                    for (int f = 0; f < 6; ++f) {
+                        const int32_t nb = m->nbr[6 * k + f];
+                        P.hnbr[8 * (cell0 + k) + f] = nb >= 0 ? (int32_t)(cell0 + nb) : nb;
+                    }
+                    double Ph[8][3], v, am;
+                    hex_nodes_h(m, k, Ph);
+                    hex_geometry_h(Ph, v, am);
+                    P.mgeo[2 * (cell0 + k)] = v;
+                    P.mgeo[2 * (cell0 + k) + 1] = v / am;      // volume over the largest face
+                    for (int f = 0; f < 6; ++f) {
+                        if (m->nbr[6 * k + f] != HS_EDGE_INFLOW) continue;
+                        const double *A;
+                        double nf[3];
+                        hex_face_h(Ph, f, A, nf);
+                        const double ln = std::sqrt(dot3h(nf, nf));
+                        if (!(ln > 0.0)) continue;
+                        const double nrm[3] = {-nf[0] / ln, -nf[1] / ln, -nf[2] / ln};
+                        FaceDev fc;
+                        fc.cell = (int32_t)(cell0 + k);
+                        fc.side = f;
+                        fc.case_id = i;
+                        fc.local = (int32_t)(P.faces.size() - d.face0);
+                        fc.lambda = edge_flux3(g, c.inflow, nrm) * (0.5 * ln) * c.dt_G / c.F_N;
+                        P.faces.push_back(fc);
+                    }
+                }
+            }
+        }
+        if (P.any_quad) {
             const int32_t node0 = (int32_t)(P.mxy.size() / 2);
-            P.mgeo.resize(2 * (size_t)(cell0 + nc), 0.0);
             P.mquad.resize(4 * (size_t)(cell0 + nc), 0);
             P.mnbr.resize(4 * (size_t)(cell0 + nc), HS_EDGE_OUTFLOW);
-            if (c.mesh) {
+            if (c.mesh && c.dim == 2) {
                 const hs_mesh *m = c.mesh;
                 P.mxy.insert(P.mxy.end(), m->xy, m->xy + 2 * (size_t)m->n_nodes);
                 for (int64_t k = 0; k < nc; ++k) {
@@ -401,11 +564,16 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.surf_bytes = 8 * 7 * (size_t)kSurfCopies * std::max<size_t>(nsurf, 1);
     L.surf = take(L.surf_bytes);
     L.trace = (flags & HS_FLAG_TRACE) ? take(sizeof(TraceDev) * nc) : 0;
-    if (P.any_mesh) {
+    if (P.any_mesh) L.mgeo = take(sizeof(double) * 2 * nc);
+    if (P.any_quad) {
         L.mxy = take(sizeof(double) * std::max<size_t>(P.mxy.size(), 2));
         L.mquad = take(sizeof(int32_t) * 4 * nc);
         L.mnbr = take(sizeof(int32_t) * 4 * nc);
-        L.mgeo = take(sizeof(double) * 2 * nc);
+    }
+    if (P.any_hex) {
+        L.hxyz = take(sizeof(double) * std::max<size_t>(P.hxyz.size(), 3));
+        L.hnode = take(sizeof(int32_t) * 8 * nc);
+        L.hnbr = take(sizeof(int32_t) * 8 * nc);
     }
     size_t maxcase = 1;
     for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
@@ -621,11 +789,16 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
         c.n_surf_total = (int32_t)ns;
     }
     c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
-    if (s->plan.any_mesh) {
+    if (s->plan.any_mesh) c.mgeo = (const double *)(w + L.mgeo);
+    if (s->plan.any_quad) {
         c.mxy = (const double *)(w + L.mxy);
         c.mquad = (const int32_t *)(w + L.mquad);
         c.mnbr = (const int32_t *)(w + L.mnbr);
-        c.mgeo = (const double *)(w + L.mgeo);
+    }
+    if (s->plan.any_hex) {
+        c.hxyz = (const double *)(w + L.hxyz);
+        c.hnode = (const int32_t *)(w + L.hnode);
+        c.hnbr = (const int32_t *)(w + L.hnbr);
     }
     c.tile_w = tile_width();
     c.dim_max = s->plan.dim_max;
@@ -649,11 +822,16 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     e = e ? e : up(L.rbox, s->plan.rbox.data(), sizeof(double) * s->plan.rbox.size());
     e = e ? e : up(L.rstate, s->plan.rstate.data(), sizeof(StateDev) * s->plan.rstate.size());
     if (s->plan.any_0d) e = e ? e : up(L.dtcell, s->plan.dtcell.data(), sizeof(double) * s->plan.dtcell.size());
-    if (s->plan.any_mesh) {
+    if (s->plan.any_mesh) e = e ? e : up(L.mgeo, s->plan.mgeo.data(), sizeof(double) * s->plan.mgeo.size());
+    if (s->plan.any_quad) {
         e = e ? e : up(L.mxy, s->plan.mxy.data(), sizeof(double) * s->plan.mxy.size());
         e = e ? e : up(L.mquad, s->plan.mquad.data(), sizeof(int32_t) * s->plan.mquad.size());
         e = e ? e : up(L.mnbr, s->plan.mnbr.data(), sizeof(int32_t) * s->plan.mnbr.size());
-        e = e ? e : up(L.mgeo, s->plan.mgeo.data(), sizeof(double) * s->plan.mgeo.size());
+    }
+    if (s->plan.any_hex) {
+        e = e ? e : up(L.hxyz, s->plan.hxyz.data(), sizeof(double) * s->plan.hxyz.size());
+        e = e ? e : up(L.hnode, s->plan.hnode.data(), sizeof(int32_t) * s->plan.hnode.size());
+        e = e ? e : up(L.hnbr, s->plan.hnbr.data(), sizeof(int32_t) * s->plan.hnbr.size());
     }
     e = e ? e : hipMemsetAsync(w + L.globals, 0, sizeof(Globals), s->stream);
     e = e ? e : hipMemsetAsync(w + L.surf, 0, L.surf_bytes, s->stream);

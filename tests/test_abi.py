@@ -97,3 +97,37 @@ def test_plan_validates_meshes_on_host():
             c["n_surf"] = 4                                 # surface elements need a cylinder frame
         c["mesh"] = m
         assert rejected(c), what
+
+
+def test_plan_validates_hexahedra_on_host():
+    """hs_plan accepts the sphere's hexahedral shell and rejects broken hexahedra (no GPU)."""
+    import numpy as np
+    from paper_2506_23917_amd import hs
+    import workloads as W
+    g = W.gas()
+    sh = W.sphere_hex(n_phi=16, n_theta=8, n_r=6, r_out=2.0, ppc_outer=40)
+    assert hs.plan_bytes(g, sh, hs.FP32_MIXED) > sh["capacity"] * 36
+    st = dict(n=1e20, u=(800.0, 0.0, 0.0), T=300.0)
+    box = W._case(dim=3, nx=4, ny=3, nz=3, h=(0.05, 0.05, 0.05), bc=("inflow",) + ("outflow",) * 5, inflow=st,
+                  regions=[((0, 0, 0, 0.2, 0.15, 0.15), st)], F_N=1e16, dt_G=1e-5, capacity=1000)
+    twin = W.mesh_twin_3d(box)
+    hs.plan_bytes(g, [twin, dict(W.mesh_twin(W._case(dim=2, nx=3, ny=2, h=(0.1, 0.1, 1.0), regions=[((0, 0, 0, 1, 1, 1), st)],
+                                                     F_N=1e16, dt_G=1e-5, capacity=100)), seed=5)])
+    for what in ("nonplanar", "inverted", "nbr", "cylinder"):
+        c = dict(twin)
+        m = {k: np.array(v, copy=True) for k, v in twin["mesh"].items()}
+        if what == "nonplanar":
+            m["xy"][m["quad"][5][6]] += np.array([0.0, 0.0, 0.01])
+        elif what == "inverted":
+            m["quad"][3] = m["quad"][3][[4, 5, 6, 7, 0, 1, 2, 3]]
+        elif what == "nbr":
+            m["nbr"][0, 3] = 7
+        else:
+            c["body"] = "cylinder"
+        c["mesh"] = m
+        try:
+            hs.plan_bytes(g, c)
+        except hs.HsError as e:
+            assert e.code == 1, what
+        else:
+            raise AssertionError("expected an argument error: " + what)

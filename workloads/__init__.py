@@ -448,3 +448,32 @@ def free_molecular_sphere_mesh(s=1.0, T=300.0, T_w=500.0, n=1.0e13, R=0.35, r_ou
                  regions=[((-big, -big, -big, big, big, big), st)], F_N=fn,
                  dt_G=0.5 * dr / (U + 3.0 * math.sqrt(R_ARGON * T)), T_sigma=T, seed=seed, n_steady=0,
                  capacity=int(2 * total) + 4096, n_surf=n_surf, mesh=m)
+
+
+# Ma 10 argon sphere of Sec. 4.4: R = 1 m, rho = 5.5e-6 kg/m^3 (n = rho / m), T = 65 K,
+# U = 1501.11 m/s, wall at 302 K.
+SPH10_N = 5.5e-6 / 6.63e-26
+SPH10_T = 65.0
+SPH10_U = 1501.11
+SPH10_A = 150.12329153025936               # sqrt(gamma R T) at 65 K
+
+
+def sphere_hex(n_phi=72, n_theta=36, n_r=76, r_out=4.0, growth=1.05, ppc_outer=400, seed=1,
+               n_steady=1 << 40, cap_factor=1.5, n_surf=36):
+    """The Sec. 4.4 sphere on a body-fitted hexahedral shell: n_phi x n_theta x n_r cells
+    (72 x 36 x 76 = 196,992, the paper's count is 197,248), radii from R = 1 m growing by
+    `growth` to r_out; the pole axis is z, the stream along +x; diffuse wall at 302 K;
+    F_N puts ppc_outer particles in an outermost equatorial cell; dt_G = first layer /
+    (U + a)."""
+    m = sphere_shell_mesh(R=1.0, r_out=r_out, n_r=n_r, growth=growth, n_theta=n_theta, n_phi=n_phi)
+    r = m["radii"]
+    st = dict(n=SPH10_N, u=(SPH10_U, 0.0, 0.0), T=SPH10_T)
+    dth, dph = np.pi / n_theta, 2.0 * np.pi / n_phi
+    outer = (r[-1] ** 3 - r[-2] ** 3) / 3.0 * dph * (np.cos(0.5 * np.pi - 0.5 * dth) - np.cos(0.5 * np.pi + 0.5 * dth))
+    fn = SPH10_N * outer / ppc_outer
+    total = SPH10_N * 4.0 / 3.0 * np.pi * (r[-1] ** 3 - r[0] ** 3) / fn
+    big = r[-1] + 1.0
+    return _case(dim=3, h=(1.0, 1.0, 1.0), inflow=st, body="sphere", body_r=1.0, body_T=302.0,
+                 regions=[((-big, -big, -big, big, big, big), st)], F_N=fn,
+                 dt_G=(r[1] - r[0]) / (SPH10_U + SPH10_A), T_sigma=SPH10_T * (1.0 + 100.0 / 3.0), seed=seed,
+                 n_steady=n_steady, capacity=int(total * cap_factor) + 4096, n_surf=n_surf, mesh=m)
