@@ -20,8 +20,10 @@ go into the line's "accuracy" object (the mixed path's bound is 1e-3).
 
 `--workload ogrid` measures the body-fitted mesh path instead: a batch of twelve O-grid runs of
 the paper's Ma 5 cylinder (first layer 1 mm, growth 1.1 or 1.05, Kn 0.01 or 0.1; ~10.4M
-particles, 149k quads), face-to-face tracking in k_move_mesh.  Its roofline object is for that
-kernel, timed the same way.
+particles, 149k quads), face-to-face tracking in k_move_mesh.  `--workload sphere_hex` the
+Ma 10 sphere of Sec. 4.4 on a 72 x 36 x 76 hexahedral shell (197k cells, ~6M particles).  Their
+roofline object is for the move group (k_move_fast passing the mesh waves + k_move_mesh), timed
+the same way.
 
 Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: the build runs on one GPU.
 """
@@ -52,6 +54,7 @@ STEP_BYTES_PER_PARTICLE = 128
 # position, velocity, new cell and slot written (8 + 12 + 4 + 4).  Node coordinates and
 # neighbours are per cell and stay in cache.
 MESH_MOVE_BYTES_PER_PARTICLE = 24 + 28
+HEX_MOVE_BYTES_PER_PARTICLE = 28 + 32      # the same in 3-D: 4 + 12 + 12 read, 12 + 12 + 4 + 4 written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_valu.txt")
 KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.hpp", "hs_common.hpp"]
@@ -164,29 +167,34 @@ def cpu_baseline(sim, case, gas, nsteps):
 
 
 def main_ogrid(args):
-    """The body-fitted O-grid batch (mesh path): FP32-mixed and FP64 throughput, the mesh
-    move kernel against the HBM roofline."""
+    """A body-fitted mesh workload (the O-grid batch or the hexahedral sphere): FP32-mixed and
+    FP64 throughput, the mesh move kernels against the HBM roofline."""
     import workloads as W
     gas = W.gas()
-    cases = W.ogrid_batch()
+    hexa = args.workload == "sphere_hex"
+    cases = [W.sphere_hex()] if hexa else W.ogrid_batch()
     for c in cases:
         c["n_steady"] = args.warmup
     ncells = sum(len(c["mesh"]["quad"]) for c in cases)
-    log("[bench] ogrid fp32-mixed: warmup %d, timed %d" % (args.warmup, args.steps))
+    log("[bench] %s fp32-mixed: warmup %d, timed %d" % (args.workload, args.warmup, args.steps))
     sim32, r32 = run_gpu("fp32", cases, gas, args.warmup, args.steps, timed_group="move")
     npart = 0.5 * (r32["n0"] + r32["n1"])
     value = npart * args.steps / r32["dt"]
     ms_step = 1e3 * r32["dt"] / args.steps
-    move_bytes = MESH_MOVE_BYTES_PER_PARTICLE * npart
+    move_bytes = (HEX_MOVE_BYTES_PER_PARTICLE if hexa else MESH_MOVE_BYTES_PER_PARTICLE) * npart
     achieved = move_bytes / (r32["tile_ms"] * 1e-3) / 1e9
     out = {
-        "metric": "particle-steps/s, 2-D Ma5 cylinder on body-fitted O-grids",
+        "metric": ("particle-steps/s, 3-D Ma10 sphere on a body-fitted hexahedral shell" if hexa else
+                   "particle-steps/s, 2-D Ma5 cylinder on body-fitted O-grids"),
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32/f64-mixed", "data": "synthetic",
-        "config": {"workload": "12 O-grid runs of the Ma 5 argon cylinder (180 nodes around, first layer "
-                               "1 mm, growth 1.1 / 1.05, outer radius 3 R, Kn 0.01 / 0.1, 500 particles "
-                               "in the outermost cells), FP32-mixed, sampling on",
+        "config": {"workload": ("Ma 10 argon sphere (R = 1 m, 65 K, wall 302 K) on a 72 x 36 x 76 hexahedral "
+                                "shell to 4 R, 400 particles in an outermost equatorial cell, FP32-mixed, "
+                                "sampling on") if hexa else
+                               ("12 O-grid runs of the Ma 5 argon cylinder (180 nodes around, first layer "
+                                "1 mm, growth 1.1 / 1.05, outer radius 3 R, Kn 0.01 / 0.1, 500 particles "
+                                "in the outermost cells), FP32-mixed, sampling on"),
                    "particles": int(npart), "cells": ncells},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -213,13 +221,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps of the CPU baseline sample")
-    ap.add_argument("--workload", choices=("cylinder", "ogrid"), default="cylinder")
+    ap.add_argument("--workload", choices=("cylinder", "ogrid", "sphere_hex"), default="cylinder")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "ogrid":
+    if args.workload in ("ogrid", "sphere_hex"):
         main_ogrid(args)
         return
 
