@@ -150,3 +150,73 @@ def test_hex_fp32_gas_at_rest_stays_uniform(gas):
     n_sh = (m["n"] * vol).reshape(-1, per).sum(axis=1) / vol.reshape(-1, per).sum(axis=1)
     n0 = case["inflow"]["n"]
     assert np.all(np.abs(n_sh[1:] / n0 - 1.0) < 0.03), n_sh / n0
+
+
+def test_hex_adaptive_step_and_batch_with_grid_and_quad_cases(gas):
+    """Eq. 26 with the hexahedra's L_cell, in one batch with a grid case and a quad-mesh case."""
+    shell = hex_cases()["shell"]
+    shell["adapt_dt"] = True
+    grid = W.cylinder_2d(nx=40, ny=30, ppc=8, seed=11, n_surf=6, n_steady=0)
+    og = W.cylinder_ogrid(n_theta=48, first=0.02, growth=1.15, r_out=2.0, ppc_outer=60, seed=12, n_surf=4)
+    cases = [grid, shell, og]
+    sim = _sim(gas, cases, precision="fp64")
+    ora = Oracle(gas, cases)
+    ora.init_particles()
+    for s in range(4):
+        sim.step(1)
+        ora.step(1)
+        _compare(gas, shell, sim.export_state(1), ora.get_state(1), label="hex adaptive step %d" % (s + 1))
+        dg, do = sim.step_dt(1), ora.step_dt(1)
+        assert abs(dg[0] - do[0]) <= 1e-12 * do[0]
+    assert ora.step_dt(1)[0] != shell["dt_G"]
+    for c in (0, 2):
+        g0, o0 = sim.export_state(c), ora.get_state(c)
+        assert np.array_equal(g0["id"], o0["id"]) and np.array_equal(g0["cell"], o0["cell"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hex_time_averages_agree_with_the_oracle(gas, prec):
+    """Small hexahedral sphere shell from the impulsive start, sampled over 300 steps: the
+    GPU's time-averaged n and T per cell against the oracle's pooled estimates, in units of
+    the standard error of a difference (10 batch means of the oracle's run); cells with at
+    least 20 samples in every batch.  z follows Student's t with 9 degrees of freedom."""
+    case = W.sphere_hex(n_phi=16, n_theta=8, n_r=6, r_out=2.0, growth=1.2, ppc_outer=80, seed=23,
+                        n_steady=60, n_surf=0)
+    ora = Oracle(gas, case)
+    ora.init_particles()
+    ora.step(60)
+    batches, prev = [], None
+    for _ in range(10):
+        ora.step(30)
+        acc = ora.get_cells(0)["acc"].copy()
+        batches.append(acc - (prev if prev is not None else 0.0))
+        prev = acc
+    vol = ora.get_cells(0)["vol"]
+    m = gas["m"]
+
+    def n_T(acc, nsamp):
+        N = acc[:, 0]
+        ok = N > 0
+        Ns = np.where(ok, N, 1.0)
+        n = np.where(ok, case["F_N"] * N / (nsamp * vol), 0.0)
+        cc = (acc[:, 4] + acc[:, 5] + acc[:, 6]) / Ns
+        uu = (acc[:, 1] ** 2 + acc[:, 2] ** 2 + acc[:, 3] ** 2) / Ns ** 2
+        return n, np.where(ok, m / (3 * W.K_BOLTZMANN) * (cc - uu), 0.0)
+
+    bn, bT = (np.array(x) for x in zip(*[n_T(a, 30) for a in batches]))
+    on, oT = n_T(prev, 300)
+    se_n = bn.std(0, ddof=1) / np.sqrt(10) * np.sqrt(2)
+    se_T = bT.std(0, ddof=1) / np.sqrt(10) * np.sqrt(2)
+    sim = _sim(gas, case, precision=prec)
+    sim.step(360)
+    g = sim.sample_moments(0, mode=0)
+    assert g["n_samples"] == 300
+    nb_min = np.min([b[:, 0] for b in batches], axis=0)
+    sel = (nb_min >= 20) & (se_n > 0) & (se_T > 0)
+    assert sel.sum() > 0.3 * len(sel)
+    zn = (g["n"][sel] - on[sel]) / se_n[sel]
+    zT = (g["T"][sel] - oT[sel]) / se_T[sel]
+    print(prec, "cells %d mean z^2 n %.3f T %.3f" % (sel.sum(), (zn ** 2).mean(), (zT ** 2).mean()))
+    for z in (zn, zT):
+        assert (z ** 2).mean() < 2.0
+        assert (abs(z) > 4).mean() < 0.02
