@@ -806,8 +806,9 @@ __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> 
     }
 }
 
-// Every particle: straight flight with specular / open walls, new cell and slot recorded.
-// Particles whose path may meet the body go to a worklist for k_move_body.
+// Every particle of the grid cases: straight flight with specular / open walls, new cell and
+// slot recorded.  Particles whose path may meet the body go to a worklist for k_move_body;
+// waves of mesh cases are left to k_move_mesh.
 template <typename P>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_move_fast(Ctx C)
 {
@@ -870,8 +871,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     }
 }
 
-// Every particle of the mesh cases: face-to-face tracking (move_mesh), new cell and slot.
-// Waves of grid cases pass straight through (k_move_fast moves them).
+// Every particle of the mesh cases: face-to-face tracking (move_mesh through quads, move_hex
+// through hexahedra), new cell and slot.  Waves of grid cases pass straight through
+// (k_move_fast moves them).
 template <typename P>
 __global__ __launch_bounds__(kBlock) void k_move_mesh(Ctx C)
 {
