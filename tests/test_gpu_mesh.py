@@ -256,3 +256,31 @@ def test_mesh_time_averages_agree_with_the_oracle(gas, prec):
     for z in (zn, zT):
         assert (z ** 2).mean() < 2.0
         assert (abs(z) > 4).mean() < 0.02
+
+
+def test_ratio_of_dsmc_on_the_paper_o_grid(gas):
+    """Sec. 4.2's statements about the ratio of DSMC on the Ma 5 cylinder O-grid (mesh1): at
+    Kn = 0.1 the hybrid is DSMC throughout, while at Kn = 0.01 the ratio varies across the
+    field and falls well below 1 in the large outer cells.  FP32-mixed, 2,500 steps from the
+    impulsive start, the last 1,000 sampled; cells with a sampled temperature.  The ratio in
+    the first wall cells on the stagnation line is printed, not asserted: on this synthetic
+    mesh those cells sit near Dt_c ~ tau (ratio ~ 0.6 at Kn = 0.01)."""
+    out, rings = {}, {}
+    for kn in (0.1, 0.01):
+        case = W.cylinder_ogrid(kn=kn, ppc_outer=100, n_steady=1500, n_surf=0, seed=31)
+        sim = _sim(gas, case, precision="fp32")
+        sim.step(2500)
+        r = sim.dsmc_ratio(0)
+        m = sim.sample_moments(0, 0)
+        ok = (m["n"] > 0) & (m["T"] > 0)
+        out[kn] = r[ok]
+        rings[kn] = r.reshape(-1, 180)
+        q = np.percentile(out[kn], [1, 5, 10, 25, 50])
+        print("Kn", kn, "cells", ok.sum(), "ratio percentiles 1/5/10/25/50:", np.round(q, 3),
+              "outer ring mean %.3f, first ring at the stagnation line %.3f" % (rings[kn][-1].mean(), rings[kn][0, 88:92].mean()))
+    # Kn = 0.1: DSMC throughout
+    assert np.mean(out[0.1] > 0.999) > 0.98
+    # Kn = 0.01: the ratio varies over the field; the large far-field cells take part
+    # SP-Shakhov steps, the refined cells are DSMC
+    assert np.percentile(out[0.01], 5) < 0.9 and out[0.01].max() > 0.999
+    assert rings[0.01][-1].mean() < 0.95 < rings[0.1][-1].mean()
