@@ -236,7 +236,7 @@ __global__ void k_init_cells(Ctx C, int fill)
 }
 
 template <typename P>
-__global__ void k_init_fill(Ctx C)
+__global__ __launch_bounds__(64) void k_init_fill(Ctx C)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= C.ncells_total) return;
@@ -580,9 +580,11 @@ __global__ void k_inject_scan(Ctx C)
     }
 }
 
-// One wavefront per inflow face; lanes stride over the face's new particles.
+// One wavefront per inflow face; lanes stride over the face's new particles.  The launch
+// bound lets the hexahedral placement keep its nodes in registers (without it the compiler
+// assumes 1024-thread blocks, caps the kernel at 128 VGPRs and spills about 700).
 template <typename P>
-__global__ void k_inject_fill(Ctx C)
+__global__ __launch_bounds__(kBlock) void k_inject_fill(Ctx C)
 {
     const int f = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1197,9 +1199,11 @@ __device__ __forceinline__ void tally_add(const Ctx &C, CaseTally &T, int cid, i
 // Tiles of the collision stage: a 64-thread block takes the cells whose weight
 // w(c) = cell_start[c] + 4 c falls in [t TW, (t+1) TW): at most TW/4 = 64 cells and TW + D
 // particles; cells denser than D go to k_collide_dense.  This kernel restores the stable
-// order of each cell's particles (source order) and writes the sorted state.
+// order of each cell's particles (source order) and writes the sorted state.  Its time is
+// load latency: in FP32 it runs at eight waves per SIMD (64 VGPRs, a few spilled), in FP64
+// at four (eight would spill 32 VGPRs).
 template <typename P, int TW, int D>
-__global__ __launch_bounds__(64) void k_sort_gather(Ctx C)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(P) == 4 ? 8 : 4, 8))) void k_sort_gather(Ctx C)
 {
     constexpr int MAXC = TW / 4;
     constexpr int MAXP = TW + D;

@@ -1373,8 +1373,8 @@ void hs_destroy(hs_sim *s)
     (void)hipStreamSynchronize(s->stream);
     if (s->side) (void)hipStreamSynchronize(s->side);
     destroy_events(s);
-    if (s->gexec) hipGraphExecDestroy(s->gexec);
-    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     if (s->side) (void)hipStreamDestroy(s->side);
