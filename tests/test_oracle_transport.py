@@ -193,17 +193,22 @@ def test_stable_sort_order_and_bijection():
     o.init_particles()
     o.step(3)
     before = o.get_state(0)
+    cnt0 = o.counters()
     pos_before = {int(i): k for k, i in enumerate(before["id"])}
     o.step(1)
     after = o.get_state(0)
+    cnt1 = o.counters()
     cells = after["cell"]
     assert np.all(np.diff(cells) >= 0)
     ids = after["id"]
     assert len(np.unique(ids)) == len(ids)
-    cnt = o.counters()
-    # surviving old particles plus injected ones
-    old = np.array([i in pos_before for i in ids])
-    assert old.sum() + (~old).sum() == len(ids)
+    injected = cnt1["injected"] - cnt0["injected"]
+    removed = cnt1["removed"] - cnt0["removed"]
+    assert injected > 0 and removed > 0
+    # the live count after one step: survivors plus the particles injected in it
+    assert len(ids) == len(before["id"]) + injected - removed
+    old = np.array([int(i) in pos_before for i in ids])
+    assert (~old).sum() == injected
     for k in np.unique(cells):
         sel = np.where(cells == k)[0]
         o_idx = [pos_before[int(i)] for i in ids[sel] if int(i) in pos_before]
@@ -212,7 +217,15 @@ def test_stable_sort_order_and_bijection():
         assert new == sorted(new)                       # injected ones last, by id
         if new and o_idx:
             assert all(int(i) in pos_before for i in ids[sel][: len(o_idx)])
-    assert len(ids) == len(before["id"]) + (cnt["injected"]) - cnt["removed"] or True
+    # brute force: the array before the sort holds the survivors in their previous order,
+    # then the injected particles in injection (= id) order; a stable argsort of their new
+    # cells must give the oracle's order exactly
+    cell_of = {int(i): int(cl) for i, cl in zip(ids, cells)}
+    pre_ids = [int(i) for i in before["id"] if int(i) in cell_of]
+    pre_ids += sorted(int(i) for i in ids if int(i) not in pos_before)
+    pre_cells = np.array([cell_of[i] for i in pre_ids])
+    perm = np.argsort(pre_cells, kind="stable")
+    assert np.array_equal(np.array(pre_ids)[perm], ids)
 
 
 def test_closed_box_conserves_particles_momentum_energy():
