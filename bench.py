@@ -98,11 +98,31 @@ def committed_valu():
     return float(m_f.group(1))
 
 
-def run_gpu(prec, case, gas, warmup, steps, timed_group="collide"):
+def host_cpu():
+    """CPU model and logical CPU counts of this host (for the CPU baseline's record)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def run_gpu(prec, case, gas, warmup, steps, timed_group="collide", develop=0):
     import torch
     from paper_2506_23917_amd.hs import Sim
 
     sim = Sim(gas, case, precision=prec, device="cuda:0")
+    if develop:
+        sim.step(develop)
     sim.step(warmup)
     sim.sync()
     # launch shapes (blocks per grid of each kernel group) picked by the autotuner on the
@@ -121,7 +141,8 @@ def run_gpu(prec, case, gas, warmup, steps, timed_group="collide"):
     tile_ms, launches = sim.kernel_timing(timed_group)
     sim.set_timing(False)
     sim.clear_timing()
-    return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches, tune=tune)
+    return sim, dict(dt=dt, n0=n0, n1=n1, tile_ms=tile_ms, launches=launches, tune=tune,
+                     before=develop + warmup + tune["steps"])
 
 
 def paired_accuracy(sim64, case, gas):
@@ -217,7 +238,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--develop", type=int, default=2000,
+                    help="untimed steps from the impulsive start before the warmup (cylinder), so the "
+                         "timed state is the developed flow whatever the warmup")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps of the CPU baseline sample")
@@ -234,11 +258,11 @@ def main():
     import workloads as W
     gas = W.gas()
     case = W.cylinder_2d()
-    case["n_steady"] = args.warmup          # the timed steps sample (Step 5 is on)
+    case["n_steady"] = args.develop + args.warmup      # the timed steps sample (Step 5 is on)
     ncells = case["nx"] * case["ny"]
 
-    log("[bench] fp32-mixed: warmup %d, timed %d" % (args.warmup, args.steps))
-    sim32, r32 = run_gpu("fp32", case, gas, args.warmup, args.steps)
+    log("[bench] fp32-mixed: develop %d, warmup %d, timed %d" % (args.develop, args.warmup, args.steps))
+    sim32, r32 = run_gpu("fp32", case, gas, args.warmup, args.steps, develop=args.develop)
     npart = 0.5 * (r32["n0"] + r32["n1"])
     value = npart * args.steps / r32["dt"]
     ms_step = 1e3 * r32["dt"] / args.steps
@@ -260,9 +284,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32/f64-mixed",
         "data": "synthetic",
-        "config": {"workload": "2-D Ma10 argon cylinder, Kn 0.01 on D, 800x600 cut-cell grid, ~30 particles "
-                               "per cell, FP32-mixed, developed flow with sampling on",
+        "config": {"workload": "2-D Ma10 argon cylinder, Kn 0.01 on D, 800x600 cut-cell grid, 30 particles "
+                               "per cell at the freestream density, FP32-mixed, sampling on; timed from %d "
+                               "steps after the impulsive start (%s flow: %d particles)"
+                               % (r32["before"], "developed" if r32["before"] >= 2000 else "developing",
+                                  int(npart)),
                    "particles": int(npart), "cells": ncells,
+                   "steps_before_timing": {"develop": args.develop, "warmup": args.warmup,
+                                           "autotune": r32["tune"]["steps"]},
                    "launch_grids": {k: v[0] for k, v in r32["tune"]["grids"].items()},
                    "tuning_steps": r32["tune"]["steps"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -280,7 +309,7 @@ def main():
         import torch
         torch.cuda.empty_cache()
         log("[bench] fp64: warmup %d, timed %d" % (args.warmup, args.steps))
-        sim64, r64 = run_gpu("fp64", case, gas, args.warmup, args.steps)
+        sim64, r64 = run_gpu("fp64", case, gas, args.warmup, args.steps, develop=args.develop)
         v64 = 0.5 * (r64["n0"] + r64["n1"]) * args.steps / r64["dt"]
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps, "tile_kernel_ms": r64["tile_ms"]}
         out["mixed_speedup_vs_fp64"] = value / v64
@@ -288,18 +317,19 @@ def main():
         acc = paired_accuracy(sim64, case, gas)
         out["accuracy"] = {"paired_one_step_rel_l2": acc, "bound": 1e-3,
                            "state": "the FP64 run's developed cylinder state after %d steps, imported "
-                                    "into an FP32-mixed sim; one step of each" % (args.warmup + args.steps)}
+                                    "into an FP32-mixed sim; one step of each" % (r64["before"] + args.steps)}
         log("[bench] FP32-mixed vs FP64, one paired step, relative L2: %s" % acc)
-        base_sim = sim64
+        base_sim, base_steps = sim64, r64["before"] + args.steps + 1
     else:
-        base_sim = sim32
+        base_sim, base_steps = sim32, r32["before"] + args.steps
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
         v_cpu, n_cpu, t_cpu = cpu_baseline(base_sim, case, gas, args.cpu_steps)
         out["cpu_baseline"] = {"value": v_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d step(s) of the same cylinder workload from the GPU's developed "
-                                         "state after %d steps (%d particles, %.1f s)" %
-                                         (args.cpu_steps, args.warmup + args.steps, n_cpu, t_cpu)}
+                               "sample": "%d step(s) of the same cylinder workload, single-threaded, from the "
+                                         "GPU's FP64 state %d steps after the impulsive start (%d particles, "
+                                         "%.1f s)" % (args.cpu_steps, base_steps, n_cpu, t_cpu),
+                               "host": host_cpu()}
         log("[bench] cpu: %.3e particle-steps/s (%.1f s)" % (v_cpu, t_cpu))
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,179 @@
+"""Step (5) and Step (6) on the GPU (gfx950) against the FP64 oracle, through the C ABI.
+
+Sampling is on from the first step (n_steady = 0), so every step adds to the 13 per-cell
+sums: N, sum c_i, sum c_i c_j (xx, yy, zz, xy, xz, yz) and sum |c|^2 c_i.  FP64 path from
+the same state and RNG stream: N exact; each sum within 1e-12 of N c_rms^k (k its order in c,
+c_rms the cell's root-mean-square speed), which is the rounding of a sum of N such terms
+added in another order; the time averages n, u, T, q of Step (6) and the current-state
+estimators of Step (3) within 1e-11 on the same scales.  Cases: the small workload shapes
+(tube cells above the tile kernel's limit take the block-per-cell kernel), the 0-D batch (all
+dense cells), the quadrilateral and hexahedral meshes, and the full-size cylinder after 2000
+steps of developed flow, whose stagnation cells are denser than the tile kernel takes.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle
+from gpu_util import gpu_to_abs, small_cases, vel_rel_err, case_extent
+from test_gpu_parity import _compare, _compare_trace
+
+pytestmark = pytest.mark.gpu
+
+M = W.ARGON["m"]
+
+
+def _sim(gas, cases, **kw):
+    from paper_2506_23917_amd.hs import Sim
+    return Sim(gas, cases, **kw)
+
+
+def compare_sums(ga, oa, label=""):
+    """The 13 per-cell sums of the GPU (ga) against the oracle's (oa), both (ncells, 13)."""
+    ga, oa = np.asarray(ga), np.asarray(oa)
+    assert ga.shape == oa.shape, label
+    assert np.array_equal(ga[:, 0], oa[:, 0]), (label, "N")
+    N = oa[:, 0]
+    crms = np.sqrt((oa[:, 4] + oa[:, 5] + oa[:, 6]) / np.maximum(N, 1.0))
+    worst = 0.0
+    for cols, k in (((1, 2, 3), 1), ((4, 5, 6, 7, 8, 9), 2), ((10, 11, 12), 3)):
+        scale = (N * crms ** k)[:, None] + 1e-300
+        e = np.abs(ga[:, cols] - oa[:, cols]) / scale
+        worst = max(worst, float(e.max()) if e.size else 0.0)
+        assert np.all(e <= 1e-12), (label, cols, float(e.max()), np.argwhere(e > 1e-12)[:5])
+    return worst
+
+
+def compare_moments(mg, mo, label="", tol=1e-11):
+    """Step (6) outputs (dicts of n, u, T, q) on the scales of each cell."""
+    n_o = np.asarray(mo["n"])
+    np.testing.assert_allclose(mg["n"], n_o, rtol=tol, atol=0, err_msg=label + " n")
+    u_o = np.asarray(mo["u"]).reshape(-1, 3)
+    u_g = np.asarray(mg["u"]).reshape(-1, 3)
+    T_o = np.asarray(mo["T"])
+    c_ref = np.sqrt(np.maximum((u_o ** 2).sum(1) + 3 * W.K_BOLTZMANN * np.abs(T_o) / M, 1.0))
+    assert np.all(np.abs(u_g - u_o) <= tol * c_ref[:, None]), (label, "u")
+    np.testing.assert_allclose(mg["T"], T_o, rtol=tol, atol=tol * 1.0, err_msg=label + " T")
+    q_scale = 0.5 * M * n_o * c_ref ** 3 + 1e-300
+    q_g = np.asarray(mg["q"]).reshape(-1, 3)
+    q_o = np.asarray(mo["q"]).reshape(-1, 3)
+    assert np.all(np.abs(q_g - q_o) <= tol * q_scale[:, None]), (label, "q")
+
+
+def _sampled(cases):
+    out = []
+    for c in cases:
+        c = dict(c)
+        c["n_steady"] = 0
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("name,steps", [("sod", 3), ("cylinder", 3), ("jets", 6), ("sphere", 2)])
+def test_fp64_sampled_steps_match_oracle(gas, name, steps):
+    cases = _sampled(small_cases()[name])
+    sim = _sim(gas, cases, precision="fp64", trace=True)
+    ora = Oracle(gas, cases, trace=True)
+    ora.init_particles()
+    for _ in range(steps):
+        sim.step(1)
+        ora.step(1)
+    dense = 0
+    for c, case in enumerate(cases):
+        g = sim.export_state(c)
+        _compare(gas, case, g, ora.get_state(c), label="%s case %d" % (name, c))
+        _compare_trace(sim.trace(c), ora.trace(c), label=name)
+        oc = ora.get_cells(c)
+        assert g["n_samples"] == oc["n_samples"] == steps
+        compare_sums(g["acc"], oc["acc"], label="%s case %d" % (name, c))
+        for mode in (0, 1):
+            compare_moments(sim.sample_moments(c, mode), ora.sample_moments(c, mode),
+                            label="%s case %d mode %d" % (name, c, mode))
+        dense += int((np.bincount(g["cell"], minlength=len(oc["acc"])) > 192).sum())
+    if name == "sod":
+        assert dense > 0          # cells above the tile kernel's limit were sampled too
+
+
+def test_fp64_sampled_0d_batch_matches_oracle(gas):
+    case = W.relax_0d(ncells=48, ppc=300, n_steady=0)
+    rng = np.random.default_rng(3)
+    case["dt_over_tau"] = 10 ** rng.uniform(-2, 2, 48)
+    v, cell, ids = W.relax_0d_state(case, ppc=300)
+    ora = Oracle(gas, case, trace=True)
+    ora.set_state(0, None, v, cell, ids, len(ids), 0)
+    sim = _sim(gas, case, precision="fp64", trace=True, no_particles=True)
+    cells = ora.get_cells(0)
+    sim.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=len(ids),
+                             step=0, sigc_max=cells["sigc_max"]))
+    for _ in range(3):
+        sim.step(1)
+        ora.step(1)
+    g = sim.export_state(0)
+    compare_sums(g["acc"], ora.get_cells(0)["acc"], label="0d")
+    for mode in (0, 1):
+        compare_moments(sim.sample_moments(0, mode), ora.sample_moments(0, mode), label="0d mode %d" % mode)
+
+
+@pytest.mark.parametrize("kind,name", [("quad", "box"), ("quad", "ogrid"), ("hex", "box"), ("hex", "shell")])
+def test_fp64_sampled_mesh_steps_match_oracle(gas, kind, name):
+    if kind == "quad":
+        from test_gpu_mesh import mesh_cases
+        case = mesh_cases()[name]
+    else:
+        from test_gpu_mesh3d import hex_cases
+        case = hex_cases()[name]
+    case = dict(case, n_steady=0)
+    sim = _sim(gas, case, precision="fp64", trace=True)
+    ora = Oracle(gas, case, trace=True)
+    ora.init_particles()
+    for _ in range(5):
+        sim.step(1)
+        ora.step(1)
+    g = sim.export_state(0)
+    o = ora.get_state(0)
+    assert np.array_equal(g["id"], o["id"]) and np.array_equal(g["cell"], o["cell"])
+    assert vel_rel_err(g["vel"], o["v"], gas) < 1e-12
+    oc = ora.get_cells(0)
+    assert oc["acc"][:, 0].sum() > 0
+    compare_sums(g["acc"], oc["acc"], label="%s %s" % (kind, name))
+    for mode in (0, 1):
+        compare_moments(sim.sample_moments(0, mode), ora.sample_moments(0, mode),
+                        label="%s %s mode %d" % (kind, name, mode))
+
+
+def test_cylinder_developed_full_size_sampled_step(gas):
+    """The cylinder at full size (800 x 600) after 2000 FP64 steps of developed flow on the
+    GPU, imported into the oracle; one sampled step on both: cells, ids and per-cell collision
+    records exact, velocities 1e-12, positions 1e-12 of the domain, all 13 sums 1e-12 and the
+    Step (6) outputs 1e-11.  The developed state puts the stagnation cells far above the tile
+    kernel's limit, so the block-per-cell kernel runs at its real shape."""
+    steps = 2000
+    case = W.cylinder_2d(n_steady=steps)
+    sim = _sim(gas, case, precision="fp64", trace=True)
+    sim.step(steps)
+    g = sim.export_state(0)
+    assert g["step"] == steps
+    counts = np.bincount(g["cell"], minlength=case["nx"] * case["ny"])
+    print("developed cylinder: %d particles, densest cell %d, cells above 192: %d (%d particles)"
+          % (len(g["id"]), counts.max(), (counts > 192).sum(), counts[counts > 192].sum()))
+    assert counts.max() > 192
+    ora = Oracle(gas, case, trace=True)
+    ora.set_state(0, gpu_to_abs(case, g), g["vel"].astype(np.float64), g["cell"], g["id"], g["next_id"], g["step"])
+    ora.set_cells(0, g["sigc_max"], g["acc"], g["n_samples"])
+    del g
+    sim.step(1)
+    ora.step(1)
+    g, o = sim.export_state(0), ora.get_state(0)
+    assert len(g["id"]) == len(o["id"])
+    assert np.array_equal(g["cell"], o["cell"]) and np.array_equal(g["id"], o["id"])
+    assert vel_rel_err(g["vel"], o["v"], gas) < 1e-12
+    assert np.abs(gpu_to_abs(case, g) - o["x"]).max() / case_extent(case) < 1e-12
+    _compare_trace(sim.trace(0), ora.trace(0), label="developed cylinder")
+    oc = ora.get_cells(0)
+    assert g["n_samples"] == oc["n_samples"] == 1
+    worst = compare_sums(g["acc"], oc["acc"], label="developed cylinder")
+    print("worst scaled sum difference %.2e" % worst)
+    del g, o
+    for mode in (0, 1):
+        compare_moments(sim.sample_moments(0, mode), ora.sample_moments(0, mode),
+                        label="developed cylinder mode %d" % mode)
