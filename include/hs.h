@@ -63,8 +63,12 @@ typedef enum {
 enum {
     HS_FLAG_TRACE = 1,         /* keep a per-cell record of the last step (hs_last_trace)  */
     HS_FLAG_NO_PARTICLES = 2,  /* hs_init_particles leaves the domain empty (for import)    */
-    HS_FLAG_GRAPH = 4          /* replay each step as a captured hipGraph                   */
+    HS_FLAG_GRAPH = 4,         /* replay each step as a captured hipGraph                   */
+    HS_FLAG_STATIC_SCRATCH = 8 /* hs_plan only: size the data part for hs_init_particles_static */
 };
+
+/* Size of the library's fixed device scratch array used by hs_init_particles_static. */
+#define HS_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
 
 /* Kernel groups of one step, for hs_kernel_timing (bit k of the timing mask = group k). */
 enum {
@@ -187,7 +191,9 @@ enum {
     HS_CNT_BOUNCE_CAP, HS_CNT_INJECT_CAP, HS_CNT_SKIPPED_CELLS, HS_NUM_COUNTERS
 };
 
-/* Size in bytes of the device workspace for this batch (no GPU work). */
+/* Size in bytes of the device workspace for this batch (no GPU work).  With
+ * HS_FLAG_STATIC_SCRATCH in flags: the size of the data part that hs_init_particles_static
+ * takes, and HS_ERR_CAPACITY when the batch's scratch part exceeds HS_STATIC_SCRATCH_BYTES. */
 hs_status hs_plan(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
                   uint32_t flags, size_t *dev_bytes);
 
@@ -199,6 +205,26 @@ hs_status hs_plan(const hs_gas *gas, const hs_case *cases, int n_cases, hs_preci
 hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases,
                             hs_precision prec, uint32_t flags, void *dev_workspace,
                             size_t dev_bytes, void *hip_stream, hs_sim **out);
+
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hs_init_particles with the step's scratch arrays
+ * (new cells, slots, sort permutation, scan partials, tile tables, cell records, output
+ * staging) placed in a fixed array inside the library, HS_STATIC_SCRATCH_BYTES on each device,
+ * held until the process ends.  The caller passes only the sim's data part, dev_data of
+ * data_bytes >= the size hs_plan reports with HS_FLAG_STATIC_SCRATCH (case tables, particle
+ * state, per-cell state and sums, wall sums, trace records), which it owns as with
+ * hs_init_particles.  The call allocates no device memory and creates no stream or event:
+ * the sim's block-per-cell kernel runs on hip_stream before the tile kernels instead of on a
+ * second stream.  Results are bit-identical to a sim made by hs_init_particles.
+ * All such sims on one device share the one array and its contents: only one may exist per
+ * device at a time (a second would overwrite the first's scratch; steps of two such sims that
+ * overlap race).  Every scratch array is written before it is read in each step, so the
+ * previous sim's contents need no clearing.  Errors: as hs_init_particles, plus
+ * HS_ERR_CAPACITY when the batch's scratch exceeds HS_STATIC_SCRATCH_BYTES (*out is then
+ * NULL) and HS_ERR_DEVICE when the array's device address cannot be found. */
+hs_status hs_init_particles_static(const hs_gas *gas, const hs_case *cases, int n_cases,
+                                   hs_precision prec, uint32_t flags, void *dev_data,
+                                   size_t data_bytes, void *hip_stream, hs_sim **out);
 
 /* Steps (2)-(5), n times, enqueued asynchronously on the sim's stream. */
 hs_status hs_step(hs_sim *sim, int64_t n);

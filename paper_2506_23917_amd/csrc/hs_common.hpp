@@ -175,6 +175,9 @@ void launch_finalize(const Ctx &c, void *stream, int case_id, int ncells, double
 void launch_surface_finalize(const Ctx &c, void *stream, int case_id, double *out);
 void launch_dsmc_ratio(const Ctx &c, void *stream, int case_id, int ncells, double *out);
 void launch_surface_reduce(const Ctx &c, void *stream, int case_id, double *out);
+// The library's fixed scratch array on the current device (HS_STATIC_SCRATCH_BYTES): its
+// device address and size; 0 on success, else the HIP error code.
+int static_scratch(void **ptr, size_t *bytes);
 int cap_wave();
 int tile_width();
 int cap_block(int precision);

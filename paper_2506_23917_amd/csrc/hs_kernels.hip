@@ -13,6 +13,7 @@
 //   finish_step    live count, step counter, sample counters
 #include "hs_device.hpp"
 
+#include <mutex>
 #include <type_traits>
 
 namespace hsk {
@@ -3067,6 +3068,33 @@ void launch_dsmc_ratio(const Ctx &c, void *s, int case_id, int ncells, double *o
 void launch_finalize(const Ctx &c, void *s, int case_id, int ncells, double *out)
 {
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(ncells, 256)), dim3(256), 0, S_(s), c, case_id, out);
+}
+
+// Fixed scratch array for hs_init_particles_static (sims whose callers cannot allocate device
+// memory).  Every device holds its own copy; its address is looked up once per device, with
+// that device current, and kept: host code uses only that address, never the array's name.
+static __device__ __align__(256) unsigned char scratch[HS_STATIC_SCRATCH_BYTES];
+
+int static_scratch(void **ptr, size_t *bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = (size_t)HS_STATIC_SCRATCH_BYTES;
+    return 0;
 }
 
 int cap_wave() { return kCapWave; }

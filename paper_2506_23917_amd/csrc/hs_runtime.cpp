@@ -20,8 +20,14 @@ constexpr double kKB_h = 1.380649e-23;
 constexpr double kPi_h = 3.14159265358979323846;
 constexpr uint32_t kMagic = 0x48534331u;  // "HSC1"
 
+// Offsets of the device arrays.  The sim's own data (case tables, particle state, per-cell
+// state and outputs) come first; the arrays a step only uses as scratch (new cells, slots,
+// permutation, scan, tiles, cell records, output staging) follow from scratch_begin.  One
+// workspace holds both parts back to back; hs_init_particles_static puts the second part in
+// the library's fixed device array instead.
 struct Layout {
     size_t total = 0;
+    size_t scratch_begin = 0;
     size_t globals, cases, faces, rbox, rstate, dtcell;
     size_t pos[2][3], vel[2][3], cell[2], id[2];
     size_t newcell, slot, perm, work, count, cstart, sigc, acc, vol, facecnt, facestart, scanpart, big, tiles, tilecase, cellrec, surf, trace, out;
@@ -527,6 +533,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     const size_t es = prec == HS_FP64 ? 8 : 4;
     const size_t cap = (size_t)std::max<int64_t>(P.capacity, 1);
     const size_t nc = (size_t)P.ncells;
+    // ---- the sim's data
     L.globals = take(sizeof(Globals));
     L.cases = take(sizeof(CaseDev) * P.cases.size());
     L.faces = take(sizeof(FaceDev) * std::max<size_t>(P.faces.size(), 1));
@@ -539,26 +546,9 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
         L.cell[b] = take(4 * cap);
         L.id[b] = take(8 * cap);
     }
-    if (P.any_spatial) {
-        L.newcell = take(4 * cap);
-        L.slot = take(4 * cap);
-        L.perm = take(4 * cap);
-    } else {
-        L.newcell = L.slot = L.perm = 0;
-    }
-    L.work = P.any_body ? take(4 * cap) : 0;
-    L.count = take(4 * nc);
-    L.cstart = take(4 * (nc + 1));
     L.sigc = take(8 * nc);
     L.acc = take(8 * 13 * nc);
     L.vol = take(8 * nc);
-    L.facecnt = take(4 * std::max<size_t>(P.faces.size(), 1));
-    L.facestart = take(4 * (P.faces.size() + 1));
-    L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
-    L.big = take(4 * nc);
-    L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
-    L.tilecase = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
-    L.cellrec = take(8 * 16 * nc);
     size_t nsurf = 0;
     for (const auto &c : P.cases) nsurf += (size_t)c.n_surf;
     L.surf_bytes = 8 * 7 * (size_t)kSurfCopies * std::max<size_t>(nsurf, 1);
@@ -575,6 +565,25 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
         L.hnode = take(sizeof(int32_t) * 8 * nc);
         L.hnbr = take(sizeof(int32_t) * 8 * nc);
     }
+    // ---- scratch of the step
+    L.scratch_begin = o;
+    if (P.any_spatial) {
+        L.newcell = take(4 * cap);
+        L.slot = take(4 * cap);
+        L.perm = take(4 * cap);
+    } else {
+        L.newcell = L.slot = L.perm = 0;
+    }
+    L.work = P.any_body ? take(4 * cap) : 0;
+    L.count = take(4 * nc);
+    L.cstart = take(4 * (nc + 1));
+    L.facecnt = take(4 * std::max<size_t>(P.faces.size(), 1));
+    L.facestart = take(4 * (P.faces.size() + 1));
+    L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
+    L.big = take(4 * nc);
+    L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
+    L.tilecase = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
+    L.cellrec = take(8 * 16 * nc);
     size_t maxcase = 1;
     for (const auto &c : P.cases) maxcase = std::max<size_t>(maxcase, (size_t)c.ncells);
     size_t maxsurf = 0;
@@ -594,7 +603,8 @@ struct hs_sim {
     // kernels, forked from and joined back into `stream` by the two events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    char *ws;
+    char *ws;                            // the sim's data (the caller's workspace)
+    char *scratch;                       // the step's scratch arrays
     size_t ws_bytes;
     Plan plan;
     Layout lay;
@@ -615,6 +625,12 @@ struct hs_sim {
 
 namespace {
 
+// Device address of the layout offset `off` (data part or scratch part).
+char *at(const hs_sim *s, size_t off)
+{
+    return off < s->lay.scratch_begin ? s->ws + off : s->scratch + (off - s->lay.scratch_begin);
+}
+
 hs_status fail(hs_sim *s, hs_status st, const std::string &why)
 {
     if (s) {
@@ -633,7 +649,7 @@ hs_status fail(hs_sim *s, hs_status st, const std::string &why)
 hs_status read_globals(hs_sim *s, Globals &G)
 {
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    HIPCHK(s, hipMemcpy(&G, s->ws + s->lay.globals, sizeof(Globals), hipMemcpyDeviceToHost));
+    HIPCHK(s, hipMemcpy(&G, at(s, s->lay.globals), sizeof(Globals), hipMemcpyDeviceToHost));
     return HS_OK;
 }
 
@@ -692,12 +708,16 @@ void enqueue_step(hs_sim *s, int timed)
     // cells denser than the tile limit: their kernel sorts, gathers and collides its cells
     // alone (from the scatter's permutation), sharing no cell with the gather, scalar and
     // tile kernels, so it runs on the side stream while they run
-    (void)hipEventRecord(s->ev_fork, ms);
-    (void)hipStreamWaitEvent(s->side, s->ev_fork, 0);
-    mark(HS_KERNEL_DENSE, true, s->side);
-    Launch::dense(c, (void *)s->side);
-    mark(HS_KERNEL_DENSE, false, s->side);
-    (void)hipEventRecord(s->ev_join, s->side);
+    // (a sim without a side stream runs it first on its own stream)
+    const hipStream_t ds = s->side ? s->side : ms;
+    if (s->side) {
+        (void)hipEventRecord(s->ev_fork, ms);
+        (void)hipStreamWaitEvent(s->side, s->ev_fork, 0);
+    }
+    mark(HS_KERNEL_DENSE, true, ds);
+    Launch::dense(c, (void *)ds);
+    mark(HS_KERNEL_DENSE, false, ds);
+    if (s->side) (void)hipEventRecord(s->ev_join, s->side);
     mark(HS_KERNEL_GATHER, true, ms);
     Launch::gather(c, st);
     mark(HS_KERNEL_GATHER, false, ms);
@@ -707,7 +727,7 @@ void enqueue_step(hs_sim *s, int timed)
     mark(HS_KERNEL_COLLIDE, true, ms);
     Launch::collide(c, st);
     mark(HS_KERNEL_COLLIDE, false, ms);
-    (void)hipStreamWaitEvent(ms, s->ev_join, 0);
+    if (s->side) (void)hipStreamWaitEvent(ms, s->ev_join, 0);
     Launch::finish_step(c, st);
     mark(HS_KERNEL_STEP, false, ms);
 }
@@ -725,85 +745,103 @@ hs_status hs_plan(const hs_gas *gas, const hs_case *cases, int n_cases, hs_preci
     if (st) return st;
     Plan P;
     build_plan(gas, cases, n_cases, P);
-    *dev_bytes = make_layout(P, prec, flags).total;
+    const Layout L = make_layout(P, prec, flags & ~(uint32_t)HS_FLAG_STATIC_SCRATCH);
+    if (flags & HS_FLAG_STATIC_SCRATCH) {
+        // the caller's part only; the scratch part must fit the library's fixed array
+        if (L.total - L.scratch_begin > (size_t)HS_STATIC_SCRATCH_BYTES) return HS_ERR_CAPACITY;
+        *dev_bytes = L.scratch_begin;
+    } else {
+        *dev_bytes = L.total;
+    }
     return HS_OK;
 }
 
-hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
-                            uint32_t flags, void *dev_workspace, size_t dev_bytes, void *hip_stream, hs_sim **out)
+}  // extern "C"
+
+namespace {
+
+// Shared set-up of hs_init_particles and hs_init_particles_static: `data` holds the sim's
+// data part of the layout (>= scratch_begin bytes, or the whole layout when `scratch` is
+// null), `scratch` the scratch part; `side_stream`: fork the dense-cell kernel onto a second
+// stream (else it runs on the caller's stream).
+hs_status create_sim(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec, uint32_t flags,
+                     char *data, size_t data_bytes, char *scratch, size_t scratch_bytes, void *hip_stream,
+                     bool side_stream, hs_sim **out)
 {
     std::string why;
-    if (!out || !dev_workspace || (prec != HS_FP64 && prec != HS_FP32_MIXED)) return HS_ERR_ARG;
+    if (!out || !data || (prec != HS_FP64 && prec != HS_FP32_MIXED)) return HS_ERR_ARG;
     hs_status st = validate(gas, cases, n_cases, why);
     if (st) return st;
     hs_sim *s = new hs_sim();
     s->prec = prec;
     s->flags = flags;
     s->stream = (hipStream_t)hip_stream;
-    s->ws = (char *)dev_workspace;
-    s->ws_bytes = dev_bytes;
+    s->ws = data;
+    s->ws_bytes = data_bytes;
     build_plan(gas, cases, n_cases, s->plan);
     s->lay = make_layout(s->plan, prec, flags);
-    if (dev_bytes < s->lay.total) {
+    s->scratch = scratch ? scratch : data + s->lay.scratch_begin;
+    const size_t need_data = scratch ? s->lay.scratch_begin : s->lay.total;
+    const size_t need_scratch = s->lay.total - s->lay.scratch_begin;
+    if (data_bytes < need_data || (scratch && scratch_bytes < need_scratch)) {
         delete s;
-        return HS_ERR_ARG;
+        return scratch && scratch_bytes < need_scratch ? HS_ERR_CAPACITY : HS_ERR_ARG;
     }
     s->cases.assign(cases, cases + n_cases);
     const Layout &L = s->lay;
-    char *w = s->ws;
     Ctx &c = s->ctx;
     std::memset(&c, 0, sizeof(c));
-    c.cases = (const CaseDev *)(w + L.cases);
-    c.faces = (const FaceDev *)(w + L.faces);
-    c.region_box = (const double *)(w + L.rbox);
-    c.region_state = (const StateDev *)(w + L.rstate);
-    c.dt_cell = s->plan.any_0d ? (const double *)(w + L.dtcell) : nullptr;
+    c.cases = (const CaseDev *)at(s, L.cases);
+    c.faces = (const FaceDev *)at(s, L.faces);
+    c.region_box = (const double *)at(s, L.rbox);
+    c.region_state = (const StateDev *)at(s, L.rstate);
+    c.dt_cell = s->plan.any_0d ? (const double *)at(s, L.dtcell) : nullptr;
     c.gas = s->plan.gas;
     for (int b = 0; b < 2; ++b) {
         for (int a = 0; a < 3; ++a) {
-            c.buf[b].pos[a] = a < s->plan.dim_max ? (void *)(w + L.pos[b][a]) : nullptr;
-            c.buf[b].vel[a] = w + L.vel[b][a];
+            c.buf[b].pos[a] = a < s->plan.dim_max ? (void *)at(s, L.pos[b][a]) : nullptr;
+            c.buf[b].vel[a] = at(s, L.vel[b][a]);
         }
-        c.buf[b].cell = (int32_t *)(w + L.cell[b]);
-        c.buf[b].id = (int64_t *)(w + L.id[b]);
+        c.buf[b].cell = (int32_t *)at(s, L.cell[b]);
+        c.buf[b].id = (int64_t *)at(s, L.id[b]);
     }
-    c.newcell = s->plan.any_spatial ? (int32_t *)(w + L.newcell) : nullptr;
-    c.slot = s->plan.any_spatial ? (int32_t *)(w + L.slot) : nullptr;
-    c.perm = s->plan.any_spatial ? (int32_t *)(w + L.perm) : nullptr;
-    c.count = (int32_t *)(w + L.count);
-    c.cstart = (int32_t *)(w + L.cstart);
-    c.sigc = (double *)(w + L.sigc);
-    c.acc = (double *)(w + L.acc);
-    c.vol = (double *)(w + L.vol);
-    c.face_cnt = (int32_t *)(w + L.facecnt);
-    c.face_start = (int32_t *)(w + L.facestart);
-    c.scan_part = (int32_t *)(w + L.scanpart);
-    c.big_list = (int32_t *)(w + L.big);
-    c.tile_cell = (int32_t *)(w + L.tiles);
-    c.tile_case = (int32_t *)(w + L.tilecase);
-    c.cellrec = (double *)(w + L.cellrec);
-    c.surf = (double *)(w + L.surf);
+    c.newcell = s->plan.any_spatial ? (int32_t *)at(s, L.newcell) : nullptr;
+    c.slot = s->plan.any_spatial ? (int32_t *)at(s, L.slot) : nullptr;
+    c.perm = s->plan.any_spatial ? (int32_t *)at(s, L.perm) : nullptr;
+    c.count = (int32_t *)at(s, L.count);
+    c.cstart = (int32_t *)at(s, L.cstart);
+    c.sigc = (double *)at(s, L.sigc);
+    c.acc = (double *)at(s, L.acc);
+    c.vol = (double *)at(s, L.vol);
+    c.face_cnt = (int32_t *)at(s, L.facecnt);
+    c.face_start = (int32_t *)at(s, L.facestart);
+    c.scan_part = (int32_t *)at(s, L.scanpart);
+    c.big_list = (int32_t *)at(s, L.big);
+    c.tile_cell = (int32_t *)at(s, L.tiles);
+    c.tile_case = (int32_t *)at(s, L.tilecase);
+    c.cellrec = (double *)at(s, L.cellrec);
+    c.surf = (double *)at(s, L.surf);
     {
         size_t ns = 0;
         for (const auto &cd : s->plan.cases) ns += (size_t)cd.n_surf;
         c.n_surf_total = (int32_t)ns;
     }
-    c.work = s->plan.any_body ? (int32_t *)(w + L.work) : nullptr;
-    if (s->plan.any_mesh) c.mgeo = (const double *)(w + L.mgeo);
+    c.work = s->plan.any_body ? (int32_t *)at(s, L.work) : nullptr;
+    if (s->plan.any_mesh) c.mgeo = (const double *)at(s, L.mgeo);
     if (s->plan.any_quad) {
-        c.mxy = (const double *)(w + L.mxy);
-        c.mquad = (const int32_t *)(w + L.mquad);
-        c.mnbr = (const int32_t *)(w + L.mnbr);
+        c.mxy = (const double *)at(s, L.mxy);
+        c.mquad = (const int32_t *)at(s, L.mquad);
+        c.mnbr = (const int32_t *)at(s, L.mnbr);
     }
     if (s->plan.any_hex) {
-        c.hxyz = (const double *)(w + L.hxyz);
-        c.hnode = (const int32_t *)(w + L.hnode);
-        c.hnbr = (const int32_t *)(w + L.hnbr);
+        c.hxyz = (const double *)at(s, L.hxyz);
+        c.hnode = (const int32_t *)at(s, L.hnode);
+        c.hnbr = (const int32_t *)at(s, L.hnbr);
     }
     c.tile_w = tile_width();
     c.dim_max = s->plan.dim_max;
-    c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)(w + L.trace) : nullptr;
-    c.g = (Globals *)(w + L.globals);
+    c.trace = (flags & HS_FLAG_TRACE) ? (TraceDev *)at(s, L.trace) : nullptr;
+    c.g = (Globals *)at(s, L.globals);
     c.n_cases = n_cases;
     c.n_faces = (int32_t)s->plan.faces.size();
     c.ncells_total = (int32_t)s->plan.ncells;
@@ -814,7 +852,7 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
 
     auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s->stream);
+        return hipMemcpyAsync(at(s, off), src, bytes, hipMemcpyHostToDevice, s->stream);
     };
     hipError_t e = hipSuccess;
     e = e ? e : up(L.cases, s->plan.cases.data(), sizeof(CaseDev) * s->plan.cases.size());
@@ -833,8 +871,8 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
         e = e ? e : up(L.hnode, s->plan.hnode.data(), sizeof(int32_t) * s->plan.hnode.size());
         e = e ? e : up(L.hnbr, s->plan.hnbr.data(), sizeof(int32_t) * s->plan.hnbr.size());
     }
-    e = e ? e : hipMemsetAsync(w + L.globals, 0, sizeof(Globals), s->stream);
-    e = e ? e : hipMemsetAsync(w + L.surf, 0, L.surf_bytes, s->stream);
+    e = e ? e : hipMemsetAsync(at(s, L.globals), 0, sizeof(Globals), s->stream);
+    e = e ? e : hipMemsetAsync(at(s, L.surf), 0, L.surf_bytes, s->stream);
     if (e != hipSuccess) {
         std::string m = hipGetErrorString(e);
         delete s;
@@ -851,9 +889,11 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     if (!s->plan.any_spatial) launch_build_big(ci, s->stream);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
+    if (side_stream) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
         if (s->side) (void)hipStreamDestroy(s->side);
@@ -863,6 +903,31 @@ hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases
     *out = s;
     hs_status cs = check_device(s);
     return cs;
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_init_particles(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
+                            uint32_t flags, void *dev_workspace, size_t dev_bytes, void *hip_stream, hs_sim **out)
+{
+    if (flags & HS_FLAG_STATIC_SCRATCH) return HS_ERR_ARG;
+    return create_sim(gas, cases, n_cases, prec, flags, (char *)dev_workspace, dev_bytes, nullptr, 0, hip_stream,
+                      true, out);
+}
+
+hs_status hs_init_particles_static(const hs_gas *gas, const hs_case *cases, int n_cases, hs_precision prec,
+                                   uint32_t flags, void *dev_data, size_t data_bytes, void *hip_stream,
+                                   hs_sim **out)
+{
+    if (!out || !dev_data) return HS_ERR_ARG;
+    *out = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    if (static_scratch(&scratch, &scratch_bytes) != 0) return HS_ERR_DEVICE;
+    return create_sim(gas, cases, n_cases, prec, flags & ~(uint32_t)HS_FLAG_STATIC_SCRATCH, (char *)dev_data,
+                      data_bytes, (char *)scratch, scratch_bytes, hip_stream, false, out);
 }
 
 hs_status hs_step(hs_sim *s, int64_t n)
@@ -895,7 +960,7 @@ hs_status hs_surface_sums(hs_sim *s, int c, double *sums7)
     hs_status st = check_device(s);
     if (st) return st;
     const CaseDev &cs = s->plan.cases[c];
-    double *out = (double *)(s->ws + s->lay.out);
+    double *out = (double *)at(s, s->lay.out);
     launch_surface_reduce(s->ctx, s->stream, c, out);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(sums7, out, 8 * 7 * (size_t)cs.n_surf, hipMemcpyDeviceToHost, s->stream));
@@ -910,7 +975,7 @@ hs_status hs_surface_sample(hs_sim *s, int c, double *elem8, double *body5, int6
     hs_status st = check_device(s);
     if (st) return st;
     const int ns = s->plan.cases[c].n_surf;
-    double *out = (double *)(s->ws + s->lay.out);
+    double *out = (double *)at(s, s->lay.out);
     launch_surface_finalize(s->ctx, s->stream, c, out);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(elem8, out, 8 * 8 * (size_t)ns, hipMemcpyDeviceToHost, s->stream));
@@ -943,7 +1008,7 @@ hs_status hs_dsmc_ratio(hs_sim *s, int c, double *ratio)
     hs_status st = check_device(s);
     if (st) return st;
     const int nc = s->plan.cases[c].ncells;
-    double *out = (double *)(s->ws + s->lay.out);
+    double *out = (double *)at(s, s->lay.out);
     launch_dsmc_ratio(s->ctx, s->stream, c, nc, out);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(ratio, out, 8 * (size_t)nc, hipMemcpyDeviceToHost, s->stream));
@@ -987,7 +1052,7 @@ hs_status hs_sample_moments(hs_sim *s, int c, int mode, double *n, double *u3, d
     hs_status st = check_device(s);
     if (st) return st;
     const int nc = s->plan.cases[c].ncells;
-    double *out = (double *)(s->ws + s->lay.out);
+    double *out = (double *)at(s, s->lay.out);
     if (mode == 0) launch_finalize(s->ctx, s->stream, c, nc, out);
     else launch_moments_now(s->ctx, s->stream, c, nc, out);
     std::vector<double> h((size_t)nc * 8);
@@ -1196,7 +1261,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     G.dt_cur[c] = hd.dt_next;
     G.dt_next[c] = kInfBits;
     G.t_sampled[c] = hd.t_sampled;
-    HIPCHK(s, hipMemcpy(s->ws + s->lay.globals, &G, sizeof(G), hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(at(s, s->lay.globals), &G, sizeof(G), hipMemcpyHostToDevice));
     Launch::tile_table(s->ctx, s->stream);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipStreamSynchronize(s->stream));

@@ -18,7 +18,7 @@ FP64, FP32_MIXED = 0, 1
 BC = {"outflow": 0, "specular": 1, "inflow": 2}
 BODY = {"none": 0, "cylinder": 1, "sphere": 2}
 EDGE = {"outflow": -1, "inflow": -2, "wall": -3, "specular": -4}
-FLAG_TRACE, FLAG_NO_PARTICLES, FLAG_GRAPH = 1, 2, 4
+FLAG_TRACE, FLAG_NO_PARTICLES, FLAG_GRAPH, FLAG_STATIC_SCRATCH = 1, 2, 4, 8
 KERNELS = {"inject": 0, "move": 1, "scan": 2, "scatter": 3, "gather": 4, "scalars": 5, "collide": 6,
            "dense": 7, "step": 8}
 
@@ -89,6 +89,8 @@ def lib():
         sig = {
             "hs_plan": ([P(HsGas), P(HsCase), C.c_int, C.c_int, C.c_uint32, P(C.c_size_t)], C.c_int),
             "hs_init_particles": ([P(HsGas), P(HsCase), C.c_int, C.c_int, C.c_uint32, V, C.c_size_t, V, P(V)], C.c_int),
+            "hs_init_particles_static": ([P(HsGas), P(HsCase), C.c_int, C.c_int, C.c_uint32, V, C.c_size_t, V,
+                                          P(V)], C.c_int),
             "hs_step": ([V, C.c_int64], C.c_int),
             "hs_sync": ([V], C.c_int),
             "hs_sample_moments": ([V, C.c_int, C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
@@ -122,7 +124,7 @@ def lib():
 
 
 def exported_symbols():
-    return ["hs_plan", "hs_init_particles", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
+    return ["hs_plan", "hs_init_particles", "hs_init_particles_static", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
             "hs_export_state", "hs_import_state", "hs_last_trace", "hs_counters", "hs_num_cells",
             "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
             "hs_surface_sums", "hs_surface_sample", "hs_step_dt", "hs_dsmc_ratio", "hs_error_string", "hs_destroy",
@@ -203,7 +205,9 @@ class Sim:
     """A batch of flow cases on one GPU.  `precision` is "fp64" or "fp32" (FP32-mixed)."""
 
     def __init__(self, gas: dict, cases, precision="fp64", trace=False, graph=False,
-                 no_particles=False, device="cuda:0"):
+                 no_particles=False, device="cuda:0", static_scratch=False):
+        """static_scratch: make the sim with hs_init_particles_static (the step's scratch in
+        the library's fixed device array; this binding then allocates only the data part)."""
         import torch
         if isinstance(cases, dict):
             cases = [cases]
@@ -219,7 +223,8 @@ class Sim:
         self._cs = _Cases(self.cases)
         self._gas = make_gas(gas)
         nb = C.c_size_t()
-        rc = self.L.hs_plan(C.byref(self._gas), self._cs.arr, self._cs.n, self.prec, self.flags, C.byref(nb))
+        plan_flags = self.flags | (FLAG_STATIC_SCRATCH if static_scratch else 0)
+        rc = self.L.hs_plan(C.byref(self._gas), self._cs.arr, self._cs.n, self.prec, plan_flags, C.byref(nb))
         if rc:
             raise HsError(rc, "hs_plan rejected the cases")
         self.ws_bytes = nb.value
@@ -230,9 +235,9 @@ class Sim:
             self.stream = torch.cuda.Stream(device=self.device)
             torch.cuda.current_stream(self.device).synchronize()
         h = C.c_void_p()
-        rc = self.L.hs_init_particles(C.byref(self._gas), self._cs.arr, self._cs.n, self.prec, self.flags,
-                                      C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
-                                      C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        init = self.L.hs_init_particles_static if static_scratch else self.L.hs_init_particles
+        rc = init(C.byref(self._gas), self._cs.arr, self._cs.n, self.prec, self.flags,
+                  C.c_void_p(self.ws.data_ptr()), self.ws_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         self.h = h
         if rc:
             msg = self.error() if h.value else "hs_init_particles"

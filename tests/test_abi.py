@@ -131,3 +131,21 @@ def test_plan_validates_hexahedra_on_host():
             assert e.code == 1, what
         else:
             raise AssertionError("expected an argument error: " + what)
+
+
+def test_plan_for_the_static_scratch_variant():
+    """hs_plan with HS_FLAG_STATIC_SCRATCH sizes only the caller's data part of a small batch,
+    and refuses a batch whose scratch exceeds the library's fixed array (no GPU)."""
+    from paper_2506_23917_amd import hs
+    import workloads as W
+    g = W.gas()
+    small = W.cylinder_2d(nx=80, ny=60, ppc=10)
+    whole = hs.plan_bytes(g, small, hs.FP64)
+    data = hs.plan_bytes(g, small, hs.FP64, flags=hs.FLAG_STATIC_SCRATCH)
+    assert 0 < data < whole
+    try:
+        hs.plan_bytes(g, W.cylinder_2d(), hs.FP32_MIXED, flags=hs.FLAG_STATIC_SCRATCH)
+    except hs.HsError as e:
+        assert e.code == 2
+    else:
+        raise AssertionError("expected a capacity error")
