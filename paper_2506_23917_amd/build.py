@@ -14,6 +14,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # the same flight; no fused multiply-add contraction anywhere
          "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no loop-invariant hoisting in the code generator: it lifts the FP64 power,
+         # exponential and sine polynomials' constants (and lane-derived addresses) out of the
+         # tile loops, where they occupy registers for the whole loop and spill
+         "-mllvm", "-disable-machine-licm", "-mllvm", "-disable-licm-promotion",
          "-Wno-unused-command-line-argument"]
 
 

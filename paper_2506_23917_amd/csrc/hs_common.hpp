@@ -56,6 +56,7 @@ struct CaseDev {
     int32_t surf0, n_surf;          // body surface elements: first of the batch, count
     int32_t adapt_dt;               // 1: Eq. 26 global step
     int32_t mesh;                   // 1: cells are quads of the mesh arrays of Ctx
+    double inv_n[2];                // 1 / n_x and 1 / (n_x n_y): cell index -> (i, j, k)
 };
 
 struct FaceDev {

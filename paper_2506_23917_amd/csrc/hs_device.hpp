@@ -131,6 +131,36 @@ __device__ __forceinline__ void cell_ijk(const CaseDev &cs, int local, int ijk[3
     if (cs.dim >= 3) ijk[2] = local / (cs.n[0] * cs.n[1]);
 }
 
+// a / n for 0 <= a < 2^31, n >= 1, from a double reciprocal (a few instructions instead of an
+// integer division), corrected to the exact quotient; r = a - q n.
+__device__ __forceinline__ int div_exact(int a, int n, double inv, int &r)
+{
+    int q = (int)((double)a * inv);
+    r = a - q * n;
+    if (r < 0) {
+        --q;
+        r += n;
+    } else if (r >= n) {
+        ++q;
+        r -= n;
+    }
+    return q;
+}
+
+// cell_ijk for a grid case (dim 1-3) by reciprocal multiplication.
+__device__ __forceinline__ void cell_ijk_fast(const CaseDev &cs, int local, int ijk[3])
+{
+    ijk[0] = local;
+    ijk[1] = ijk[2] = 0;
+    if (cs.dim == 3) {
+        int rem;
+        ijk[2] = div_exact(local, cs.n[0] * cs.n[1], cs.inv_n[1], rem);
+        ijk[1] = div_exact(rem, cs.n[0], cs.inv_n[0], ijk[0]);
+    } else if (cs.dim == 2) {
+        ijk[1] = div_exact(local, cs.n[0], cs.inv_n[0], ijk[0]);
+    }
+}
+
 __device__ __forceinline__ int cell_local(const CaseDev &cs, const int ijk[3])
 {
     return ijk[0] + cs.n[0] * (ijk[1] + cs.n[1] * ijk[2]);
@@ -325,7 +355,7 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
 {
     const int dim = cs.dim;
     int ijk[3];
-    cell_ijk(cs, local, ijk);
+    cell_ijk_fast(cs, local, ijk);
     if (cs.body != HS_BODY_NONE) {
         double X[3] = {0.0, 0.0, 0.0}, V[3];
         for (int a = 0; a < 3; ++a) if (a < dim) X[a] = cs.lo[a] + ((double)ijk[a] + (double)xr[a]) * cs.h[a];
@@ -442,7 +472,7 @@ __device__ __forceinline__ int flight(const CaseDev &cs, int local, P xr[3], P v
 {
     const int dim = cs.dim;
     int ijk[3];
-    cell_ijk(cs, local, ijk);
+    cell_ijk_fast(cs, local, ijk);
     if (cs.body != HS_BODY_NONE) {
         const int na = body_axes(cs);
         bool near = true;

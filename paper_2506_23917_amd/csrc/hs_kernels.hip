@@ -753,33 +753,89 @@ __global__ __launch_bounds__(kBlock) void k_inject_fill(Ctx C)
     if (capped) atomicAdd((unsigned long long *)&C.g->counters[fd.case_id][HS_CNT_INJECT_CAP], (unsigned long long)capped);
 }
 
+// Counter sums of one wave by case.  Lane l holds counter base + (l & 7) of slot l >> 3
+// (eight cases at a time).  Lanes count privately; when the wave moves to a tile of another
+// case their counts are summed over the wave into that case's slot, and the flush adds each
+// slot with one atomic per lane, so no address takes an atomic per lane or per tile.
+struct CaseTally {
+    long long val;
+    int slot_case;
+    int nslot;                          // uniform over the wave
+};
+
+template <int K>
+__device__ __forceinline__ void tally_flush(const Ctx &C, CaseTally &T, int base)
+{
+    const int k = threadIdx.x & 7;
+    if (T.slot_case >= 0 && k < K && T.val != 0)
+        atomicAdd((unsigned long long *)&C.g->counters[T.slot_case][base + k], (unsigned long long)T.val);
+    T.val = 0;
+    T.slot_case = -1;
+    T.nslot = 0;
+}
+
+// Adds the wave's sums of v[] to case cid (every lane of the wave calls it).
+template <int K>
+__device__ __forceinline__ void tally_add(const Ctx &C, CaseTally &T, int cid, int base, const long long (&v)[K])
+{
+    static_assert(K <= 8, "eight counters per slot");
+    long long tot[K];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        long long x = v[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        tot[j] = x;
+        any = any || x != 0;
+    }
+    if (!any || cid < 0) return;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long hit = __ballot(T.slot_case == cid);
+    int slot;
+    if (hit) {
+        slot = (__ffsll((long long)hit) - 1) >> 3;
+    } else {
+        if (T.nslot == 8) tally_flush<K>(C, T, base);
+        slot = T.nslot++;
+        if ((lane >> 3) == slot) T.slot_case = cid;
+    }
+    if ((lane >> 3) == slot) {
+        const int k = lane & 7;
+        long long a = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j == k) a = tot[j];
+        T.val += a;
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // Free transport and cell counts (Step 2 -> Step 3 histogram)
 // ------------------------------------------------------------------------------------
 
 // Wave-aggregated slot allocation: one atomic per distinct destination cell in the wave;
 // returns this lane's slot in its cell (order within a cell is arbitrary; the collide
-// kernels restore the stable order).
+// kernels restore the stable order).  The lanes are grouped by cell first (one uniform pass
+// per distinct cell, each lane keeping its group's lane mask); a lane's rank is the number
+// of its group's lanes below it, and the group's lowest lane takes the group's slots.
 __device__ __forceinline__ int wave_slot(int32_t *count, int nc, bool want)
 {
-    const int lane = threadIdx.x & 63;
     unsigned long long pending = __ballot(want);
-    int leader = 0, rank = 0, cnt = 0;
-    // group the lanes by destination cell (ALU only), then one batched atomic per wave
+    unsigned long long mine = 0ull;
     while (pending) {
         const int l0 = __ffsll((long long)pending) - 1;
-        const int c0 = __shfl(nc, l0, 64);
-        const unsigned long long same = __ballot(want && nc == c0) & pending;
-        if (lane == l0) cnt = __popcll(same);
-        if ((same >> lane) & 1ull) {
-            leader = l0;
-            rank = __popcll(same & ((1ull << lane) - 1ull));
-        }
+        const int c0 = __builtin_amdgcn_readlane(nc, l0);
+        const bool in = want && nc == c0;
+        const unsigned long long same = __ballot(in);
+        if (in) mine = same;
         pending &= ~same;
     }
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned int)(mine >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned int)mine, 0u));
     int old = 0;
-    if (cnt) old = atomicAdd(&count[nc], cnt);
-    old = __shfl(old, leader, 64);
+    if (want && rank == 0) old = atomicAdd(&count[nc], __popcll(mine));
+    old = __shfl(old, __ffsll((long long)mine) - 1, 64);
     return old + rank;
 }
 
@@ -811,7 +867,11 @@ __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> 
 
 // Every particle of the grid cases: straight flight with specular / open walls, new cell and
 // slot recorded.  Particles whose path may meet the body go to a worklist for k_move_body;
-// waves of mesh cases are left to k_move_mesh.
+// waves of mesh cases are left to k_move_mesh.  Cases are contiguous in the particle array
+// (the sorted live part, then the injected particles case by case), so a wave nearly always
+// lies in one case: that case's fields are then uniform (scalar loads) and its removals are
+// counted per lane and summed once per case change; a wave spanning two cases takes the
+// general path.
 template <typename P>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_move_fast(Ctx C)
 {
@@ -821,6 +881,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     const uint32_t st = (uint32_t)G->step;
     const Parts<P> S(C.buf[G->step & 1]);
     const int stride = gridDim.x * blockDim.x;
+    CaseTally tally{0, -1, 0};
+    long long removed[1] = {0};          // this lane's removals in case rcase (uniform waves)
+    int rcase = -1;
     for (int base = blockIdx.x * blockDim.x; base < n_total; base += stride) {
         const int i = base + threadIdx.x;
         const bool valid = i < n_total;       // the valid lanes of a wave are a prefix
@@ -834,25 +897,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
             for (int a = 0; a < 3; ++a) v[a] = S.vel[a][i];
         }
-        // Cases are contiguous in the particle array (the sorted live part, then the injected
-        // particles case by case), so a wave nearly always lies in the case of its first
-        // particle: that case is then found once, with uniform loads, for the whole wave.
         const int cu = case_of(C, __builtin_amdgcn_readfirstlane(g));
         const CaseDev &csu = case_const(C, cu);
         const bool one = __all(!valid || (g >= csu.cell0 && g < csu.cell0 + csu.ncells));
-        if (one && csu.mesh) continue;          // a mesh case's wave: k_move_mesh moves it
-        int nc = -1, cid = cu;
-        bool to_body = false, skip = false;
+        int nc = -1;
+        bool to_body = false, mine = false;
         if (one) {
+            if (csu.mesh) continue;           // a mesh case's wave: k_move_mesh moves it
+            mine = valid;
             if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, const_read(&G->dt_cur[cu]), nc, to_body);
-        } else if (valid) {
-            cid = case_of(C, g);
-            skip = C.cases[cid].mesh != 0;
-            if (!skip) move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
-        }
-        if (skip) {
-            nc = -1;
-            to_body = false;
+            if (cu != rcase) {
+                tally_add<1>(C, tally, rcase, HS_CNT_REMOVED, removed);
+                removed[0] = 0;
+                rcase = cu;
+            }
+            removed[0] += (valid && !to_body && nc < 0) ? 1 : 0;
+        } else {
+            int cid = cu;
+            if (valid) {
+                cid = case_of(C, g);
+                mine = C.cases[cid].mesh == 0;
+                if (mine) move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
+            }
+            wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, mine && !to_body && nc < 0);
         }
         // worklist of body candidates
         {
@@ -866,12 +933,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 if (to_body) C.work[basew + __popcll(m & ((1ull << lane) - 1ull))] = i;
             }
         }
-        const bool counted = valid && !skip && !to_body && nc >= 0;
-        if (valid && !skip && !to_body) C.newcell[i] = nc;
+        const bool counted = mine && !to_body && nc >= 0;
+        if (mine && !to_body) C.newcell[i] = nc;
         const int myslot = wave_slot(C.count, nc, counted);
         if (counted) C.slot[i] = myslot;
-        wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, valid && !skip && !to_body && nc < 0);
     }
+    tally_add<1>(C, tally, rcase, HS_CNT_REMOVED, removed);
+    tally_flush<1>(C, tally, HS_CNT_REMOVED);
 }
 
 // Every particle of the mesh cases: face-to-face tracking (move_mesh through quads, move_hex
@@ -1140,62 +1208,12 @@ __device__ __forceinline__ TileRef tile_ref(const Ctx &C, int t, int ntiles)
     return r;
 }
 
-// Counter sums of one wave by case.  Lane l holds counter base + (l & 7) of slot l >> 3
-// (eight cases at a time).  Lanes count privately; when the wave moves to a tile of another
-// case their counts are summed over the wave into that case's slot, and the flush adds each
-// slot with one atomic per lane, so no address takes an atomic per lane or per tile.
-struct CaseTally {
-    long long val;
-    int slot_case;
-    int nslot;                          // uniform over the wave
+// Per-cell record written by k_cell_scalars for the tile kernel (16 doubles per cell):
+// U[3], T, P_relax, (sigma c)_max, N_col, active, Shakhov parameters Q[3], p, RT,
+// sqrt(2RT), A_max.
+enum : int {
+    kRecU = 0, kRecT = 3, kRecPr = 4, kRecScm = 5, kRecNcol = 6, kRecAct = 7, kRecPar = 8, kRecLen = 16
 };
-
-template <int K>
-__device__ __forceinline__ void tally_flush(const Ctx &C, CaseTally &T, int base)
-{
-    const int k = threadIdx.x & 7;
-    if (T.slot_case >= 0 && k < K && T.val != 0)
-        atomicAdd((unsigned long long *)&C.g->counters[T.slot_case][base + k], (unsigned long long)T.val);
-    T.val = 0;
-    T.slot_case = -1;
-    T.nslot = 0;
-}
-
-// Adds the wave's sums of v[] to case cid (every lane of the wave calls it).
-template <int K>
-__device__ __forceinline__ void tally_add(const Ctx &C, CaseTally &T, int cid, int base, const long long (&v)[K])
-{
-    static_assert(K <= 8, "eight counters per slot");
-    long long tot[K];
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        long long x = v[j];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        tot[j] = x;
-        any = any || x != 0;
-    }
-    if (!any || cid < 0) return;
-    const int lane = threadIdx.x & 63;
-    const unsigned long long hit = __ballot(T.slot_case == cid);
-    int slot;
-    if (hit) {
-        slot = (__ffsll((long long)hit) - 1) >> 3;
-    } else {
-        if (T.nslot == 8) tally_flush<K>(C, T, base);
-        slot = T.nslot++;
-        if ((lane >> 3) == slot) T.slot_case = cid;
-    }
-    if ((lane >> 3) == slot) {
-        const int k = lane & 7;
-        long long a = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j == k) a = tot[j];
-        T.val += a;
-    }
-}
 
 // Tiles of the collision stage: a 64-thread block takes the cells whose weight
 // w(c) = cell_start[c] + 4 c falls in [t TW, (t+1) TW): at most TW/4 = 64 cells and TW + D
@@ -1246,9 +1264,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(P) ==
         const int dim = case_const(C, cur.ci).dim;
         // owner lane = local cell
         const bool own = lane < ncl;
-        const int g = cb + lane;
         int n = 0, start = 0;
         bool dense = false;
+        const int g = cb + lane;
         if (own) {
             start = C.cstart[g];
             n = C.cstart[g + 1] - start;
@@ -1297,23 +1315,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(P) ==
         team_sync<64>();
         // stable order inside each cell: a source's rank among its cell's sources is its
         // place (sources are distinct); the slots then hold sources in destination order.
-        // The cell's sources are read four at a time (aligned 16-byte LDS reads, the ends
-        // masked).
+        // The cell's sources are read four at a time (aligned 16-byte LDS reads) and all
+        // counted; the few words of the first and last row outside the cell are counted again
+        // and taken off (words past np are read, added and subtracted alike).
         static_assert(MAXP % 4 == 0, "whole 16-byte rows");
         for (int s = lane; s < np; s += 64) {
             const int lc = s_lc[s];
             const int o = c_off[lc], e = c_off[lc + 1];
             const int src = s_src[s];
+            const int u0 = o >> 2, u1 = (e + 3) >> 2;
             int rk = 0;
             const int4 *q = reinterpret_cast<const int4 *>(s_src);
-            for (int u = o >> 2; u < (e + 3) >> 2; ++u) {
+            for (int u = u0; u < u1; ++u) {
                 const int4 w = q[u];
-                const int b = u << 2;
-                rk += (b >= o && b < e && w.x < src) ? 1 : 0;
-                rk += (b + 1 >= o && b + 1 < e && w.y < src) ? 1 : 0;
-                rk += (b + 2 >= o && b + 2 < e && w.z < src) ? 1 : 0;
-                rk += (b + 3 >= o && b + 3 < e && w.w < src) ? 1 : 0;
+                rk += (int)(w.x < src) + (int)(w.y < src) + (int)(w.z < src) + (int)(w.w < src);
             }
+            for (int k = u0 << 2; k < o; ++k) rk -= (int)(s_src[k] < src);
+            for (int k = e; k < (u1 << 2); ++k) rk -= (int)(s_src[k] < src);
             s_dsrc[o + rk] = src;
         }
         team_sync<64>();
@@ -1454,13 +1472,6 @@ __device__ __forceinline__ int group_sum_iv(int x, int kb, int kbmax)
     for (int l = 4; l < kbmax; ++l) { const int y = __shfl_xor(x, 1 << l, 64); if (kb > l) x += y; }
     return x;
 }
-
-// Per-cell record written by k_cell_scalars for the tile kernel (16 doubles per cell):
-// U[3], T, P_relax, (sigma c)_max, N_col, active, Shakhov parameters Q[3], p, RT,
-// sqrt(2RT), A_max.
-enum : int {
-    kRecU = 0, kRecT = 3, kRecPr = 4, kRecScm = 5, kRecNcol = 6, kRecAct = 7, kRecPar = 8, kRecLen = 16
-};
 
 // Steps (3)-(4a) of the tiles' cells: Eq. 31 moments of the sorted velocities, Eq. 10 / 25-28
 // timescales and split, the NTC candidate count and the Shakhov parameters; one record per
@@ -2130,31 +2141,54 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         cnt[3] += rel1;
         cnt[4] += rel2;
 
-        // Eq. 19 rescale to the Step (3) U and T
-        double r1[3] = {0.0, 0.0, 0.0};
-        if (active) {
-            for (int i = sub; i < nn; i += kk) {
-                r1[0] = r1[0] + (double)s_v[0][o + i];
-                r1[1] = r1[1] + (double)s_v[1][o + i];
-                r1[2] = r1[2] + (double)s_v[2][o + i];
-            }
-        }
-        group_sum_v<3>(r1, kb, kbmax);
+        // Eq. 19 rescale to the Step (3) U and T.  FP32-mixed: one pass of FP64 sums of c and
+        // |c|^2 over the FP32 velocities (the peculiar sum as their difference, whose rounding
+        // stays far below the FP32 storage rounding); FP64: mean first, then the peculiar sum.
         double Up[3] = {0.0, 0.0, 0.0};
-        double r2[1] = {0.0};
-        if (active) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) Up[a] = r1[a] / (double)nn;
-            for (int i = sub; i < nn; i += kk) {
-                const double cx = (double)s_v[0][o + i] - Up[0], cy = (double)s_v[1][o + i] - Up[1], cz = (double)s_v[2][o + i] - Up[2];
-                r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
-            }
-        }
-        group_sum_v<1>(r2, kb, kbmax);
         double f = 0.0;
-        if (active) {
-            const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
-            f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+        if constexpr (sizeof(P) == 4) {
+            double r1[4] = {0.0, 0.0, 0.0, 0.0};
+            if (active) {
+                for (int i = sub; i < nn; i += kk) {
+                    const double x = (double)s_v[0][o + i], y = (double)s_v[1][o + i], z = (double)s_v[2][o + i];
+                    r1[0] = r1[0] + x;
+                    r1[1] = r1[1] + y;
+                    r1[2] = r1[2] + z;
+                    r1[3] = r1[3] + (x * x + y * y + z * z);
+                }
+            }
+            group_sum_v<4>(r1, kb, kbmax);
+            if (active) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Up[a] = r1[a] / (double)nn;
+                const double Tp = gas.m * (r1[3] - (r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]) / (double)nn) /
+                                  (3.0 * kKB * (double)(nn - 1));
+                f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+            }
+        } else {
+            double r1[3] = {0.0, 0.0, 0.0};
+            if (active) {
+                for (int i = sub; i < nn; i += kk) {
+                    r1[0] = r1[0] + (double)s_v[0][o + i];
+                    r1[1] = r1[1] + (double)s_v[1][o + i];
+                    r1[2] = r1[2] + (double)s_v[2][o + i];
+                }
+            }
+            group_sum_v<3>(r1, kb, kbmax);
+            double r2[1] = {0.0};
+            if (active) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Up[a] = r1[a] / (double)nn;
+                for (int i = sub; i < nn; i += kk) {
+                    const double cx = (double)s_v[0][o + i] - Up[0], cy = (double)s_v[1][o + i] - Up[1], cz = (double)s_v[2][o + i] - Up[2];
+                    r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
+                }
+            }
+            group_sum_v<1>(r2, kb, kbmax);
+            if (active) {
+                const double Tp = gas.m * r2[0] / (3.0 * kKB * (double)(nn - 1));
+                f = Tp > 0.0 ? sqrt(T / Tp) : 0.0;
+            }
         }
         // apply, write the final velocities, Step (5) sums
         const bool sampling = work && samp_on;
@@ -2183,36 +2217,46 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 }
             }
         }
-        if (__any(sums)) group_sum_v<12>(sm, kb, kbmax);
         int nrel[3] = {rel0, rel1, rel2};
         if (tracing) {
+            // the trace record keeps the group's sums of c and |c|^2 and its relaxation counts
+            double t4[4] = {sm[0], sm[1], sm[2], sm[3] + sm[4] + sm[5]};
+            group_sum_v<4>(t4, kb, kbmax);
 #pragma unroll
             for (int j = 0; j < 3; ++j) nrel[j] = group_sum_iv(nrel[j], kb, kbmax);
-        }
-        if (sampling) {
-            // one add per cell and step (no other thread touches the cell's sums), so the
-            // result equals a load-add-store; the atomic form needs no return value.  Every
-            // lane of the group holds the same sums: lane j adds sum j, so a cell's 13 adds
-            // leave in one vector instruction when the group has 16 lanes or more
-            double *A = &C.acc[13 * (size_t)g];
-            for (int j = sub; j < 13; j += kk) {
-                double v = (double)nn;
-#pragma unroll
-                for (int q = 0; q < 12; ++q)
-                    if (j == q + 1) v = sm[q];
-                unsafeAtomicAdd(&A[j], v);
-            }
-        }
-        if (lead) {
-            if (tracing) {
+            if (lead) {
                 TraceDev *tr = &C.trace[g];
-                tr->post_sum[0] = sm[0];
-                tr->post_sum[1] = sm[1];
-                tr->post_sum[2] = sm[2];
-                tr->post_sum[3] = sm[3] + sm[4] + sm[5];
+                for (int j = 0; j < 4; ++j) tr->post_sum[j] = t4[j];
                 tr->nrelax = nrel[0];
                 tr->ar_attempts = nrel[1];
                 tr->ar_cap = nrel[2];
+            }
+        }
+        if (__any(sampling)) {
+            // Step (5) sums of each cell from its group's partial sums, through LDS: every lane
+            // leaves its partial sums there, six at a time, in the velocity rows (the apply
+            // loop is done with them); lane `sub` of a group adds partial sums j = sub,
+            // sub + kk, ... over the group's lanes in lane order and sends each total to the
+            // cell's sums with one atomic add (no other thread touches the cell's sums in
+            // this step, so the result equals a load-add-store; no return value is needed)
+            static_assert(6 * 64 * sizeof(double) <= sizeof(s_v), "six rows of partial sums fit");
+            double *T6 = reinterpret_cast<double *>(&s_v[0][0]);
+            double *A = &C.acc[13 * (size_t)g];
+            const int goff = lane - sub;
+            if (sampling && sub == 0) unsafeAtomicAdd(&A[0], (double)nn);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                team_sync<64>();
+#pragma unroll
+                for (int j = 0; j < 6; ++j) T6[j * 64 + lane] = sm[6 * h + j];
+                team_sync<64>();
+                if (sampling) {
+                    for (int j = sub; j < 6; j += kk) {
+                        double tot = 0.0;
+                        for (int l = 0; l < kk; ++l) tot = tot + T6[j * 64 + goff + l];
+                        unsafeAtomicAdd(&A[1 + 6 * h + j], tot);
+                    }
+                }
             }
         }
         team_sync<64>();

@@ -366,6 +366,8 @@ void build_plan(const hs_gas *g, const hs_case *cs, int n, Plan &P)
             d.body_c[a] = c.body_c[a];
             d.in_u[a] = c.inflow.u[a];
         }
+        d.inv_n[0] = 1.0 / (double)std::max(d.n[0], 1);
+        d.inv_n[1] = 1.0 / ((double)std::max(d.n[0], 1) * (double)std::max(d.n[1], 1));
         d.body_r = c.body_r;
         d.body_T = c.body_T;
         d.F_N = c.F_N;
