@@ -25,10 +25,12 @@
  *    return data (hs_sample_moments, hs_export_state, hs_last_trace, hs_counters, hs_sync)
  *    synchronise the given stream.
  *  - Errors: every call returns an hs_status.  Argument errors return at once and
- *    change nothing.  Faults found on the device (capacity overflow, a cell denser than
- *    the per-cell limit, a non-finite moment, inconsistent state) are latched in a
- *    device error word and reported by the next synchronising call; after that the sim
- *    answers HS_ERR_STATE to everything but hs_error_string/hs_destroy.
+ *    change nothing.  Faults found on the device (capacity overflow, a non-finite
+ *    moment, inconsistent state) are latched in a device error word and reported by the
+ *    next synchronising call; after that the sim answers HS_ERR_STATE to everything but
+ *    hs_error_string/hs_destroy.  A cell may hold any number of particles up to the
+ *    case's capacity (cells above 4096 particles are worked on in device memory instead
+ *    of LDS, more slowly).
  *  - Not thread-safe: one sim, one host thread, one stream.
  *  - Randomness: Philox4x32-10 keyed by each case's seed; counters are
  *    (entity, stream, step, draw) with entities local to the case, so a case gives the
@@ -46,7 +48,7 @@ extern "C" {
 typedef enum {
     HS_OK = 0,
     HS_ERR_ARG = 1,        /* invalid argument                                        */
-    HS_ERR_CAPACITY = 2,   /* particle capacity or per-cell particle limit exceeded   */
+    HS_ERR_CAPACITY = 2,   /* particle capacity (or a static-scratch size) exceeded   */
     HS_ERR_NUMERIC = 3,    /* non-finite velocity or moment                           */
     HS_ERR_DEVICE = 4,     /* a HIP runtime call failed                               */
     HS_ERR_STATE = 5       /* the sim is in a failed state                            */

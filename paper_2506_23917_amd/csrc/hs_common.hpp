@@ -29,7 +29,6 @@ enum : uint32_t { kDrawRelax = 0, kDrawShakhov = 1, kDrawBounce = 200, kDrawInje
 // Error bits of the device error word.
 enum : uint32_t {
     kErrCapacity = 1u,      // particle capacity exceeded
-    kErrCellLimit = 2u,     // a cell holds more particles than the collide kernels take
     kErrNumeric = 4u,       // non-finite moment / velocity
     kErrState = 8u          // internal inconsistency (recomputed move disagrees)
 };
@@ -143,7 +142,7 @@ struct Ctx {
     const int32_t *hnode, *hnbr;
     Globals *g;
     int32_t n_cases, n_faces, ncells_total, cap_wave;   // cap_wave: densest cell of the tile kernel
-    int32_t cap_block, precision, tile_w, dim_max;   // dim_max: largest case dimension
+    int32_t cap_block, precision, tile_w, dim_max;   // cap_block: densest cell worked on in LDS; dim_max: largest case dimension
     int32_t n_surf_total;         // surface elements of the batch (one copy)
     int64_t capacity;             // total particle capacity of the batch
     // launch shapes (blocks per grid; 0 = the built-in default), chosen by the autotuner

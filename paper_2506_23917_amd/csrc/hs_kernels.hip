@@ -2301,24 +2301,27 @@ __device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
     }
 }
 
-// Largest cell of the block-per-cell kernel, and the size class below it (FP64): cells of up
-// to kCapBlockMid particles take 128-thread blocks, larger ones 256-thread blocks.  The FP64
-// kernel needs 256 registers a lane, so a 256-thread block fills a compute unit alone; two
-// 128-thread blocks per unit keep twice as many cells in flight.  Results do not depend on
-// the class.
-constexpr int kCapBlockMax = 2048;   // a power of two: the bitonic sort pads to one
+// Size classes of the block-per-cell kernel.  Cells of up to kCapBlockLds particles are worked
+// on in LDS: FP32 in one class of 256-thread blocks up to kCapBlockMax and one up to
+// kCapBlockLds (64 KB of LDS); FP64 in 128-thread blocks up to kCapBlockMid (the FP64 kernel
+// needs 256 registers a lane, so a 256-thread block fills a compute unit alone; two 128-thread
+// blocks per unit keep twice as many cells in flight), 256-thread blocks up to kCapBlockMax
+// and up to kCapBlockLds (112 KB of LDS).  A denser cell takes the global class: its velocities
+// stay in the new state's arrays and its claim words and sorted sources in two per-particle
+// scratch arrays the step no longer needs at that point (the move's slots and new cells),
+// so no cell of a case is too dense.  Results do not depend on the class.
+constexpr int kCapBlockMax = 2048;   // powers of two: the bitonic sort pads to one
 constexpr int kCapBlockMid = 512;
+constexpr int kCapBlockLds = 4096;
 
-// Cells denser than the tile kernel takes: one block per cell (its size class).  The stages are
-// those of k_cell_scalars and k_collide_tile with block-wide sums (every thread ends with the
-// same bits and derives the cell's scalars itself) and NTC rounds over the block.
-template <typename P, int CAPB, int NB>
+template <typename P, int CAPB, int NB, bool GLOB = false>
 __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
 {
     constexpr int KC = 2 * NB;             // NTC candidates per chunk (two per thread)
     static_assert(KC <= 1024, "candidate number fits the claim word");
-    __shared__ int32_t s_src[CAPB];            // sources during the gather, then claim words
-    __shared__ P s_v[3][CAPB];
+    constexpr int CAPL = GLOB ? 4 : CAPB;  // LDS rows (the global class keeps its cell in memory)
+    __shared__ int32_t s_src[CAPL];            // sources during the gather, then claim words
+    __shared__ P s_v[3][CAPL];
     __shared__ double s_red[(NB / 64) * 12];
     __shared__ unsigned long long s_obs, s_hash;
     __shared__ int s_nacc, s_left;
@@ -2343,33 +2346,59 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         const int n = C.cstart[g + 1] - s0;
         const int cid = case_of(C, g);
         const CaseDev &cs = C.cases[cid];
-        if (n <= nmin) continue;               // a cell of the smaller size class
-        if (n > CAPB) {
-            if (CAPB >= kCapBlockMax && tid == 0) raise_error(G, kErrCellLimit);
-            continue;                          // else: a cell of the larger size class
-        }
+        if (n <= nmin) continue;               // a cell of a smaller size class
+        if (!GLOB && n > CAPB) continue;       // a cell of a larger size class
         if (tid == 0 && cid != my_case) {
             if (my_case >= 0) flush_counts(C, my_case, cc);
             my_case = cid;
         }
+        // the cell's working velocities and claim words: LDS, or for the global class the new
+        // state's rows of the cell and the move's slot array (dead after the scatter)
+        P *sv[3];
+        uint32_t *claim;
+        int32_t *srt;                          // sources in stable order
+        if constexpr (GLOB) {
+            for (int a = 0; a < 3; ++a) sv[a] = Dd.vel[a] + s0;
+            claim = reinterpret_cast<uint32_t *>(C.slot + s0);
+            srt = C.newcell + s0;
+        } else {
+            for (int a = 0; a < 3; ++a) sv[a] = s_v[a];
+            claim = s_claim;
+            srt = s_src;
+        }
         // stable order (sort of the source indices), gather, sorted state
-        int p2 = 1;
-        while (p2 < n) p2 <<= 1;
-        for (int k = tid; k < p2; k += NB) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
+        if constexpr (GLOB) {
+            // rank of each source among the cell's (sources are distinct)
+            for (int k = tid; k < n; k += NB) {
+                const int src = use_perm ? C.perm[s0 + k] : s0 + k;
+                int rk = 0;
+                if (use_perm)
+                    for (int j = 0; j < n; ++j) rk += (int)(C.perm[s0 + j] < src);
+                else
+                    rk = k;
+                srt[rk] = src;
+            }
+        } else {
+            int p2 = 1;
+            while (p2 < n) p2 <<= 1;
+            for (int k = tid; k < p2; k += NB) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
+            __syncthreads();
+            if (use_perm) bitonic_sort<NB>(s_src, p2, tid);
+        }
         __syncthreads();
-        if (use_perm) bitonic_sort<NB>(s_src, p2, tid);
         for (int k = tid; k < n; k += NB) {
-            const int src = s_src[k];
+            const int src = srt[k];
             const size_t dst = (size_t)s0 + k;
             for (int a = 0; a < 3; ++a) if (a < cs.dim) Dd.pos[a][dst] = S.pos[a][src];
             Dd.cell[dst] = g;
             Dd.id[dst] = S.id[src];
-            s_v[0][k] = S.vel[0][src];
-            s_v[1][k] = S.vel[1][src];
-            s_v[2][k] = S.vel[2][src];
+            const P v0 = S.vel[0][src], v1 = S.vel[1][src], v2 = S.vel[2][src];
+            sv[0][k] = v0;
+            sv[1][k] = v1;
+            sv[2][k] = v2;
         }
         __syncthreads();
-        for (int k = tid; k < n; k += NB) s_claim[k] = 0u;
+        for (int k = tid; k < n; k += NB) claim[k] = 0u;
         if (tid == 0) {
             s_obs = 0ull;
             s_hash = 0ull;
@@ -2380,7 +2409,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         // Eq. 31 moments
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
         for (int k = tid; k < n; k += NB) {
-            const double x = (double)s_v[0][k], y = (double)s_v[1][k], z = (double)s_v[2][k];
+            const double x = (double)sv[0][k], y = (double)sv[1][k], z = (double)sv[2][k];
             s1[0] = s1[0] + x;
             s1[1] = s1[1] + y;
             s1[2] = s1[2] + z;
@@ -2399,9 +2428,9 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                 ud[a] = (float)(U[a] - (double)uf[a]);
             }
             for (int k = tid; k < n; k += NB) {
-                const float cx = (s_v[0][k] - uf[0]) - ud[0];
-                const float cy = (s_v[1][k] - uf[1]) - ud[1];
-                const float cz = (s_v[2][k] - uf[2]) - ud[2];
+                const float cx = (sv[0][k] - uf[0]) - ud[0];
+                const float cy = (sv[1][k] - uf[1]) - ud[1];
+                const float cz = (sv[2][k] - uf[2]) - ud[2];
                 const float c2 = cx * cx + cy * cy + cz * cz;
                 s2[0] = s2[0] + (double)c2;
                 s2[1] = s2[1] + (double)(c2 * cx);
@@ -2410,7 +2439,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
             }
         } else {
             for (int k = tid; k < n; k += NB) {
-                const double cx = s_v[0][k] - U[0], cy = s_v[1][k] - U[1], cz = s_v[2][k] - U[2];
+                const double cx = sv[0][k] - U[0], cy = sv[1][k] - U[1], cz = sv[2][k] - U[2];
                 const double c2 = cx * cx + cy * cy + cz * cz;
                 s2[0] = s2[0] + c2;
                 s2[1] = s2[1] + c2 * cx;
@@ -2540,7 +2569,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
             __syncthreads();
             for (;;) {
                 if (round == 0x3fffffu) {      // round counter exhausted: clear the claims
-                    for (int k = tid; k < n; k += NB) s_claim[k] = 0u;
+                    for (int k = tid; k < n; k += NB) claim[k] = 0u;
                     round = 0;
                     __syncthreads();
                 }
@@ -2550,8 +2579,8 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                 for (int r = 0; r < 2; ++r) {
                     tag[r] = (round << 10) | (uint32_t)(1023 - (tid + NB * r));
                     if (pend[r]) {
-                        atomicMax(&s_claim[ci[r]], tag[r]);
-                        atomicMax(&s_claim[cj[r]], tag[r]);
+                        atomicMax(&claim[ci[r]], tag[r]);
+                        atomicMax(&claim[cj[r]], tag[r]);
                     }
                 }
                 __syncthreads();
@@ -2560,10 +2589,10 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                 for (int r = 0; r < 2; ++r) {
                     if (!pend[r]) continue;
                     const int i = ci[r], j = cj[r];
-                    if (s_claim[i] != tag[r] || s_claim[j] != tag[r]) continue;
+                    if (claim[i] != tag[r] || claim[j] != tag[r]) continue;
                     pend[r] = false;
                     ++done;
-                    P *vx = s_v[0], *vy = s_v[1], *vz = s_v[2];
+                    P *vx = sv[0], *vy = sv[1], *vz = sv[2];
                     const P gx = vx[i] - vx[j], gy = vy[i] - vy[j], gz = vz[i] - vz[j];
                     const P cr = Real<P>::sq(gx * gx + gy * gy + gz * gz);
                     P sc;
@@ -2605,17 +2634,17 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         // SP-Shakhov relaxation (Eq. 16-18)
         if (pr > 0.0) {
             int nrel = 0, nar = 0, ncap = 0;
-            // decisions first (at most CAPB / NB particles per thread), then the draws
-            static_assert(CAPB / NB <= 32, "decision mask");
+            // decisions first (32 particles per thread at a time), then the draws
+            for (int k0 = tid; k0 < n; k0 += 32 * NB) {
             uint32_t mask = 0u;
-            for (int k = tid, j = 0; k < n; k += NB, ++j) {
+            for (int k = k0, j = 0; k < n && j < 32; k += NB, ++j) {
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 if (unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr) mask |= 1u << j;
             }
             while (mask) {
                 const int j = __ffs((int)mask) - 1;
                 mask &= mask - 1u;
-                const int k = tid + NB * j;
+                const int k = k0 + NB * j;
                 const int64_t id = Dd.id[(size_t)s0 + k];
                 P Cv[3];
                 int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, par, (P)(1.0 - gas.Pr), Cv);
@@ -2625,9 +2654,10 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                 }
                 ++nrel;
                 nar += used;
-                s_v[0][k] = (P)(U[0] + (double)Cv[0]);
-                s_v[1][k] = (P)(U[1] + (double)Cv[1]);
-                s_v[2][k] = (P)(U[2] + (double)Cv[2]);
+                sv[0][k] = (P)(U[0] + (double)Cv[0]);
+                sv[1][k] = (P)(U[1] + (double)Cv[1]);
+                sv[2][k] = (P)(U[2] + (double)Cv[2]);
+            }
             }
             if (nrel) atomicAdd(&s_rel[0], nrel);
             if (nar) atomicAdd(&s_rel[1], nar);
@@ -2638,15 +2668,15 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         // Eq. 19 rescale (each thread rescales the particles it summed), Step (5) sums
         double r1[3] = {0.0, 0.0, 0.0};
         for (int k = tid; k < n; k += NB) {
-            r1[0] = r1[0] + (double)s_v[0][k];
-            r1[1] = r1[1] + (double)s_v[1][k];
-            r1[2] = r1[2] + (double)s_v[2][k];
+            r1[0] = r1[0] + (double)sv[0][k];
+            r1[1] = r1[1] + (double)sv[1][k];
+            r1[2] = r1[2] + (double)sv[2][k];
         }
         team_sum<NB, 3>(r1, s_red);
         const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
         double r2[1] = {0.0};
         for (int k = tid; k < n; k += NB) {
-            const double cx = (double)s_v[0][k] - Up[0], cy = (double)s_v[1][k] - Up[1], cz = (double)s_v[2][k] - Up[2];
+            const double cx = (double)sv[0][k] - Up[0], cy = (double)sv[1][k] - Up[1], cz = (double)sv[2][k] - Up[2];
             r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
         }
         team_sum<NB, 1>(r2, s_red);
@@ -2661,7 +2691,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
 #pragma unroll
         for (int j = 0; j < 12; ++j) sm[j] = 0.0;
         for (int k = tid; k < n; k += NB) {
-            double a = (double)s_v[0][k], bb = (double)s_v[1][k], c = (double)s_v[2][k];
+            double a = (double)sv[0][k], bb = (double)sv[1][k], c = (double)sv[2][k];
             if (f > 0.0) {
                 a = U[0] + (a - Up[0]) * f;
                 bb = U[1] + (bb - Up[1]) * f;
@@ -2847,8 +2877,6 @@ __global__ void k_philox(uint64_t seed, uint32_t stream, uint64_t e0, uint32_t s
 // launchers
 // ------------------------------------------------------------------------------------
 
-constexpr int kCapBlock64 = kCapBlockMax;
-constexpr int kCapBlock32 = kCapBlockMax;
 
 static inline hipStream_t S_(void *s) { return (hipStream_t)s; }
 static inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
@@ -2953,13 +2981,19 @@ void Launch::collide(const Ctx &c, void *s)
 void Launch::dense(const Ctx &c, void *s)
 {
     const int gb = c.grid[HS_KERNEL_DENSE] > 0 ? c.grid[HS_KERNEL_DENSE] : std::max(1, std::min(c.ncells_total, 256 * 2));
+    // the two densest classes are rare: a few blocks each
+    const int gr = std::max(1, std::min(gb, 64));
     if (c.precision == HS_FP64) {
         hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMid, 128>), dim3(2 * gb), dim3(128), 0, S_(s), c, 0);
-        hipLaunchKernelGGL((k_collide_dense<double, kCapBlock64, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, kCapBlockMid);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, kCapBlockMid);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockMax);
+        hipLaunchKernelGGL((k_collide_dense<double, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockLds);
     } else {
-        // FP32 keeps one class: at 256 threads it already holds two blocks per compute unit,
-        // and 128-thread blocks measured slower
-        hipLaunchKernelGGL((k_collide_dense<float, kCapBlock32, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 0);
+        // FP32 up to kCapBlockMax in one class: at 256 threads it already holds two blocks per
+        // compute unit, and 128-thread blocks measured slower
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 0);
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockMax);
+        hipLaunchKernelGGL((k_collide_dense<float, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockLds);
     }
 }
 void Launch::finish_step(const Ctx &c, void *s)
@@ -3143,6 +3177,6 @@ int static_scratch(void **ptr, size_t *bytes)
 
 int cap_wave() { return kCapWave; }
 int tile_width() { return kTileW; }
-int cap_block(int precision) { return precision == HS_FP64 ? kCapBlock64 : kCapBlock32; }
+int cap_block(int) { return kCapBlockLds; }
 
 }  // namespace hsk

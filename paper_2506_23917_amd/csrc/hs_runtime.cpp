@@ -569,13 +569,11 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     }
     // ---- scratch of the step
     L.scratch_begin = o;
-    if (P.any_spatial) {
-        L.newcell = take(4 * cap);
-        L.slot = take(4 * cap);
-        L.perm = take(4 * cap);
-    } else {
-        L.newcell = L.slot = L.perm = 0;
-    }
+    // new cells and slots of the move; the block-per-cell kernel also uses them as scratch
+    // (claim words, sorted sources) for cells too dense for LDS, so every batch has them
+    L.newcell = take(4 * cap);
+    L.slot = take(4 * cap);
+    L.perm = P.any_spatial ? take(4 * cap) : 0;
     L.work = P.any_body ? take(4 * cap) : 0;
     L.count = take(4 * nc);
     L.cstart = take(4 * (nc + 1));
@@ -665,7 +663,6 @@ hs_status check_device(hs_sim *s)
         std::string why = "device error:";
         hs_status code = HS_ERR_STATE;
         if (G.err & kErrCapacity) { why += " particle capacity exceeded"; code = HS_ERR_CAPACITY; }
-        if (G.err & kErrCellLimit) { why += " a cell exceeds the per-cell particle limit"; code = HS_ERR_CAPACITY; }
         if (G.err & kErrNumeric) { why += " non-finite moment"; if (code == HS_ERR_STATE) code = HS_ERR_NUMERIC; }
         if (G.err & kErrState) { why += " inconsistent state"; }
         s->err = why;
@@ -807,8 +804,8 @@ hs_status create_sim(const hs_gas *gas, const hs_case *cases, int n_cases, hs_pr
         c.buf[b].cell = (int32_t *)at(s, L.cell[b]);
         c.buf[b].id = (int64_t *)at(s, L.id[b]);
     }
-    c.newcell = s->plan.any_spatial ? (int32_t *)at(s, L.newcell) : nullptr;
-    c.slot = s->plan.any_spatial ? (int32_t *)at(s, L.slot) : nullptr;
+    c.newcell = (int32_t *)at(s, L.newcell);
+    c.slot = (int32_t *)at(s, L.slot);
     c.perm = s->plan.any_spatial ? (int32_t *)at(s, L.perm) : nullptr;
     c.count = (int32_t *)at(s, L.count);
     c.cstart = (int32_t *)at(s, L.cstart);

@@ -327,26 +327,6 @@ def test_degenerate_cells_match_oracle(gas):
     assert np.array_equal(g["vel"][np.isin(g["cell"], [1, 4, 8])], v0)
 
 
-def test_cell_limit_is_reported(gas):
-    from paper_2506_23917_amd.hs import HsError
-    from oracle.oracle import Oracle
-    counts = [100, 2100, 50]
-    case = W.relax_0d(ncells=3, ppc=1000)
-    case["dt_over_tau"] = np.array([1.0, 1.0, 1.0])
-    cell = np.repeat(np.arange(3, dtype=np.int32), counts)
-    v = np.random.default_rng(1).standard_normal((len(cell), 3)) * 300.0
-    ids = np.arange(len(cell), dtype=np.int64)
-    sc = Oracle(gas, case).get_cells(0)["sigc_max"]
-    case["capacity"] = len(cell)
-    sim = _sim(gas, case, precision="fp32", no_particles=True)
-    sim.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=len(ids),
-                             step=0, sigc_max=sc))
-    sim.step(1)
-    with pytest.raises(HsError) as e:
-        sim.sync()
-    assert e.value.code == 2
-
-
 def test_bench_workload_full_size(gas):
     """The cylinder at its full size (800 x 600 cells, ~14.2M particles) in the launch
     configuration bench.py uses.  FP64: init and one step equal the oracle's (cells, ids, pair
