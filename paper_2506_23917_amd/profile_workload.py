@@ -16,6 +16,14 @@
         state is imported into an FP32-mixed sim (the first four cases of a batch), both take
         one step with the same random numbers, and the relative L2 differences of the cells'
         n, u, T, q (Eq. 31 estimators of the current particles) are printed
+    python -m paper_2506_23917_amd.profile_workload --long-accuracy --warmup 2000 --steps 2000
+        the accuracy gate on the cylinder (800 x 600): the flow developed in FP64 for `warmup`
+        steps, then from that state `steps` sampled steps each in FP32-mixed (same seed), FP64
+        (same seed) and FP64 (another seed), in ten batches; prints one JSON line with the
+        relative L2 of the time-averaged n, u, T, q against the same-seed FP64 run (FP32-mixed,
+        and the other-seed FP64 run as the noise floor), the share of cells beyond 3 standard
+        errors of a difference (from the FP64 run's batch means) and the paired one- and
+        ten-step L2 (same imported state and seed)
     python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
         a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
         counters to bytes
@@ -38,6 +46,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--accuracy", action="store_true")
+    ap.add_argument("--long-accuracy", action="store_true")
     ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere", "sod", "relax", "ogrid"])
     args = ap.parse_args()
     import torch
@@ -56,6 +65,9 @@ def main():
     from paper_2506_23917_amd.hs import Sim
     if args.accuracy:
         paired_accuracy(args)
+        return
+    if args.long_accuracy:
+        long_accuracy(args)
         return
     if args.workload == "jets":
         cases = W.jets_2d()
@@ -154,6 +166,118 @@ def paired_accuracy(args):
     out["u"] = float(np.sqrt(np.sum((u32 - u64) ** 2)) / scale)
     print("accuracy %s cases %d cells %d after %d FP64 steps: n %.3e u %.3e T %.3e q %.3e" %
           (args.workload, len(cases), int(sel.sum()), args.warmup, out["n"], out["u"], out["T"], out["q"]), flush=True)
+
+
+def _acc_moments(acc, steps, m=6.63e-26, kb=1.380649e-23):
+    """Step (6) averages over `steps` sampled steps from 13-sum arrays (cells, 13): n (up to
+    the factor F_N / V), u (3), T, q (3, up to the same factor); zero where a cell has no
+    samples."""
+    import numpy as np
+    N = acc[:, 0]
+    ok = N > 0
+    Ns = np.where(ok, N, 1.0)
+    U = acc[:, 1:4] / Ns[:, None]
+    cc = (acc[:, 4] + acc[:, 5] + acc[:, 6]) / Ns
+    uu = (U ** 2).sum(1)
+    cij = np.stack([np.stack([acc[:, 4], acc[:, 7], acc[:, 8]], 1),
+                    np.stack([acc[:, 7], acc[:, 5], acc[:, 9]], 1),
+                    np.stack([acc[:, 8], acc[:, 9], acc[:, 6]], 1)], 1) / Ns[:, None, None]
+    uc = np.einsum("kab,kb->ka", cij, U)
+    n = N / steps
+    q = 0.5 * m * n[:, None] * (acc[:, 10:13] / Ns[:, None] - 2 * uc - U * cc[:, None] + 2 * U * uu[:, None])
+    T = m / (3 * kb) * (cc - uu)
+    z = lambda x: np.where(ok if x.ndim == 1 else ok[:, None], x, 0.0)
+    return dict(n=n, u=z(U), T=z(T), q=z(q))
+
+
+def long_accuracy(args):
+    import json
+    import numpy as np
+    import workloads as W
+    from paper_2506_23917_amd.hs import Sim
+    gas = W.gas()
+    case = W.cylinder_2d()
+    s64 = Sim(gas, case, precision="fp64", device="cuda:0")
+    done = 0
+    while done < args.warmup:
+        k = min(500, args.warmup - done)
+        s64.step(k)
+        s64.sync()
+        done += k
+        print("fp64 development %d / %d" % (done, args.warmup), flush=True)
+    st0 = s64.export_state(0)
+    del s64
+    rel = lambda x, y: float(np.sqrt(np.sum((x - y) ** 2)) / max(np.sqrt(np.sum(y ** 2)), 1e-300))
+
+    def l2(a, b, sel):
+        out = {k: rel(np.asarray(a[k])[sel], np.asarray(b[k])[sel]) for k in ("n", "T", "q")}
+        u_a, u_b, T_b = np.asarray(a["u"]).reshape(-1, 3)[sel], np.asarray(b["u"]).reshape(-1, 3)[sel], np.asarray(b["T"])[sel]
+        scale = np.sqrt(np.sum(u_b ** 2) + np.sum(1.380649e-23 * np.maximum(T_b, 0.0) / gas["m"]))
+        out["u"] = float(np.sqrt(np.sum((u_a - u_b) ** 2)) / scale)
+        return out
+
+    # paired short horizons: one and ten steps from the same state and seed; beside them, an
+    # FP64 run with another seed from the same state (the noise of the current-state moments)
+    paired, paired_noise = {}, {}
+    p32 = Sim(gas, case, precision="fp32", device="cuda:0", no_particles=True)
+    p64 = Sim(gas, case, precision="fp64", device="cuda:0", no_particles=True)
+    p64b = Sim(gas, dict(case, seed=977), precision="fp64", device="cuda:0", no_particles=True)
+    for sim in (p32, p64, p64b):
+        sim.import_state(0, st0)
+    for k, nsteps in (("1", 1), ("10", 9)):
+        for sim in (p32, p64, p64b):
+            sim.step(nsteps)
+        a, b, c = p32.sample_moments(0, mode=1), p64.sample_moments(0, mode=1), p64b.sample_moments(0, mode=1)
+        paired[k] = l2(a, b, np.asarray(b["n"]) > 0)
+        paired_noise[k] = l2(c, b, np.asarray(b["n"]) > 0)
+    del p32, p64, p64b
+    print("paired", paired, "noise", paired_noise, flush=True)
+
+    nb = 10
+    per = max(1, args.steps // nb)
+    runs = {}
+    for name, prec, seed in (("fp32", "fp32", case["seed"]), ("fp64", "fp64", case["seed"]), ("fp64b", "fp64", 977)):
+        c = dict(case, seed=seed, n_steady=args.warmup)
+        sim = Sim(gas, c, precision=prec, device="cuda:0", no_particles=True)
+        sim.import_state(0, st0)
+        prev = None
+        batches = []
+        for b in range(nb):
+            sim.step(per)
+            acc = sim.export_state(0)["acc"].copy()
+            batches.append(acc - (prev if prev is not None else 0.0))
+            prev = acc
+        runs[name] = dict(final=sim.sample_moments(0, mode=0), acc=prev, batches=batches)
+        print("%s: %d sampled steps" % (name, runs[name]["final"]["n_samples"]), flush=True)
+        del sim
+    sel_all = np.asarray(runs["fp64"]["final"]["n"]) > 0
+    long_l2 = {"fp32_mixed_vs_fp64": l2(runs["fp32"]["final"], runs["fp64"]["final"], sel_all),
+               "fp64_other_seed_vs_fp64": l2(runs["fp64b"]["final"], runs["fp64"]["final"], sel_all)}
+    # 3-sigma: z of each cell's average against the same-seed FP64 run, in standard errors of a
+    # difference of two independent runs (batch means of the FP64 run); cells with at least 20
+    # particles in every batch
+    bm = [_acc_moments(b, per) for b in runs["fp64"]["batches"]]
+    nmin = np.min([b[:, 0] for b in runs["fp64"]["batches"]], axis=0)
+    base = nmin >= 20 * per
+    pooled = {k: _acc_moments(runs[k]["acc"], nb * per) for k in runs}
+    sigma = {}
+    for k in ("n", "u", "T", "q"):
+        arr = np.array([x[k] for x in bm])
+        se = arr.std(0, ddof=1) / np.sqrt(nb) * np.sqrt(2)
+        sel = (base if se.ndim == 1 else base[:, None]) & (se > 0)
+        res = {}
+        for other in ("fp32", "fp64b"):
+            z = (pooled[other][k][sel] - pooled["fp64"][k][sel]) / se[sel]
+            res[other] = {"beyond_3sigma": float((np.abs(z) > 3).mean()), "mean_z2": float((z ** 2).mean()),
+                          "values": int(z.size)}
+        sigma[k] = res
+    out = {"workload": "2-D Ma10 argon cylinder 800x600, developed %d FP64 steps, then %d sampled steps per run"
+                       % (args.warmup, nb * per),
+           "cells_compared": int(sel_all.sum()), "cells_in_3sigma_test": int(base.sum()),
+           "paired_l2": paired, "paired_l2_fp64_other_seed": paired_noise, "time_average_l2": long_l2,
+           "three_sigma": sigma,
+           "z_reference": "Student t, 9 degrees of freedom: mean z^2 = 9/7 = 1.29, P(|z| > 3) = 0.015"}
+    print("LONG_ACCURACY " + json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
