@@ -10,8 +10,9 @@ LIB = os.path.join(HERE, "libhs.so")
 SOURCES = ["hs_kernels.hip", "hs_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         # identical rounding in the move/count and collide kernels, which both evaluate
-         # the same flight; no fused multiply-add contraction anywhere
+         # no fused multiply-add contraction: the flight must round as the plain method does
+         # (cell decisions are bit-exact); only the collision stage's sums and rescale, whose
+         # rounding decides no integer, ask for contraction locally (fp contract pragmas)
          "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # no loop-invariant hoisting in the code generator: it lifts the FP64 power,

@@ -1561,6 +1561,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         // Eq. 31: sums of c and |c|^2
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+#pragma clang fp contract(fast)
             P bx[kU], by[kU], bz[kU];
             load_u(i0, bx, by, bz);
 #pragma unroll
@@ -1594,6 +1595,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                         ud[a] = (float)(U[a] - (double)uf[a]);
                     }
                     for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+#pragma clang fp contract(fast)
                         P bx[kU], by[kU], bz[kU];
                         load_u(i0, bx, by, bz);
 #pragma unroll
@@ -1612,6 +1614,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     }
                 } else {
                     for (int i0 = sub; i0 < nn; i0 += kU * kk) {
+#pragma clang fp contract(fast)
                         P bx[kU], by[kU], bz[kU];
                         load_u(i0, bx, by, bz);
 #pragma unroll
@@ -2150,6 +2153,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             double r1[4] = {0.0, 0.0, 0.0, 0.0};
             if (active) {
                 for (int i = sub; i < nn; i += kk) {
+#pragma clang fp contract(fast)
                     const double x = (double)s_v[0][o + i], y = (double)s_v[1][o + i], z = (double)s_v[2][o + i];
                     r1[0] = r1[0] + x;
                     r1[1] = r1[1] + y;
@@ -2169,6 +2173,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             double r1[3] = {0.0, 0.0, 0.0};
             if (active) {
                 for (int i = sub; i < nn; i += kk) {
+#pragma clang fp contract(fast)
                     r1[0] = r1[0] + (double)s_v[0][o + i];
                     r1[1] = r1[1] + (double)s_v[1][o + i];
                     r1[2] = r1[2] + (double)s_v[2][o + i];
@@ -2180,6 +2185,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) Up[a] = r1[a] / (double)nn;
                 for (int i = sub; i < nn; i += kk) {
+#pragma clang fp contract(fast)
                     const double cx = (double)s_v[0][o + i] - Up[0], cy = (double)s_v[1][o + i] - Up[1], cz = (double)s_v[2][o + i] - Up[2];
                     r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
                 }
@@ -2198,6 +2204,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         for (int j = 0; j < 12; ++j) sm[j] = 0.0;
         if (f > 0.0 || sums) {
             for (int i = sub; i < nn; i += kk) {
+#pragma clang fp contract(fast)
                 double a = (double)s_v[0][o + i], b = (double)s_v[1][o + i], c = (double)s_v[2][o + i];
                 if (f > 0.0) {
                     a = U[0] + (a - Up[0]) * f;
@@ -2409,6 +2416,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         // Eq. 31 moments
         double s1[4] = {0.0, 0.0, 0.0, 0.0};
         for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
             const double x = (double)sv[0][k], y = (double)sv[1][k], z = (double)sv[2][k];
             s1[0] = s1[0] + x;
             s1[1] = s1[1] + y;
@@ -2428,6 +2436,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                 ud[a] = (float)(U[a] - (double)uf[a]);
             }
             for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
                 const float cx = (sv[0][k] - uf[0]) - ud[0];
                 const float cy = (sv[1][k] - uf[1]) - ud[1];
                 const float cz = (sv[2][k] - uf[2]) - ud[2];
@@ -2439,6 +2448,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
             }
         } else {
             for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
                 const double cx = sv[0][k] - U[0], cy = sv[1][k] - U[1], cz = sv[2][k] - U[2];
                 const double c2 = cx * cx + cy * cy + cz * cz;
                 s2[0] = s2[0] + c2;
@@ -2668,6 +2678,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         // Eq. 19 rescale (each thread rescales the particles it summed), Step (5) sums
         double r1[3] = {0.0, 0.0, 0.0};
         for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
             r1[0] = r1[0] + (double)sv[0][k];
             r1[1] = r1[1] + (double)sv[1][k];
             r1[2] = r1[2] + (double)sv[2][k];
@@ -2676,6 +2687,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
         const double Up[3] = {r1[0] / (double)n, r1[1] / (double)n, r1[2] / (double)n};
         double r2[1] = {0.0};
         for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
             const double cx = (double)sv[0][k] - Up[0], cy = (double)sv[1][k] - Up[1], cz = (double)sv[2][k] - Up[2];
             r2[0] = r2[0] + (cx * cx + cy * cy + cz * cz);
         }
@@ -2691,6 +2703,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
 #pragma unroll
         for (int j = 0; j < 12; ++j) sm[j] = 0.0;
         for (int k = tid; k < n; k += NB) {
+#pragma clang fp contract(fast)
             double a = (double)sv[0][k], bb = (double)sv[1][k], c = (double)sv[2][k];
             if (f > 0.0) {
                 a = U[0] + (a - Up[0]) * f;
