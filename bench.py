@@ -145,13 +145,29 @@ def run_gpu(prec, case, gas, warmup, steps, timed_group="collide", develop=0):
                      before=develop + warmup + tune["steps"])
 
 
+def membership(st, ncells):
+    """Per cell: particle count and a wrapping 64-bit sum of hashed ids (equal in two states
+    exactly when the cell holds the same particles, up to hash collisions)."""
+    import numpy as np
+    cell = st["cell"].astype(np.int64)
+    h = st["id"].astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    cnt = np.bincount(cell, minlength=ncells)
+    starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    hs = np.zeros(ncells, np.uint64)
+    nz = cnt > 0
+    if nz.any():
+        hs[nz] = np.add.reduceat(h, starts[nz])
+    return cnt, hs
+
+
 def paired_accuracy(sim64, case, gas):
     """FP32-mixed against FP64 from the same developed state and RNG stream: one step of each,
     relative L2 over the cells of n, T and q, and of u relative to the local speed scale
-    sqrt(|u|^2 + kT/m).  Beside it, the same measure for an FP64 step from the same state
-    with another seed: the statistical noise of the current-state moments after one step (a
-    particle that FP32 rounding puts in the neighbouring cell changes that cell's pairs and
-    its q by up to this noise, so the paired figure is read against it)."""
+    sqrt(|u|^2 + kT/m).  A particle that FP32 rounding puts in the neighbouring cell changes
+    that cell's NTC pairs, so the figure is also given over the cells that hold the same
+    particles in both runs (the precision error proper) with the number of cells that do
+    not, and beside it the same measure for an FP64 step from the same state with another
+    seed (the statistical noise of the current-state moments after one step)."""
     import numpy as np
     from paper_2506_23917_amd.hs import Sim
     st = sim64.export_state(0)
@@ -162,17 +178,23 @@ def paired_accuracy(sim64, case, gas):
     s64b.import_state(0, st)
     s64b.step(1)
     sim64.step(1)
+    del st
     a, b, c = s32.sample_moments(0, mode=1), sim64.sample_moments(0, mode=1), s64b.sample_moments(0, mode=1)
-    sel = b["n"] > 0
+    nc = len(b["n"])
+    m32, m64 = membership(s32.export_state(0), nc), membership(sim64.export_state(0), nc)
+    occupied = b["n"] > 0
+    same = occupied & (m32[0] == m64[0]) & (m32[1] == m64[1])
 
-    def l2(x, y):
+    def l2(x, y, sel):
         out = {k: float(np.sqrt(np.sum((x[k][sel] - y[k][sel]) ** 2)) / max(np.sqrt(np.sum(y[k][sel] ** 2)), 1e-300))
                for k in ("n", "T", "q")}
         scale = np.sqrt(np.sum(y["u"][sel] ** 2) + np.sum(1.380649e-23 * np.maximum(y["T"][sel], 0.0) / gas["m"]))
         out["u"] = float(np.sqrt(np.sum((x["u"][sel] - y["u"][sel]) ** 2)) / scale)
         return out
 
-    out = l2(a, b), l2(c, b)
+    out = dict(all_cells=l2(a, b, occupied), same_particles=l2(a, b, same),
+               cells_with_other_particles=int(np.sum(occupied & ~same)), occupied_cells=int(np.sum(occupied)),
+               fp64_other_seed=l2(c, b, occupied))
     del s32, s64b
     return out
 
@@ -325,15 +347,18 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["dt"] / args.steps, "tile_kernel_ms": r64["tile_ms"]}
         out["mixed_speedup_vs_fp64"] = value / v64
         log("[bench] fp64: %.3f ms/step, %.3e particle-steps/s" % (1e3 * r64["dt"] / args.steps, v64))
-        acc, noise = paired_accuracy(sim64, case, gas)
-        out["accuracy"] = {"paired_one_step_rel_l2": acc, "bound": 1e-3,
-                           "fp64_other_seed_one_step_rel_l2": noise,
+        acc = paired_accuracy(sim64, case, gas)
+        out["accuracy"] = {"paired_one_step_rel_l2": acc["all_cells"], "bound": 1e-3,
+                           "paired_one_step_rel_l2_same_particles": acc["same_particles"],
+                           "cells_with_other_particles": acc["cells_with_other_particles"],
+                           "occupied_cells": acc["occupied_cells"],
+                           "fp64_other_seed_one_step_rel_l2": acc["fp64_other_seed"],
                            "state": "the FP64 run's developed cylinder state after %d steps, imported "
                                     "into an FP32-mixed sim and into an FP64 sim with another seed; one "
                                     "step of each" % (r64["before"] + args.steps),
                            "long_run": "profiles/mixed_accuracy_cylinder_long.md (2000 sampled steps: "
                                        "time averages against the other-seed noise floor, 3-sigma shares)"}
-        log("[bench] FP32-mixed vs FP64, one paired step, relative L2: %s (other-seed FP64: %s)" % (acc, noise))
+        log("[bench] FP32-mixed vs FP64, one paired step, relative L2: %s" % acc)
         base_sim, base_steps = sim64, r64["before"] + args.steps + 1
     else:
         base_sim, base_steps = sim32, r32["before"] + args.steps

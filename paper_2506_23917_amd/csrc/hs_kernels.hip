@@ -1806,17 +1806,21 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         const int lc0 = cb - cs.cell0;
         const bool samp_on = step >= cs.n_steady;
         // cell table: lane = local cell
-        int nn0 = 0, n_lane = 0;
+        int nn0 = 0, n_lane = 0, start_l = 0;
         if (lane < ncl) {
             const int g0 = cb + lane;
-            const int start = C.cstart[g0];
-            n_lane = C.cstart[g0 + 1] - start;
-            c_start[lane] = start;
+            start_l = C.cstart[g0];
+            n_lane = C.cstart[g0 + 1] - start_l;
+            c_start[lane] = start_l;
             nn0 = n_lane > D ? 0 : n_lane;
         }
         const int incl = wave_incl_scan(nn0);
         const int np = __shfl(incl, 63, 64);
         if (np == 0) continue;           // empty cells only (or dense ones, served elsewhere)
+        // without a dense cell the tile's slots are the contiguous run of the sorted state that
+        // starts at its first cell (nearly every tile); else a slot's cell is searched for
+        const bool contig = !__any(lane < ncl && n_lane > D);
+        const int base0 = __shfl(start_l, 0, 64);
         if (lane < ncl) c_off[lane] = incl - nn0;
         if (lane == 0) c_off[ncl] = np;
         team_sync<64>();
@@ -1829,13 +1833,16 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 for (int r = 0; r < R; ++r) {
                     const int s = lane + 64 * r;
                     if (s < np) {
-                        int a = 0, b = ncl - 1;
-                        while (a < b) {
-                            const int mid = (a + b + 1) >> 1;
-                            if (c_off[mid] <= s) a = mid;
-                            else b = mid - 1;
+                        uint32_t i = (uint32_t)(base0 + s);
+                        if (!contig) {
+                            int a = 0, b = ncl - 1;
+                            while (a < b) {
+                                const int mid = (a + b + 1) >> 1;
+                                if (c_off[mid] <= s) a = mid;
+                                else b = mid - 1;
+                            }
+                            i = (uint32_t)(c_start[a] + (s - c_off[a]));
                         }
-                        const uint32_t i = (uint32_t)(c_start[a] + (s - c_off[a]));
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
                             __builtin_amdgcn_global_load_lds((const void *)(Dd.vel[c] + i),
@@ -1850,13 +1857,17 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                     const int s = lane + 64 * r;
                     boff[r] = 0;
                     if (s < np) {
-                        int a = 0, b = ncl - 1;
-                        while (a < b) {
-                            const int mid = (a + b + 1) >> 1;
-                            if (c_off[mid] <= s) a = mid;
-                            else b = mid - 1;
+                        int i = base0 + s;
+                        if (!contig) {
+                            int a = 0, b = ncl - 1;
+                            while (a < b) {
+                                const int mid = (a + b + 1) >> 1;
+                                if (c_off[mid] <= s) a = mid;
+                                else b = mid - 1;
+                            }
+                            i = c_start[a] + (s - c_off[a]);
                         }
-                        boff[r] = (uint32_t)(c_start[a] + (s - c_off[a])) * (uint32_t)sizeof(P);
+                        boff[r] = (uint32_t)i * (uint32_t)sizeof(P);
                     }
                 }
                 P gv[R][3];
