@@ -9,9 +9,10 @@ time split, NTC DSMC, Shakhov resampling, conservation rescale, sampling.  Input
 resident in HBM when the timed region starts (the state never leaves the device).
 
 The roofline object is for the dominant kernel (the tile collision kernel), timed with HIP
-events on the simulation's stream inside the timed region.  Its HBM traffic comes from a
-committed rocprofv3 counter summary and is reported only while the kernel sources are the
-ones it was measured on; so does `valu_active_frac`, the share of the kernel's time its SIMDs
+events on the simulation's stream inside the timed region.  Its HBM traffic is the ratio of
+counter bytes to algorithmic bytes from a committed rocprofv3 counter summary times the
+algorithmic bytes of the timed state, reported only while the kernel sources are the ones
+it was measured on; so is `valu_active_frac`, the share of the kernel's time its SIMDs
 spend issuing vector-ALU instructions (SQ counters), which shows what bounds it instead of HBM.
 
 The FP64 run's developed state is then imported into an FP32-mixed sim and both take one step
@@ -72,17 +73,18 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic():
-    """HBM bytes per launch of the tile kernel from the committed counter summary, if it was
-    measured on the current kernel sources; else None."""
+def committed_traffic_ratio():
+    """HBM bytes over algorithmic bytes of the tile kernel from the committed counter summary,
+    if it was measured on the current kernel sources; else None.  The bench multiplies it by
+    the algorithmic bytes of the state it times, so the traffic it reports is that state's."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
+    m_r = re.search(r"hbm_traffic_over_algorithmic:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_r or m_h.group(1) != kernel_source_hash():
         return None
-    return float(m_b.group(1))
+    return float(m_r.group(1))
 
 
 def committed_valu():
@@ -301,7 +303,8 @@ def main():
     ms_step = 1e3 * r32["dt"] / args.steps
     tile_bytes = TILE_BYTES_PER_PARTICLE * npart + TILE_BYTES_PER_CELL * ncells
     achieved = tile_bytes / (r32["tile_ms"] * 1e-3) / 1e9
-    traffic = committed_traffic()
+    ratio = committed_traffic_ratio()
+    traffic = ratio * tile_bytes if ratio is not None else None
     log("[bench] fp32: %.3f ms/step, %.3e particle-steps/s, tile kernel %.3f ms" % (ms_step, value, r32["tile_ms"]))
 
     out = {

@@ -1352,7 +1352,8 @@ hs_status hs_autotune(hs_sim *s, int steps_per_trial, hs_tune_report *rep)
         {HS_KERNEL_COLLIDE, {1024, 2048, 3072, 4096, 6144, 8192}},
         {HS_KERNEL_GATHER, {2048, 4096, 8192, 16384}},
         {HS_KERNEL_SCALARS, {2048, 4096, 8192, 16384}},
-        {HS_KERNEL_DENSE, {128, 256, 512}},
+        // dense cells: a few hundred on the cylinder, tens of thousands on the O-grids
+        {HS_KERNEL_DENSE, {128, 256, 512, 1024, 2048}},
         {HS_KERNEL_MOVE, {4096, 8192, 16384, 32768}},
         {HS_KERNEL_SCATTER, {2048, 4096, 8192, 16384}},
     };

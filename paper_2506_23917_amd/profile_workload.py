@@ -10,7 +10,10 @@
         (240 x 160 x 160); `--workload sod` 256 replicas of the Sod tube (200 cells, 160 / 20
         particles per cell, graph replay); `--workload relax` the 0-D batch (4096 cells x 1000
         particles from the skewed bi-Maxwellian state); `--workload ogrid` the batch of twelve
-        Ma 5 cylinder O-grids.  Each prints particle-steps/s of the timed steps.
+        Ma 5 cylinder O-grids; `--workload sphere_hex` the Ma 10 sphere on a hexahedral shell.
+        Each prints particle-steps/s of the timed steps; with `--repeats 5` it times five
+        windows of `steps` steps one after the other and prints one JSON line with each and
+        their median; `--autotune` first picks the launch shapes on the developed flow.
     python -m paper_2506_23917_amd.profile_workload --workload sod --accuracy --warmup 40
         FP32-mixed against FP64 from the same state: the FP64 path runs `warmup` steps, its
         state is imported into an FP32-mixed sim (the first four cases of a batch), both take
@@ -47,7 +50,11 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--accuracy", action="store_true")
     ap.add_argument("--long-accuracy", action="store_true")
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "jets", "sphere", "sod", "relax", "ogrid"])
+    ap.add_argument("--workload", default="cylinder",
+                    choices=["cylinder", "jets", "sphere", "sod", "relax", "ogrid", "sphere_hex"])
+    ap.add_argument("--repeats", type=int, default=1,
+                    help="time this many windows of --steps steps; print each and their median (one JSON line)")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shapes after the warmup")
     args = ap.parse_args()
     import torch
     if args.copy_mib:
@@ -84,8 +91,8 @@ def main():
         st0 = sim.export_state(0)
         sim.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=len(ids),
                                  step=0, sigc_max=st0["sigc_max"]))
-    elif args.workload == "ogrid":
-        cases = W.ogrid_batch()
+    elif args.workload in ("ogrid", "sphere_hex"):
+        cases = W.ogrid_batch() if args.workload == "ogrid" else [W.sphere_hex()]
         for c in cases:
             c["n_steady"] = args.warmup
         sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0")
@@ -102,16 +109,32 @@ def main():
         sim.sync()
         done += k
         print("warmup %d / %d" % (done, args.warmup), flush=True)
-    n0 = sum(sim.num_particles(c) for c in range(nc))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n1 = sum(sim.num_particles(c) for c in range(nc))
-    print("timed steps %d, particles %d, %.4f ms/step, %.4e particle-steps/s" %
-          (args.steps, n1, 1e3 * dt / max(args.steps, 1), 0.5 * (n0 + n1) * args.steps / dt), flush=True)
+    if args.autotune:
+        tune = sim.autotune(steps_per_trial=10)
+        print("autotuned: %s (%d steps)" % ({k: v[0] for k, v in tune["grids"].items()}, tune["steps"]), flush=True)
+    windows = []
+    for rep in range(max(1, args.repeats)):
+        n0 = sum(sim.num_particles(c) for c in range(nc))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n1 = sum(sim.num_particles(c) for c in range(nc))
+        windows.append(dict(ms_per_step=1e3 * dt / max(args.steps, 1), particles=0.5 * (n0 + n1),
+                            particle_steps_per_s=0.5 * (n0 + n1) * args.steps / dt))
+        print("timed steps %d, particles %d, %.4f ms/step, %.4e particle-steps/s" %
+              (args.steps, n1, windows[-1]["ms_per_step"], windows[-1]["particle_steps_per_s"]), flush=True)
+    if args.repeats > 1:
+        import json
+        import statistics
+        med = statistics.median(w["particle_steps_per_s"] for w in windows)
+        print(json.dumps(dict(workload=args.workload, precision=args.precision, warmup=args.warmup, steps=args.steps,
+                              repeats=args.repeats, median_particle_steps_per_s=med,
+                              median_ms_per_step=statistics.median(w["ms_per_step"] for w in windows),
+                              particles=statistics.median(w["particles"] for w in windows), windows=windows)),
+              flush=True)
 
 
 def _cases(name, warmup):

@@ -21,16 +21,23 @@ def test_counter_summaries_are_read_only_for_the_sources_they_were_measured_on(t
     h = bench.kernel_source_hash()
     assert len(h) == 64
     good = tmp_path / "traffic.txt"
-    good.write_text("hbm_bytes_per_launch: 5.0e+08\nkernel_source_sha256: %s\n" % h)
+    good.write_text("hbm_traffic_over_algorithmic: 1.059\nkernel_source_sha256: %s\n" % h)
     stale = tmp_path / "stale.txt"
-    stale.write_text("hbm_bytes_per_launch: 5.0e+08\nkernel_source_sha256: %s\n" % ("0" * 64))
+    stale.write_text("hbm_traffic_over_algorithmic: 1.059\nkernel_source_sha256: %s\n" % ("0" * 64))
     valu = tmp_path / "valu.txt"
     valu.write_text("valu_active_frac: 0.700\nkernel_source_sha256: %s\n" % h)
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
-    assert bench.committed_traffic() == 5.0e8
+    assert bench.committed_traffic_ratio() == 1.059
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
-    assert bench.committed_traffic() is None
+    assert bench.committed_traffic_ratio() is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.committed_traffic() is None
+    assert bench.committed_traffic_ratio() is None
     monkeypatch.setattr(bench, "VALU_FILE", str(valu))
     assert bench.committed_valu() == 0.7
+
+
+def test_committed_summaries_match_the_current_sources():
+    """The committed tile-kernel counter summaries carry the hash of the kernel sources they
+    were measured on; the bench reports traffic and VALU share only while it matches."""
+    assert bench.committed_traffic_ratio() is not None
+    assert bench.committed_valu() is not None
