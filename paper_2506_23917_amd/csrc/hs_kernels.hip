@@ -1173,6 +1173,11 @@ __device__ __forceinline__ void seg_round(double (&x)[K], int head, int tail, do
 // XCD c mod 8, and its blocks sweep them in order.  The grid is a multiple of 8.
 constexpr int kXcds = 8;
 constexpr int kTileChunk = 256;
+// FP32-mixed tiles of the tile collision kernel with more cells than this send their Step (5)
+// sums in address order (see the kernel); fewer, wider groups send their own.  FP64 tiles always
+// send their own: that kernel runs two waves per SIMD and is bound by instruction issue, its
+// per-lane adds overlap with its arithmetic, and the address-order walk measured slower there.
+constexpr int kSampSpread = 16;
 
 // Eq. 26: fold a wave's smallest local step of case cid (lanes hold their own minima, +inf
 // where none) into the case's minimum for the next global step; one atomic per wave.
@@ -1919,7 +1924,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
             team_sync<64>();
             for (int j = 0; j < gsz; ++j) s_gcell[goff + j] = (uint8_t)lane;
             if (lane < ncl) {
-                c_goff[lane] = (uint8_t)goff;
+                c_goff[lane] = (uint8_t)(gsz > 0 ? goff : 0xFF);   // 0xFF: no group
                 c_gkb[lane] = (uint8_t)(gsz > 0 ? 31 - __clz(gsz) : 0);
                 c_kb[lane] = 0;
             }
@@ -2250,29 +2255,52 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                 tr->ar_cap = nrel[2];
             }
         }
-        if (__any(sampling)) {
-            // Step (5) sums of each cell from its group's partial sums, through LDS: every lane
-            // leaves its partial sums there, six at a time, in the velocity rows (the apply
-            // loop is done with them); lane `sub` of a group adds partial sums j = sub,
-            // sub + kk, ... over the group's lanes in lane order and sends each total to the
-            // cell's sums with one atomic add (no other thread touches the cell's sums in
-            // this step, so the result equals a load-add-store; no return value is needed)
-            static_assert(6 * 64 * sizeof(double) <= sizeof(s_v), "six rows of partial sums fit");
-            double *T6 = reinterpret_cast<double *>(&s_v[0][0]);
-            double *A = &C.acc[13 * (size_t)g];
+        if (samp_on) {
+            // Step (5) sums of the tile's cells.  Each lane leaves six partial sums at a time in
+            // LDS (the velocity rows: the apply loop is done with them), a group's first lane
+            // also the cell's count (row 6); lane `sub` of a group adds rows j = sub, sub + kk,
+            // ... over the group's lanes in lane order.  No other thread touches these cells'
+            // sums in this step, so each total goes out with one atomic add (equal to a
+            // load-add-store, no value returned), in one of two orders:
+            //  - few cells (wide groups): the lane sends its totals itself; the lanes of one
+            //    instruction then cover a few neighbouring cells;
+            //  - many cells in FP32-mixed (groups of one to a few lanes, where those adds
+            //    would hit a different cell in every lane): the totals go back to the group's
+            //    first slot of their rows and the wave walks the tile's block of sums (13 per
+            //    cell, consecutive cells) in address order, entries 0..6 of each cell in the
+            //    first half, 7..12 in the second.  Empty and dense cells (no group) are skipped.
+            static_assert(7 * 64 * sizeof(double) <= sizeof(s_v), "seven rows of partial sums fit");
+            double *T7 = reinterpret_cast<double *>(&s_v[0][0]);
+            double *Acc = C.acc + 13 * (size_t)cb;
             const int goff = lane - sub;
-            if (sampling && sub == 0) unsafeAtomicAdd(&A[0], (double)nn);
+            const bool spread = sizeof(P) == 4 && ncl > kSampSpread;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 team_sync<64>();
 #pragma unroll
-                for (int j = 0; j < 6; ++j) T6[j * 64 + lane] = sm[6 * h + j];
+                for (int j = 0; j < 6; ++j) T7[j * 64 + lane] = sm[6 * h + j];
+                if (h == 0 && work && sub == 0) {
+                    if (spread) T7[6 * 64 + lane] = (double)nn;
+                    else unsafeAtomicAdd(&Acc[13 * gc], (double)nn);
+                }
                 team_sync<64>();
-                if (sampling) {
-                    for (int j = sub; j < 6; j += kk) {
-                        double tot = 0.0;
-                        for (int l = 0; l < kk; ++l) tot = tot + T6[j * 64 + goff + l];
-                        unsafeAtomicAdd(&A[1 + 6 * h + j], tot);
+                // row j of a group's slots is read and rewritten by the same lane only
+                for (int j = sub; work && j < 6; j += kk) {
+                    double tot = 0.0;
+                    for (int l = 0; l < kk; ++l) tot = tot + T7[j * 64 + goff + l];
+                    if (spread) T7[j * 64 + goff] = tot;
+                    else unsafeAtomicAdd(&Acc[13 * gc + 1 + 6 * h + j], tot);
+                }
+                if (spread) {
+                    team_sync<64>();
+                    const int per = 7 - h;
+                    for (int k = lane; k < per * ncl; k += 64) {
+                        const int cl = k / per, e = k - cl * per;
+                        const int go = c_goff[cl];
+                        if (go != 0xFF) {
+                            const int row = h == 1 ? e : (e == 0 ? 6 : e - 1);
+                            unsafeAtomicAdd(&Acc[13 * cl + 7 * h + e], T7[row * 64 + go]);
+                        }
                     }
                 }
             }

@@ -11,7 +11,7 @@
         particles per cell, graph replay); `--workload relax` the 0-D batch (4096 cells x 1000
         particles from the skewed bi-Maxwellian state); `--workload ogrid` the batch of twelve
         Ma 5 cylinder O-grids; `--workload sphere_hex` the Ma 10 sphere on a hexahedral shell.
-        Each prints particle-steps/s of the timed steps; with `--repeats 5` it times five
+        Each prints particle-steps/s of the timed steps (Step 5 sampling on in them); with `--repeats 5` it times five
         windows of `steps` steps one after the other and prints one JSON line with each and
         their median; `--autotune` first picks the launch shapes on the developed flow.
     python -m paper_2506_23917_amd.profile_workload --workload sod --accuracy --warmup 40
@@ -78,6 +78,8 @@ def main():
         return
     if args.workload == "jets":
         cases = W.jets_2d()
+        for c in cases:
+            c["n_steady"] = args.warmup        # the timed steps sample (Step 5 is on)
         sim = Sim(W.gas(), cases, precision=args.precision, device="cuda:0", graph=True)
     elif args.workload == "sod":
         cases = [W.sod_1d(seed=1 + r, n_steady=0) for r in range(256)]

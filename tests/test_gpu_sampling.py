@@ -9,6 +9,9 @@ estimators of Step (3) within 1e-11 on the same scales.  Cases: the small worklo
 (tube cells above the tile kernel's limit take the block-per-cell kernel), the 0-D batch (all
 dense cells), the quadrilateral and hexahedral meshes, and the full-size cylinder after 2000
 steps of developed flow, whose stagnation cells are denser than the tile kernel takes.
+FP32-mixed: after exactly one sampled step every cell's 13 sums equal the host's sums over the
+exported particles to the FP32 storage rounding of their terms (small shapes, the full-size
+jets, whose many-cell tiles send their sums in address order, and the developed cylinder).
 """
 import numpy as np
 import pytest
@@ -177,3 +180,60 @@ def test_cylinder_developed_full_size_sampled_step(gas):
     for mode in (0, 1):
         compare_moments(sim.sample_moments(0, mode), ora.sample_moments(0, mode),
                         label="developed cylinder mode %d" % mode)
+
+
+def _state_sums(vel, cell, ncells):
+    """The 13 Step (5) sums of every cell computed on the host (FP64) from a particle state:
+    N, sum c_i, sum c_i c_j (xx, yy, zz, xy, xz, yz), sum |c|^2 c_i."""
+    v = np.asarray(vel, np.float64)
+    c2 = (v * v).sum(1)
+    cols = [np.ones(len(cell)), v[:, 0], v[:, 1], v[:, 2], v[:, 0] ** 2, v[:, 1] ** 2, v[:, 2] ** 2,
+            v[:, 0] * v[:, 1], v[:, 0] * v[:, 2], v[:, 1] * v[:, 2], c2 * v[:, 0], c2 * v[:, 1], c2 * v[:, 2]]
+    return np.stack([np.bincount(cell, weights=w, minlength=ncells) for w in cols], axis=1)
+
+
+def _fp32_one_sampled_step(gas, cases, steps):
+    """Run `steps` unsampled FP32-mixed steps and one sampled step; per case: the exported
+    state and the host sums of its velocities, with the GPU's sums checked against them.
+    The GPU adds the FP64 post-collision velocities before they are stored in FP32, so a sum
+    differs from the host's by the storage rounding of its terms: within 2e-6 of N c_rms^k
+    (k its order in c; the terms' relative rounding is at most 3 x 2^-24)."""
+    cases = [dict(c, n_steady=steps) for c in cases]
+    sim = _sim(gas, cases, precision="fp32")
+    sim.step(steps + 1)
+    out = []
+    for c, case in enumerate(cases):
+        g = sim.export_state(c)
+        assert g["n_samples"] == 1
+        nc = len(g["acc"])
+        h = _state_sums(g["vel"], g["cell"], nc)
+        ga = g["acc"]
+        assert np.array_equal(ga[:, 0], h[:, 0]), "N"
+        N = h[:, 0]
+        crms = np.sqrt((h[:, 4] + h[:, 5] + h[:, 6]) / np.maximum(N, 1.0))
+        for cols, k in (((1, 2, 3), 1), ((4, 5, 6, 7, 8, 9), 2), ((10, 11, 12), 3)):
+            scale = (N * crms ** k)[:, None] + 1e-300
+            e = np.abs(ga[:, cols] - h[:, cols]) / scale
+            assert np.all(e <= 2e-6), (c, cols, float(e.max()), np.argwhere(e > 2e-6)[:5])
+        out.append((g, N))
+    return out
+
+
+@pytest.mark.parametrize("name", ["sod", "cylinder", "jets", "sphere"])
+def test_fp32_sampled_sums_match_the_state(gas, name):
+    for g, N in _fp32_one_sampled_step(gas, small_cases()[name], 5):
+        assert N.sum() == len(g["id"]) > 0
+
+
+def test_fp32_sampled_sums_full_size_jets_and_cylinder(gas):
+    """Full-size workloads: the 32 ragged jets (a few particles per cell, so the tile kernel's
+    tiles hold far more than 16 cells and send their sums in address order) and the developed
+    800 x 600 cylinder (tens of particles per cell: wide lane groups; stagnation cells in the
+    block-per-cell kernel)."""
+    res = _fp32_one_sampled_step(gas, W.jets_2d(), 600)
+    occ = np.concatenate([N[(N > 0) & (N <= 192)] for _, N in res])
+    print("jets: %d occupied cells, mean %.2f particles" % (len(occ), occ.mean()))
+    assert occ.mean() < 8
+    (g, N), = _fp32_one_sampled_step(gas, [W.cylinder_2d()], 2000)
+    print("cylinder: %d particles, cells above 192: %d" % (len(g["id"]), (N > 192).sum()))
+    assert (N > 192).sum() > 0
