@@ -58,6 +58,11 @@ MESH_MOVE_BYTES_PER_PARTICLE = 24 + 28
 HEX_MOVE_BYTES_PER_PARTICLE = 28 + 32      # the same in 3-D: 4 + 12 + 12 read, 12 + 12 + 4 + 4 written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "collide_tile_cylinder_valu.txt")
+STEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cylinder_step_traffic.md")
+# HIP timing events go into every TIMING_PERIOD-th timed step only: each event costs the
+# stream a few microseconds, and the kernel's average is taken over launches spread evenly
+# through the timed region.
+TIMING_PERIOD = 8
 KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.hpp", "hs_common.hpp"]
 
 
@@ -73,31 +78,50 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def _committed_value(path, key):
+    """A `key: value` figure of a committed counter summary, if the summary was measured on
+    the current kernel sources (its kernel_source_sha256 line); else None."""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    m_v = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_v or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_v.group(1))
+
+
 def committed_traffic_ratio():
     """HBM bytes over algorithmic bytes of the tile kernel from the committed counter summary,
     if it was measured on the current kernel sources; else None.  The bench multiplies it by
     the algorithmic bytes of the state it times, so the traffic it reports is that state's."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    txt = open(TRAFFIC_FILE).read()
-    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    m_r = re.search(r"hbm_traffic_over_algorithmic:\s*([0-9.eE+]+)", txt)
-    if not m_h or not m_r or m_h.group(1) != kernel_source_hash():
-        return None
-    return float(m_r.group(1))
+    return _committed_value(TRAFFIC_FILE, "hbm_traffic_over_algorithmic")
 
 
 def committed_valu():
     """Share of the tile kernel's time its SIMDs spend issuing VALU instructions, from the
     committed SQ counter summary, if it was measured on the current kernel sources; else None."""
-    if not os.path.exists(VALU_FILE):
-        return None
-    txt = open(VALU_FILE).read()
-    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    m_f = re.search(r"valu_active_frac:\s*([0-9.]+)", txt)
-    if not m_h or not m_f or m_h.group(1) != kernel_source_hash():
-        return None
-    return float(m_f.group(1))
+    return _committed_value(VALU_FILE, "valu_active_frac")
+
+
+def committed_step_bytes():
+    """HBM bytes per particle-step of the whole cylinder step by the counters of every kernel
+    (the committed summary), if measured on the current kernel sources; else None."""
+    return _committed_value(STEP_TRAFFIC_FILE, "step_hbm_bytes_per_particle_step")
+
+
+def step_roofline(value):
+    """The whole step against the HBM peak: at the planned 128 B per particle-step, and at the
+    bytes every kernel of the step moves by the committed counter summary (None if that
+    summary was measured on other kernel sources)."""
+    out = {"bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
+           "achieved_GBs": STEP_BYTES_PER_PARTICLE * value / 1e9,
+           "frac": STEP_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS}
+    b = committed_step_bytes()
+    out["counter_bytes_per_particle_step"] = b
+    out["counter_achieved_GBs"] = b * value / 1e9 if b else None
+    out["counter_frac"] = b * value / 1e9 / HBM_PEAK_GBS if b else None
+    return out
 
 
 def host_cpu():
@@ -132,7 +156,7 @@ def run_gpu(prec, case, gas, warmup, steps, timed_group="collide", develop=0):
     tune = sim.autotune(steps_per_trial=10)
     nc = len(sim.cases)
     n0 = sum(sim.num_particles(c) for c in range(nc))
-    sim.set_timing([timed_group])
+    sim.set_timing([timed_group], period=TIMING_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -334,11 +358,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_collide_tile<float> (NTC, Shakhov, rescale, sampling on LDS tiles)",
                      "kernel_ms": r32["tile_ms"], "launches_timed": r32["launches"],
+                     "timing_period": TIMING_PERIOD,
                      "algorithmic_bytes_per_launch": tile_bytes,
                      "valu_active_frac": committed_valu()},
-        "step_roofline": {"bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
-                          "achieved_GBs": STEP_BYTES_PER_PARTICLE * value / 1e9,
-                          "frac": STEP_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS},
+        "step_roofline": step_roofline(value),
     }
     if not args.no_fp64:
         del sim32

@@ -272,8 +272,12 @@ int64_t hs_num_particles(hs_sim *sim, int case_id);
  * timing is on (steps then run as plain launches, not as a graph).  hs_kernel_timing
  * synchronises and returns the average duration (ms) of kernel group `which` over the
  * timed steps and their number (0 if the group was not selected); hs_clear_timing forgets
- * them. */
+ * them.  hs_set_timing_period(sim, k) records the events in every k-th step of hs_step only
+ * (counted from the last hs_clear_timing; k = 1, the default, times every step): the events
+ * cost the stream a few microseconds each, so a long timed run samples its launches evenly
+ * instead; HS_ERR_ARG for k < 1.  The autotuner times every step of its trials. */
 hs_status hs_set_timing(hs_sim *sim, uint32_t mask);
+hs_status hs_set_timing_period(hs_sim *sim, int period);
 hs_status hs_kernel_timing(hs_sim *sim, int which, double *avg_ms, int64_t *launches);
 hs_status hs_clear_timing(hs_sim *sim);
 

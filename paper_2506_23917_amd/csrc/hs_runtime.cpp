@@ -616,6 +616,7 @@ struct hs_sim {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     uint32_t timing = 0;                 // mask of timed kernel groups
+    int timing_period = 1;               // timed: every timing_period-th step of hs_step
     struct StepEvents {
         hipEvent_t b[HS_NUM_KERNELS], e[HS_NUM_KERNELS];
     };
@@ -934,7 +935,7 @@ hs_status hs_step(hs_sim *s, int64_t n)
     if (!s || n < 0) return HS_ERR_ARG;
     if (s->failed) return HS_ERR_STATE;
     if (s->timing) {
-        for (int64_t k = 0; k < n; ++k) enqueue_step(s, 1);
+        for (int64_t k = 0; k < n; ++k) enqueue_step(s, (s->timed_steps + k) % s->timing_period == 0 ? 1 : 0);
         s->timed_steps += n;
     } else if (s->flags & HS_FLAG_GRAPH) {
         if (!s->graph_ready) {
@@ -1297,6 +1298,13 @@ hs_status hs_set_timing(hs_sim *s, uint32_t mask)
 {
     if (!s || (mask >> HS_NUM_KERNELS) != 0) return HS_ERR_ARG;
     s->timing = mask;
+    return HS_OK;
+}
+
+hs_status hs_set_timing_period(hs_sim *s, int period)
+{
+    if (!s || period < 1) return HS_ERR_ARG;
+    s->timing_period = period;
     return HS_OK;
 }
 

@@ -103,6 +103,7 @@ def lib():
             "hs_num_cells": ([V, C.c_int], C.c_int64),
             "hs_num_particles": ([V, C.c_int], C.c_int64),
             "hs_set_timing": ([V, C.c_uint32], C.c_int),
+            "hs_set_timing_period": ([V, C.c_int], C.c_int),
             "hs_kernel_timing": ([V, C.c_int, P(C.c_double), P(C.c_int64)], C.c_int),
             "hs_clear_timing": ([V], C.c_int),
             "hs_autotune": ([V, C.c_int, P(HsTuneReport)], C.c_int),
@@ -126,7 +127,7 @@ def lib():
 def exported_symbols():
     return ["hs_plan", "hs_init_particles", "hs_init_particles_static", "hs_step", "hs_sync", "hs_sample_moments", "hs_state_bytes",
             "hs_export_state", "hs_import_state", "hs_last_trace", "hs_counters", "hs_num_cells",
-            "hs_num_particles", "hs_set_timing", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
+            "hs_num_particles", "hs_set_timing", "hs_set_timing_period", "hs_kernel_timing", "hs_clear_timing", "hs_autotune", "hs_set_grid",
             "hs_surface_sums", "hs_surface_sample", "hs_step_dt", "hs_dsmc_ratio", "hs_error_string", "hs_destroy",
             "hs_debug_philox"]
 
@@ -383,9 +384,9 @@ class Sim:
         self._check(self.L.hs_import_state(self.h, c, buf, len(raw)), "hs_import_state")
 
     # -- timing -------------------------------------------------------------------------
-    def set_timing(self, groups=True):
+    def set_timing(self, groups=True, period=1):
         """Time kernel groups with HIP events: True = all, False/None = off, or an iterable
-        of names from KERNELS."""
+        of names from KERNELS; with period k the events are recorded in every k-th step."""
         if groups is True:
             mask = (1 << len(KERNELS)) - 1
         elif not groups:
@@ -395,6 +396,7 @@ class Sim:
             for g in groups:
                 mask |= 1 << KERNELS[g]
         self._check(self.L.hs_set_timing(self.h, mask), "hs_set_timing")
+        self._check(self.L.hs_set_timing_period(self.h, int(period)), "hs_set_timing_period")
 
     def kernel_timing(self, which="collide"):
         ms, n = C.c_double(), C.c_int64()

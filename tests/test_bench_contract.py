@@ -37,7 +37,8 @@ def test_counter_summaries_are_read_only_for_the_sources_they_were_measured_on(t
 
 
 def test_committed_summaries_match_the_current_sources():
-    """The committed tile-kernel counter summaries carry the hash of the kernel sources they
-    were measured on; the bench reports traffic and VALU share only while it matches."""
+    """The committed counter summaries (tile kernel, whole step) carry the hash of the kernel
+    sources they were measured on; the bench reports their figures only while it matches."""
     assert bench.committed_traffic_ratio() is not None
     assert bench.committed_valu() is not None
+    assert bench.committed_step_bytes() is not None

@@ -4,7 +4,8 @@
 * batching: a case gives the same bits alone or inside a ragged batch (case-local RNG keys);
 * graph replay (HS_FLAG_GRAPH) equals eager launches, replay after replay;
 * checkpoint: export, import into a fresh sim and continue == never stopping;
-* the launch-shape autotuner changes no result;
+* the launch-shape autotuner changes no result, nor do timing events (every step or every
+  k-th);
 * FP32-mixed against FP64 from the same state: relative L2 of the cell moments n, u, T, q
   <= 1e-3 after one step (paired); over 300 sampled steps no further from FP64 than a second
   FP64 run with another seed; the FP32-mixed Sod ensemble against the exact Riemann solution;
@@ -115,6 +116,31 @@ def test_autotune_is_result_neutral(gas, prec):
     b.step(1)
     _same(a.export_state(0), b.export_state(0), prec)
 
+
+
+def test_sampled_timing_events(gas):
+    """Timing events in every k-th step only: the number of timed launches over a run, the
+    averages positive, the result unchanged, and a period below 1 rejected."""
+    from paper_2506_23917_amd.hs import HsError
+    case = _cyl()
+    a = _sim(gas, case, precision="fp32")
+    a.set_timing(["collide", "step"], period=4)
+    a.step(9)                          # steps 0, 4 and 8 of the timed run
+    ms, n = a.kernel_timing("collide")
+    assert n == 3 and ms > 0.0
+    assert a.kernel_timing("step")[1] == 3
+    a.clear_timing()
+    a.step(2)                          # counted again from the clear: step 0 only
+    assert a.kernel_timing("collide")[1] == 1
+    a.set_timing(["collide"])
+    a.step(2)
+    assert a.kernel_timing("collide")[1] == 3
+    with pytest.raises(HsError):
+        a.set_timing(["collide"], period=0)
+    a.set_timing(False)
+    b = _sim(gas, case, precision="fp32")
+    b.step(13)
+    _same(a.export_state(0), b.export_state(0), "timed")
 
 def _rel_l2(a, b):
     d = np.sqrt(np.sum((np.asarray(a) - np.asarray(b)) ** 2))
