@@ -22,6 +22,24 @@ constexpr int kMaxPosTry = 64;       // initial-position attempts in a cut cell
 constexpr int kSub = 16;             // sub-cells per axis of the cut-cell volume rule
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 
+// Size classes of the block-per-cell collide kernel (cells above the tile kernel's limit):
+// class 0 up to kCapBlockMid particles, 1 up to kCapBlockMax, 2 up to kCapBlockLds (the
+// densest worked on in LDS), 3 above.  Each class has its own list of cells, built by the
+// scan, so a launch for one class visits only its own cells.
+constexpr int kCapBlockMid = 512;
+constexpr int kCapBlockMax = 2048;   // powers of two: the bitonic sort pads to one
+constexpr int kCapBlockLds = 4096;
+constexpr int kDenseClasses = 4;
+constexpr int dense_class(int n)
+{
+    return n <= kCapBlockMid ? 0 : n <= kCapBlockMax ? 1 : n <= kCapBlockLds ? 2 : 3;
+}
+// Lower bound (exclusive) of the particles of a cell of class k, given the tile limit.
+constexpr int dense_class_floor(int k, int cap_wave)
+{
+    return k == 0 ? cap_wave : k == 1 ? kCapBlockMid : k == 2 ? kCapBlockMax : kCapBlockLds;
+}
+
 // Philox streams and per-step draw indices (shared numbering of the method's draws).
 enum : uint32_t { kStreamParticle = 0, kStreamCell = 1, kStreamFace = 2, kStreamInit = 3 };
 enum : uint32_t { kDrawRelax = 0, kDrawShakhov = 1, kDrawBounce = 200, kDrawInjectTime = 300 };
@@ -75,7 +93,7 @@ struct Globals {
     int32_t n_live;          // particles in the current buffer
     int32_t n_total;         // after injection
     int32_t n_new;           // after the sort
-    int32_t n_big;           // cells handed to the block-per-cell collide kernel
+    int32_t spare;
     uint32_t err;
     uint32_t halt;
     int32_t n_inject;        // particles injected this step
@@ -90,6 +108,7 @@ struct Globals {
     double dt_cur[kMaxCases];                // global step of the current step
     unsigned long long dt_next[kMaxCases];   // Eq. 26 minimum so far (bits of a positive double)
     double t_sampled[kMaxCases];             // sum of the global steps of the sampled steps
+    int32_t n_big[kDenseClasses];            // cells of each size class of the block-per-cell kernel
 };
 
 // Cell trace record (same field order as hs_trace).
@@ -125,7 +144,8 @@ struct Ctx {
     double *surf;                 // kSurfCopies x (7 sums per body surface element, all cases)
     int32_t *face_cnt, *face_start;
     int32_t *scan_part;
-    int32_t *big_list;
+    int32_t *big_list;            // the cells of size class k at big_off[k] .. big_off[k + 1]
+    int32_t big_off[kDenseClasses + 1];
     int32_t *tile_cell;           // first cell of each collide tile (n_tiles + 1 entries)
     int32_t *tile_case;           // case of each tile (tiles never span cases)
     int32_t *work;                // body worklist (particle indices)

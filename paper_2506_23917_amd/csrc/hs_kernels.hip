@@ -371,9 +371,34 @@ __global__ void k_init_finish(Ctx C, int64_t step0)
         G->n_live = C.cstart[C.ncells_total];
         G->n_total = G->n_live;
         G->n_new = G->n_live;
-        G->n_big = 0;
+        for (int k = 0; k < kDenseClasses; ++k) G->n_big[k] = 0;
         G->n_inject = 0;
         if (G->n_live > C.capacity) raise_error(G, kErrCapacity);
+    }
+}
+
+// Append the lanes' dense cells g (n particles, above the tile limit; `dense` false for the
+// other lanes) to the lists of their size classes: one atomic per class and wave, called by
+// every lane of the wave alike.  A class-k list holds at most capacity / (floor_k + 1) cells,
+// its reserved length.
+__device__ __forceinline__ void add_dense(const Ctx &C, int g, int n, bool dense)
+{
+    if (!__any(dense)) return;
+    const int cls = dense ? dense_class(n) : -1;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kDenseClasses; ++k) {
+        const unsigned long long m = __ballot(cls == k);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&C.g->n_big[k], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (cls == k) {
+            const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+            if (C.big_off[k] + slot < C.big_off[k + 1]) C.big_list[C.big_off[k] + slot] = g;
+            else raise_error(C.g, kErrState);
+        }
     }
 }
 
@@ -518,11 +543,8 @@ __global__ void k_scan_final(Ctx C, int build_big, int nparts)
         if (g < C.ncells_total) {
             C.cstart[g] = run;
             C.count[g] = 0;
-            if (build_big && v[k] > C.cap_wave) {
-                const int slot = atomicAdd(&C.g->n_big, 1);
-                C.big_list[slot] = g;
-            }
         }
+        if (build_big) add_dense(C, g, v[k], g < C.ncells_total && v[k] > C.cap_wave);
         run += v[k];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2347,26 +2369,24 @@ __device__ __forceinline__ void bitonic_sort(int32_t *a, int p2, int tid)
     }
 }
 
-// Size classes of the block-per-cell kernel.  Cells of up to kCapBlockLds particles are worked
-// on in LDS: FP32 in one class of 256-thread blocks up to kCapBlockMax and one up to
-// kCapBlockLds (64 KB of LDS); FP64 in 128-thread blocks up to kCapBlockMid (the FP64 kernel
-// needs 256 registers a lane, so a 256-thread block fills a compute unit alone; two 128-thread
-// blocks per unit keep twice as many cells in flight), 256-thread blocks up to kCapBlockMax
-// and up to kCapBlockLds (112 KB of LDS).  A denser cell takes the global class: its velocities
-// stay in the new state's arrays and its claim words and sorted sources in two per-particle
-// scratch arrays the step no longer needs at that point (the move's slots and new cells),
-// so no cell of a case is too dense.  Results do not depend on the class.
-constexpr int kCapBlockMax = 2048;   // powers of two: the bitonic sort pads to one
-constexpr int kCapBlockMid = 512;
-constexpr int kCapBlockLds = 4096;
+// Size classes of the block-per-cell kernel (dense_class).  Cells of up to kCapBlockLds
+// particles are worked on in LDS: FP32 in one launch of 256-thread blocks for classes 0 and 1
+// (up to kCapBlockMax) and one for class 2 (up to kCapBlockLds, 64 KB of LDS); FP64 in
+// 128-thread blocks for class 0 (the FP64 kernel needs 256 registers a lane, so a 256-thread
+// block fills a compute unit alone; two 128-thread blocks per unit keep twice as many cells in
+// flight) and 256-thread blocks for classes 1 and 2 (112 KB of LDS).  A denser cell (class 3)
+// takes the global launch: its velocities stay in the new state's arrays and its claim words
+// and sorted sources in two per-particle scratch arrays the step no longer needs at that point
+// (the move's slots and new cells), so no cell of a case is too dense.  A launch visits the
+// lists of its classes only; results do not depend on the class.
 
 template <typename P, int CAPB, int NB, bool GLOB = false>
-__global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
+__global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int cls_lo, int cls_hi)
 {
     constexpr int KC = 2 * NB;             // NTC candidates per chunk (two per thread)
     static_assert(KC <= 1024, "candidate number fits the claim word");
     constexpr int CAPL = GLOB ? 4 : CAPB;  // LDS rows (the global class keeps its cell in memory)
-    __shared__ int32_t s_src[CAPL];            // sources during the gather, then claim words
+    __shared__ __attribute__((aligned(16))) int32_t s_src[CAPL];   // sources during the gather, then claim words
     __shared__ P s_v[3][CAPL];
     __shared__ double s_red[(NB / 64) * 12];
     __shared__ unsigned long long s_obs, s_hash;
@@ -2381,19 +2401,23 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
     const Parts<P> S(C.buf[step & 1]);
     const Parts<P> Dd(C.buf[(step & 1) ^ 1]);
     const bool use_perm = C.perm != nullptr;
-    const int nbig = G->n_big;
+    // the cells of size classes cls_lo .. cls_hi (at most two), one list after the other
+    const int nlo = G->n_big[cls_lo];
+    const int nbig = nlo + (cls_hi > cls_lo ? G->n_big[cls_hi] : 0);
     const GasDev &gas = C.gas;
     const bool tracing = C.trace != nullptr;
     CellCounts cc{0, 0, 0, 0, 0, 0};
     int my_case = -1;
     for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const int g = C.big_list[b];
+        const int g = b < nlo ? C.big_list[C.big_off[cls_lo] + b] : C.big_list[C.big_off[cls_hi] + (b - nlo)];
         const int s0 = C.cstart[g];
         const int n = C.cstart[g + 1] - s0;
         const int cid = case_of(C, g);
         const CaseDev &cs = C.cases[cid];
-        if (n <= nmin) continue;               // a cell of a smaller size class
-        if (!GLOB && n > CAPB) continue;       // a cell of a larger size class
+        if (n <= C.cap_wave || (!GLOB && n > CAPB)) {   // not of this launch's classes
+            if (tid == 0) raise_error(G, kErrState);
+            continue;
+        }
         if (tid == 0 && cid != my_case) {
             if (my_case >= 0) flush_counts(C, my_case, cc);
             my_case = cid;
@@ -2424,16 +2448,46 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
                     rk = k;
                 srt[rk] = src;
             }
-        } else {
-            int p2 = 1;
+        }
+        // up to kRankMax particles: each source's rank among the cell's (sources are distinct)
+        // counted over the whole list, read four at a time (every thread the same words: LDS
+        // broadcasts), into the third velocity row, which is free until the gather; denser
+        // cells: bitonic sort in place
+        constexpr int kRankMax = CAPB < 512 ? CAPB : 512;
+        constexpr int GRK = (kRankMax + NB - 1) / NB;
+        const bool by_rank = !GLOB && use_perm && n <= kRankMax;
+        int rsrc[GRK];
+        if constexpr (!GLOB) {
+            int p2 = 4;
             while (p2 < n) p2 <<= 1;
             for (int k = tid; k < p2; k += NB) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
             __syncthreads();
-            if (use_perm) bitonic_sort<NB>(s_src, p2, tid);
+            if (by_rank) {
+                int32_t *rk_out = reinterpret_cast<int32_t *>(&s_v[2][0]);
+                const int4 *q = reinterpret_cast<const int4 *>(s_src);
+                const int u1 = (n + 3) >> 2;             // words past n hold 0x7fffffff
+                for (int k = tid; k < n; k += NB) {
+                    const int src = s_src[k];
+                    int rk = 0;
+                    for (int u = 0; u < u1; ++u) {
+                        const int4 w = q[u];
+                        rk += (int)(w.x < src) + (int)(w.y < src) + (int)(w.z < src) + (int)(w.w < src);
+                    }
+                    rk_out[rk] = src;
+                }
+                __syncthreads();
+                // every thread takes its sources before any velocity row is written
+#pragma unroll
+                for (int r = 0; r < GRK; ++r) {
+                    const int k = tid + NB * r;
+                    rsrc[r] = k < n ? rk_out[k] : 0;
+                }
+            } else if (use_perm) {
+                bitonic_sort<NB>(s_src, p2, tid);
+            }
         }
         __syncthreads();
-        for (int k = tid; k < n; k += NB) {
-            const int src = srt[k];
+        auto gather_one = [&](int k, int src) {
             const size_t dst = (size_t)s0 + k;
             for (int a = 0; a < 3; ++a) if (a < cs.dim) Dd.pos[a][dst] = S.pos[a][src];
             Dd.cell[dst] = g;
@@ -2442,6 +2496,15 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
             sv[0][k] = v0;
             sv[1][k] = v1;
             sv[2][k] = v2;
+        };
+        if (by_rank) {
+#pragma unroll
+            for (int r = 0; r < GRK; ++r) {
+                const int k = tid + NB * r;
+                if (k < n) gather_one(k, rsrc[r]);
+            }
+        } else {
+            for (int k = tid; k < n; k += NB) gather_one(k, srt[k]);
         }
         __syncthreads();
         for (int k = tid; k < n; k += NB) claim[k] = 0u;
@@ -2791,11 +2854,9 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int nmin)
 __global__ void k_build_big(Ctx C)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= C.ncells_total) return;
-    if (C.cstart[g + 1] - C.cstart[g] > C.cap_wave) {
-        const int slot = atomicAdd(&C.g->n_big, 1);
-        C.big_list[slot] = g;
-    }
+    const bool in = g < C.ncells_total;
+    const int n = in ? C.cstart[g + 1] - C.cstart[g] : 0;
+    add_dense(C, g, n, in && n > C.cap_wave);
 }
 
 __global__ void k_finish_step(Ctx C, int sorted)
@@ -2817,7 +2878,7 @@ __global__ void k_finish_step(Ctx C, int sorted)
     if (threadIdx.x == 0) {
         if (sorted) {
             G->n_live = G->n_new;
-            G->n_big = 0;      // rebuilt by the next step's scan
+            for (int k = 0; k < kDenseClasses; ++k) G->n_big[k] = 0;   // rebuilt by the next step's scan
         }
         G->n_work = 0;
         G->n_total = G->n_live;
@@ -3036,16 +3097,16 @@ void Launch::dense(const Ctx &c, void *s)
     // the two densest classes are rare: a few blocks each
     const int gr = std::max(1, std::min(gb, 64));
     if (c.precision == HS_FP64) {
-        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMid, 128>), dim3(2 * gb), dim3(128), 0, S_(s), c, 0);
-        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, kCapBlockMid);
-        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockMax);
-        hipLaunchKernelGGL((k_collide_dense<double, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockLds);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMid, 128>), dim3(2 * gb), dim3(128), 0, S_(s), c, 0, 0);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 1, 1);
+        hipLaunchKernelGGL((k_collide_dense<double, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, 2, 2);
+        hipLaunchKernelGGL((k_collide_dense<double, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, 3, 3);
     } else {
-        // FP32 up to kCapBlockMax in one class: at 256 threads it already holds two blocks per
+        // FP32 classes 0 and 1 in one launch: at 256 threads it already holds two blocks per
         // compute unit, and 128-thread blocks measured slower
-        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 0);
-        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockMax);
-        hipLaunchKernelGGL((k_collide_dense<float, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, kCapBlockLds);
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockMax, kBlock>), dim3(gb), dim3(kBlock), 0, S_(s), c, 0, 1);
+        hipLaunchKernelGGL((k_collide_dense<float, kCapBlockLds, kBlock>), dim3(gr), dim3(kBlock), 0, S_(s), c, 2, 2);
+        hipLaunchKernelGGL((k_collide_dense<float, 1, kBlock, true>), dim3(gr), dim3(kBlock), 0, S_(s), c, 3, 3);
     }
 }
 void Launch::finish_step(const Ctx &c, void *s)

@@ -59,6 +59,19 @@ struct Plan {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Length of the first k size-class lists of the dense cells: the list of class j reserves room
+// for every cell that can hold more than the class's floor of particles, at most
+// capacity / (floor + 1) of the batch's cells.
+size_t dense_list_length(int64_t capacity, size_t ncells, int k)
+{
+    size_t o = 0;
+    for (int j = 0; j < k; ++j) {
+        const int64_t most = capacity / ((int64_t)dense_class_floor(j, cap_wave()) + 1);
+        o += std::min<size_t>(ncells, (size_t)std::max<int64_t>(most, 0));
+    }
+    return o;
+}
+
 double cross2(const double *a0, const double *a1, const double *b0, const double *b1)
 {
     return (a1[0] - a0[0]) * (b1[1] - b0[1]) - (a1[1] - a0[1]) * (b1[0] - b0[0]);
@@ -580,7 +593,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
     L.facecnt = take(4 * std::max<size_t>(P.faces.size(), 1));
     L.facestart = take(4 * (P.faces.size() + 1));
     L.scanpart = take(4 * (nc / (kBlock * 16) + 2));
-    L.big = take(4 * nc);
+    L.big = take(4 * std::max<size_t>(nc, dense_list_length(P.capacity, nc, kDenseClasses)));
     L.tiles = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.tilecase = take(4 * ((cap + 4 * nc) / tile_width() + P.cases.size() + 3));
     L.cellrec = take(8 * 16 * nc);
@@ -817,6 +830,8 @@ hs_status create_sim(const hs_gas *gas, const hs_case *cases, int n_cases, hs_pr
     c.face_start = (int32_t *)at(s, L.facestart);
     c.scan_part = (int32_t *)at(s, L.scanpart);
     c.big_list = (int32_t *)at(s, L.big);
+    for (int k = 0; k <= kDenseClasses; ++k)
+        c.big_off[k] = (int32_t)dense_list_length(s->plan.capacity, s->plan.ncells, k);
     c.tile_cell = (int32_t *)at(s, L.tiles);
     c.tile_case = (int32_t *)at(s, L.tilecase);
     c.cellrec = (double *)at(s, L.cellrec);
@@ -1253,7 +1268,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     G.n_live = (int32_t)total;
     G.n_total = (int32_t)total;
     G.n_new = (int32_t)total;
-    G.n_big = 0;
+    for (int k = 0; k < kDenseClasses; ++k) G.n_big[k] = 0;
     G.n_work = 0;
     G.n_tiles = (int32_t)(((int64_t)total + 4 * s->plan.ncells + tile_width() - 1) / tile_width());
     G.next_id[c] = hd.next_id;
