@@ -2392,6 +2392,7 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int cls_lo, int cls
     __shared__ unsigned long long s_obs, s_hash;
     __shared__ int s_nacc, s_left;
     __shared__ int32_t s_rel[3];
+    __shared__ int s_rows[8];                  // runs starting in each row of 64 slots (ranking)
     uint32_t *s_claim = (uint32_t *)s_src;
     Globals *G = C.g;
     if (G->halt) return;
@@ -2450,11 +2451,16 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int cls_lo, int cls
             }
         }
         // up to kRankMax particles: each source's rank among the cell's (sources are distinct)
-        // counted over the whole list, read four at a time (every thread the same words: LDS
-        // broadcasts), into the third velocity row, which is free until the gather; denser
-        // cells: bitonic sort in place
+        // from its runs: the slots split into maximal runs of increasing sources inside one
+        // aligned block of 64 source indices (the move hands out a wave's slots of a cell as one
+        // such run).  Runs of different blocks are ordered by their block, so a source's rank is
+        // the length of the runs of lower blocks plus, in each run of its own block (its own
+        // run, rarely another), the sources below it (binary search).  Run starts and blocks go
+        // to the first two velocity rows and the sorted sources to the third, all free until
+        // the gather.  Denser cells: bitonic sort in place.
         constexpr int kRankMax = CAPB < 512 ? CAPB : 512;
         constexpr int GRK = (kRankMax + NB - 1) / NB;
+        static_assert(kRankMax / 64 <= 8, "run counts of the rows fit");
         const bool by_rank = !GLOB && use_perm && n <= kRankMax;
         int rsrc[GRK];
         if constexpr (!GLOB) {
@@ -2463,17 +2469,55 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int cls_lo, int cls
             for (int k = tid; k < p2; k += NB) s_src[k] = k < n ? (use_perm ? C.perm[s0 + k] : s0 + k) : 0x7fffffff;
             __syncthreads();
             if (by_rank) {
+                int32_t *run_at = reinterpret_cast<int32_t *>(&s_v[0][0]);
+                int32_t *run_blk = reinterpret_cast<int32_t *>(&s_v[1][0]);
                 int32_t *rk_out = reinterpret_cast<int32_t *>(&s_v[2][0]);
-                const int4 *q = reinterpret_cast<const int4 *>(s_src);
-                const int u1 = (n + 3) >> 2;             // words past n hold 0x7fffffff
-                for (int k = tid; k < n; k += NB) {
-                    const int src = s_src[k];
-                    int rk = 0;
-                    for (int u = 0; u < u1; ++u) {
-                        const int4 w = q[u];
-                        rk += (int)(w.x < src) + (int)(w.y < src) + (int)(w.z < src) + (int)(w.w < src);
+                const int lane = tid & 63, nrow = (n + 63) >> 6;
+                auto run_head = [&](int k) {
+                    if (k >= n) return false;
+                    if (k == 0) return true;
+                    const int x = s_src[k], y = s_src[k - 1];
+                    return (x >> 6) != (y >> 6) || x < y;
+                };
+                for (int r = tid >> 6; r < nrow; r += NB / 64) {
+                    const unsigned long long m = __ballot(run_head(64 * r + lane));
+                    if (lane == 0) s_rows[r] = __popcll(m);
+                }
+                __syncthreads();
+                int nrun = 0;
+                for (int r = 0; r < nrow; ++r) nrun += s_rows[r];
+                for (int r = tid >> 6; r < nrow; r += NB / 64) {
+                    int before = 0;
+                    for (int q = 0; q < r; ++q) before += s_rows[q];
+                    const int k = 64 * r + lane;
+                    const bool h = run_head(k);
+                    const unsigned long long m = __ballot(h);
+                    if (h) {
+                        const int j = before + __popcll(m & ((1ull << lane) - 1ull));
+                        run_at[j] = k;
+                        run_blk[j] = s_src[k] >> 6;
                     }
-                    rk_out[rk] = src;
+                }
+                if (tid == 0) run_at[nrun] = n;
+                __syncthreads();
+                for (int k = tid; k < n; k += NB) {
+                    const int x = s_src[k], bx = x >> 6;
+                    int rk = 0;
+                    for (int j = 0; j < nrun; ++j) {
+                        const int bj = run_blk[j], a = run_at[j], e = run_at[j + 1];
+                        if (bj < bx) {
+                            rk += e - a;
+                        } else if (bj == bx) {
+                            int lo = a, hi = e;            // first source of the run not below x
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (s_src[mid] < x) lo = mid + 1;
+                                else hi = mid;
+                            }
+                            rk += lo - a;
+                        }
+                    }
+                    rk_out[rk] = x;
                 }
                 __syncthreads();
                 // every thread takes its sources before any velocity row is written
