@@ -27,6 +27,10 @@
         and the other-seed FP64 run as the noise floor), the share of cells beyond 3 standard
         errors of a difference (from the FP64 run's batch means) and the paired one- and
         ten-step L2 (same imported state and seed)
+    python -m paper_2506_23917_amd.profile_workload --dense-census --warmup 2000 --steps 200
+        the cylinder's cells above the tile kernel's limit: particles-per-cell histogram after
+        `warmup` steps, then the block-per-cell kernels' time (side stream) and the step's, by
+        HIP events over `steps` steps after the autotuner
     python -m paper_2506_23917_amd.profile_workload --copy-mib 1024
         a plain device-to-device copy of a known size, to scale the FETCH_SIZE / WRITE_SIZE
         counters to bytes
@@ -55,6 +59,8 @@ def main():
     ap.add_argument("--repeats", type=int, default=1,
                     help="time this many windows of --steps steps; print each and their median (one JSON line)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shapes after the warmup")
+    ap.add_argument("--dense-census", action="store_true",
+                    help="cylinder: particles-per-cell histogram and the block-per-cell kernel's share and time")
     args = ap.parse_args()
     import torch
     if args.copy_mib:
@@ -75,6 +81,9 @@ def main():
         return
     if args.long_accuracy:
         long_accuracy(args)
+        return
+    if args.dense_census:
+        dense_census(args)
         return
     if args.workload == "jets":
         cases = W.jets_2d()
@@ -137,6 +146,43 @@ def main():
                               median_ms_per_step=statistics.median(w["ms_per_step"] for w in windows),
                               particles=statistics.median(w["particles"] for w in windows), windows=windows)),
               flush=True)
+
+
+def dense_census(args):
+    """The developed cylinder after `warmup` steps: histogram of particles per cell, the cells
+    above the tile kernel's limit (192) and their particles, then `steps` steps with the launch
+    shapes the autotuner picks and HIP events around the block-per-cell kernels (on the side
+    stream) and around the whole step; one JSON line."""
+    import json
+    import numpy as np
+    import workloads as W
+    from paper_2506_23917_amd.hs import Sim
+    case = W.cylinder_2d()
+    case["n_steady"] = args.warmup
+    sim = Sim(W.gas(), case, precision=args.precision, device="cuda:0")
+    done = 0
+    while done < args.warmup:
+        k = min(500, args.warmup - done)
+        sim.step(k)
+        sim.sync()
+        done += k
+    st = sim.export_state(0)
+    cnt = np.bincount(st["cell"], minlength=case["nx"] * case["ny"])
+    edges = [(0, 0), (1, 9), (10, 19), (20, 39), (40, 63), (64, 127), (128, 192), (193, 512), (513, 1024),
+             (1025, 2048), (2049, 4096), (4097, 1 << 30)]
+    hist = [dict(lo=a, hi=b, cells=int(((cnt >= a) & (cnt <= b)).sum()), particles=int(cnt[(cnt >= a) & (cnt <= b)].sum()))
+            for a, b in edges]
+    dense = cnt > 192
+    tune = sim.autotune(steps_per_trial=10)
+    sim.set_timing(["dense", "step"])
+    sim.clear_timing()
+    sim.step(args.steps)
+    sim.sync()
+    print(json.dumps(dict(workload="cylinder", precision=args.precision, step=int(st["step"]), particles=int(cnt.sum()),
+                          cells=int(cnt.size), dense_cells=int(dense.sum()), dense_particles=int(cnt[dense].sum()),
+                          densest=int(cnt.max()), histogram=hist, launch_grids={k: v[0] for k, v in tune["grids"].items()},
+                          timed_steps=args.steps, dense_ms=sim.kernel_timing("dense")[0],
+                          step_ms=sim.kernel_timing("step")[0])), flush=True)
 
 
 def _cases(name, warmup):
