@@ -246,8 +246,11 @@ hs_status hs_sample_moments(hs_sim *sim, int case_id, int mode, double *n, doubl
  * the cell-relative position in [0,1) per axis; on a mesh, the position relative to the
  * cell's first node, in m), cell[np] (int32, case-local),
  * id[np] (int64), sigc_max[ncells], acc[ncells][13] (double).  Particles are sorted by
- * cell.  hs_state_bytes gives the size.  Importing requires cells non-decreasing; it sets
- * the sim's step counter (shared by all cases). */
+ * cell.  hs_state_bytes gives the size.  Importing requires cells non-decreasing and every
+ * id in [next_id - 2^32 + 1, next_id) (the device keeps an id's low 32 bits and restores it
+ * from the case's next id, so a live particle's id is one of its case's last 2^32 ids; a
+ * particle that stayed while 2^32 later particles entered its case would lose its id);
+ * it sets the sim's step counter (shared by all cases); HS_ERR_ARG otherwise. */
 typedef struct {
     uint32_t magic, version, precision, dim;
     int64_t np, ncells, next_id, step, n_samples;

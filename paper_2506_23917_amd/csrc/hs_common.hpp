@@ -121,12 +121,20 @@ struct TraceDev {
 };
 static_assert(sizeof(TraceDev) == sizeof(hs_trace), "trace layout");
 
+// Particle state.  A particle's id is kept as its low 32 bits: every live id of a case is one
+// of the case's last 2^32 ids (below its next id), so the full id is the largest value below
+// the case's next id with those bits (full_id).
 struct PartBuf {
     void *pos[3];
     void *vel[3];
     int32_t *cell;
-    int64_t *id;
+    uint32_t *id;
 };
+
+constexpr int64_t full_id(uint32_t low, int64_t next_id)
+{
+    return next_id - (int64_t)(uint32_t)((uint32_t)next_id - low);
+}
 
 // Everything a kernel needs, passed by value.
 struct Ctx {

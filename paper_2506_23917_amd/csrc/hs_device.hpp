@@ -10,6 +10,14 @@
 
 namespace hsk {
 
+// Where a particle's id is loaded from when first needed: its stored low 32 bits and the
+// case's next id (full_id).
+struct IdSrc {
+    const uint32_t *low;
+    int64_t next;
+    __device__ int64_t get() const { return full_id(*low, next); }
+};
+
 constexpr double kKB = 1.380649e-23;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -306,7 +314,7 @@ struct MoveStats {
 // xr in [0,1)^dim, velocity v): body reflections in FP64 on absolute coordinates, plain
 // flight in cell units in the storage precision, specular walls by mirroring, removal
 // through open faces.  Returns the new case-local cell or -1.
-// `id` is the particle id, or -1 to load it from *idsrc on the first body reflection.
+// `id` is the particle id, or -1 to load it from idsrc on the first body reflection.
 // Step (5) on the wall: the momentum dP = m F_N (c_in - c_out) and the energy
 // dE = m F_N (|c_in|^2 - |c_out|^2) / 2 one diffuse reflection gives the body, added to the
 // surface element of the hit point X.  Elements are bands of the polar angle th from the
@@ -350,7 +358,7 @@ __device__ inline void surface_hit(const GasDev &gas, const CaseDev &cs, const d
 
 template <typename P>
 __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int local, P xr[3], P v[3],
-                                    int64_t &id, const int64_t *idsrc, double t, bool full_step,
+                                    int64_t &id, IdSrc idsrc, double t, bool full_step,
                                     uint32_t step, MoveStats &ms, double *surf)
 {
     const int dim = cs.dim;
@@ -373,7 +381,7 @@ __device__ inline int move_particle(const GasDev &gas, const CaseDev &cs, int lo
                 t = 0.0;
                 break;
             }
-            if (id < 0) id = *idsrc;
+            if (id < 0) id = idsrc.get();
             const double Vin[3] = {V[0], V[1], V[2]};
             diffuse_reflect(gas, cs, X, draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + b), V);
             if (surf) surface_hit(gas, cs, X, Vin, V, surf);
@@ -556,7 +564,7 @@ __device__ __forceinline__ double bilinear(const double P[4][2], double u, doubl
 // together are the caps (the particle then stops where it is), so the loop always ends.  Returns the new global cell, or -1.
 template <typename P>
 __device__ inline int move_mesh(const Ctx &C, const CaseDev &cs, int g, P xr[3], P v[3], int64_t &id,
-                                const int64_t *idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
+                                IdSrc idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
 {
     double Pn[4][2];
     mesh_nodes(C, g, Pn);
@@ -607,7 +615,7 @@ __device__ inline int move_mesh(const Ctx &C, const CaseDev &cs, int g, P xr[3],
         }
         ms.hits++;
         if (bounce == kMaxBounce) { ms.capped++; break; }
-        if (id < 0) id = *idsrc;
+        if (id < 0) id = idsrc.get();
         const W4 w = draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + bounce);
         ++bounce;
         const double Vin[3] = {V[0], V[1], V[2]};
@@ -658,7 +666,7 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3])
 // or -1.
 template <typename P>
 __device__ inline int move_hex(const Ctx &C, const CaseDev &cs, int g, P xr[3], P v[3], int64_t &id,
-                               const int64_t *idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
+                               IdSrc idsrc, double t, uint32_t step, MoveStats &ms, double *surf)
 {
     double Pn[8][3];
     hex_nodes(C, g, Pn);
@@ -708,7 +716,7 @@ __device__ inline int move_hex(const Ctx &C, const CaseDev &cs, int g, P xr[3], 
         }
         ms.hits++;
         if (bounce == kMaxBounce) { ms.capped++; break; }
-        if (id < 0) id = *idsrc;
+        if (id < 0) id = idsrc.get();
         const W4 w = draw(cs, kStreamParticle, (uint64_t)id, step, kDrawBounce + bounce);
         ++bounce;
         const double Vin[3] = {V[0], V[1], V[2]};

@@ -137,7 +137,7 @@ struct Parts {
     P *pos[3];
     P *vel[3];
     int32_t *cell;
-    int64_t *id;
+    uint32_t *id;             // low 32 bits of the ids (full_id)
     __device__ explicit Parts(const PartBuf &b)
     {
         for (int a = 0; a < 3; ++a) {
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64) void k_init_fill(Ctx C)
             B.vel[d][i] = (P)(st->u[d] + C3[d]);
         }
         B.cell[i] = g;
-        B.id[i] = id0 + q;
+        B.id[i] = (uint32_t)(id0 + q);
     }
 }
 
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(kBlock) void k_inject_fill(Ctx C)
                 S.vel[a][i] = (P)(n[a] * z / beta + t1[a] * v1 + t2[a] * v2);
             }
             S.cell[i] = fd.cell;
-            S.id[i] = id0 + q;
+            S.id[i] = (uint32_t)(id0 + q);
         }
     } else if (cs.mesh) {
         // a mesh edge: inward normal n = (-e_y, e_x) / |e|, in-plane tangent t = (-n_y, n_x)
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void k_inject_fill(Ctx C)
             S.vel[1][i] = (P)(ny * z / beta + ty * vt);
             S.vel[2][i] = (P)vz;
             S.cell[i] = fd.cell;
-            S.id[i] = id0 + q;
+            S.id[i] = (uint32_t)(id0 + q);
         }
     } else
     for (int q = lane; q < cnt; q += 64) {
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_inject_fill(Ctx C)
             S.vel[d][i] = (P)v[d];
         }
         S.cell[i] = fd.cell;
-        S.id[i] = id0 + q;
+        S.id[i] = (uint32_t)(id0 + q);
     }
     if (capped) atomicAdd((unsigned long long *)&C.g->counters[fd.case_id][HS_CNT_INJECT_CAP], (unsigned long long)capped);
 }
@@ -866,7 +866,8 @@ __device__ __forceinline__ int wave_slot(int32_t *count, int nc, bool want)
 // (-1: left the domain); to_body when the path may meet the body.
 template <typename P>
 __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> &S, int i, int g, P (&xr)[3],
-                                              P (&v)[3], uint32_t st, int n_live, double dt, int &nc, bool &to_body)
+                                              P (&v)[3], uint32_t st, int n_live, double dt, const int64_t *next_id,
+                                              int &nc, bool &to_body)
 {
     if (cs.dim == 0) {
         nc = g;
@@ -874,7 +875,7 @@ __device__ __forceinline__ void move_fast_one(const CaseDev &cs, const Parts<P> 
     }
     const bool full = i < n_live;
     double t = dt;
-    if (!full) t = dt * unid(draw(cs, kStreamParticle, (uint64_t)S.id[i], st, kDrawInjectTime).x);
+    if (!full) t = dt * unid(draw(cs, kStreamParticle, (uint64_t)full_id(S.id[i], *next_id), st, kDrawInjectTime).x);
     bool vchg = false;
     const int nl = flight<P>(cs, g - cs.cell0, xr, v, t, full, vchg);
     if (nl == -2) {
@@ -927,7 +928,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         if (one) {
             if (csu.mesh) continue;           // a mesh case's wave: k_move_mesh moves it
             mine = valid;
-            if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, const_read(&G->dt_cur[cu]), nc, to_body);
+            if (valid) move_fast_one<P>(csu, S, i, g, xr, v, st, n_live, const_read(&G->dt_cur[cu]), &G->next_id[cu], nc, to_body);
             if (cu != rcase) {
                 tally_add<1>(C, tally, rcase, HS_CNT_REMOVED, removed);
                 removed[0] = 0;
@@ -939,7 +940,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             if (valid) {
                 cid = case_of(C, g);
                 mine = C.cases[cid].mesh == 0;
-                if (mine) move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], nc, to_body);
+                if (mine) move_fast_one<P>(C.cases[cid], S, i, g, xr, v, st, n_live, G->dt_cur[cid], &G->next_id[cid], nc, to_body);
             }
             wave_add(&G->counters[0][0], HS_NUM_COUNTERS, cid, HS_CNT_REMOVED, 1, mine && !to_body && nc < 0);
         }
@@ -996,17 +997,18 @@ __global__ __launch_bounds__(kBlock) void k_move_mesh(Ctx C)
             int64_t id = -1;
             const double dt = G->dt_cur[cid];
             double t = dt;
+            const IdSrc ids{&S.id[i], G->next_id[cid]};
             if (!full) {
-                id = S.id[i];
+                id = ids.get();
                 t = dt * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
             }
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
                                ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
             if (cs.dim == 3) {
                 xr[2] = S.pos[2][i];
-                nc = move_hex<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+                nc = move_hex<P>(C, cs, g, xr, v, id, ids, t, st, ms, surf);
             } else {
-                nc = move_mesh<P>(C, cs, g, xr, v, id, &S.id[i], t, st, ms, surf);
+                nc = move_mesh<P>(C, cs, g, xr, v, id, ids, t, st, ms, surf);
             }
             if (nc >= 0) {
                 S.pos[0][i] = xr[0];
@@ -1051,8 +1053,9 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
             int64_t id = -1;
             const double dt = G->dt_cur[cid];
             double t = dt;
+            const IdSrc ids{&S.id[i], G->next_id[cid]};
             if (!full) {
-                id = S.id[i];
+                id = ids.get();
                 t = dt * unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawInjectTime).x);
             }
             // wall sums of the body (Step (5) on the surface) in sampled steps
@@ -1060,7 +1063,7 @@ __global__ __launch_bounds__(kBlock) void k_move_body(Ctx C)
             const int copy = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kSurfCopies);
             double *surf = (cs.n_surf > 0 && G->step >= cs.n_steady)
                                ? C.surf + 7 * (size_t)copy * (size_t)C.n_surf_total : nullptr;
-            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, &S.id[i], t, full, st, ms, surf);
+            const int nl = move_particle<P>(C.gas, cs, g - cs.cell0, xr, v, id, ids, t, full, st, ms, surf);
             if (nl >= 0) {
                 nc = cs.cell0 + nl;
                 for (int a = 0; a < 3; ++a) if (a < cs.dim) S.pos[a][i] = xr[a];
@@ -1369,7 +1372,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(P) ==
 #pragma unroll
         for (int r0 = 0; r0 < R; r0 += RG) {
             P gv[RG][3], gp[RG][3];
-            int64_t gid[RG];
+            uint32_t gid[RG];
 #pragma unroll
             for (int q = 0; q < RG; ++q) {
                 const int d = lane + 64 * (r0 + q);
@@ -1377,7 +1380,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(P) ==
                     const uint32_t src = (uint32_t)s_dsrc[d];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) gv[q][c] = ld_off(S.vel[c], src * (uint32_t)sizeof(P));
-                    gid[q] = ld_off(S.id, src * 8u);
+                    gid[q] = ld_off(S.id, src * 4u);
 #pragma unroll
                     for (int a2 = 0; a2 < 3; ++a2)
                         gp[q][a2] = a2 < dim ? ld_off(S.pos[a2], src * (uint32_t)sizeof(P)) : (P)0;
@@ -2139,7 +2142,8 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
         // busiest lane has relaxing particles.
         int rel0 = 0, rel1 = 0, rel2 = 0;
         if (pr > 0.0) {
-            const int64_t *ids = Dd.id + c_start[gc];
+            const uint32_t *ids = Dd.id + c_start[gc];
+            const int64_t nid = G->next_id[cid];
 #pragma unroll 1
             for (int base = sub; base < nn; base += 64 * kk) {
                 const int lim = min(nn, base + 64 * kk);
@@ -2150,7 +2154,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int i = i0 + u * kk;
-                        idv[u] = i < lim ? ids[i] : 0;
+                        idv[u] = i < lim ? full_id(ids[i], nid) : 0;
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -2163,7 +2167,7 @@ __device__ __forceinline__ void collide_tile_body(const Ctx &C)
                     const int bit = __ffsll((long long)mask) - 1;
                     mask &= mask - 1ull;
                     const int i = base + bit * kk;
-                    const int64_t id = ids[i];
+                    const int64_t id = full_id(ids[i], nid);
                     P Cv[3];
                     int used = shakhov_draw<P>(sd0, sd1, id, st, par, (P)(1.0 - gas.Pr), Cv);
                     if (used < 0) {
@@ -2794,14 +2798,14 @@ __global__ __launch_bounds__(NB) void k_collide_dense(Ctx C, int cls_lo, int cls
             for (int k0 = tid; k0 < n; k0 += 32 * NB) {
             uint32_t mask = 0u;
             for (int k = k0, j = 0; k < n && j < 32; k += NB, ++j) {
-                const int64_t id = Dd.id[(size_t)s0 + k];
+                const int64_t id = full_id(Dd.id[(size_t)s0 + k], G->next_id[cid]);
                 if (unid(draw(cs, kStreamParticle, (uint64_t)id, st, kDrawRelax).x) < pr) mask |= 1u << j;
             }
             while (mask) {
                 const int j = __ffs((int)mask) - 1;
                 mask &= mask - 1u;
                 const int k = k0 + NB * j;
-                const int64_t id = Dd.id[(size_t)s0 + k];
+                const int64_t id = full_id(Dd.id[(size_t)s0 + k], G->next_id[cid]);
                 P Cv[3];
                 int used = shakhov_draw<P>(cs.seed_lo, cs.seed_hi, id, st, par, (P)(1.0 - gas.Pr), Cv);
                 if (used < 0) {

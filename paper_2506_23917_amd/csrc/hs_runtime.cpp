@@ -559,7 +559,7 @@ Layout make_layout(const Plan &P, hs_precision prec, uint32_t flags)
         for (int a = 0; a < 3; ++a) L.pos[b][a] = a < P.dim_max ? take(es * cap) : 0;
         for (int a = 0; a < 3; ++a) L.vel[b][a] = take(es * cap);
         L.cell[b] = take(4 * cap);
-        L.id[b] = take(8 * cap);
+        L.id[b] = take(4 * cap);
     }
     L.sigc = take(8 * nc);
     L.acc = take(8 * 13 * nc);
@@ -816,7 +816,7 @@ hs_status create_sim(const hs_gas *gas, const hs_case *cases, int n_cases, hs_pr
             c.buf[b].vel[a] = at(s, L.vel[b][a]);
         }
         c.buf[b].cell = (int32_t *)at(s, L.cell[b]);
-        c.buf[b].id = (int64_t *)at(s, L.id[b]);
+        c.buf[b].id = (uint32_t *)at(s, L.id[b]);
     }
     c.newcell = (int32_t *)at(s, L.newcell);
     c.slot = (int32_t *)at(s, L.slot);
@@ -1145,7 +1145,13 @@ hs_status hs_export_state(hs_sim *s, int c, void *host_buf, size_t bytes)
     if (np) HIPCHK(s, hipMemcpy(p, B.cell + a, 4 * np, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < np; ++i) cellp[i] -= cs.cell0;
     p += 4 * np;
-    if (np) HIPCHK(s, hipMemcpy(p, B.id + a, 8 * np, hipMemcpyDeviceToHost));
+    {
+        // ids are kept as their low 32 bits (full_id)
+        std::vector<uint32_t> low(np);
+        if (np) HIPCHK(s, hipMemcpy(low.data(), B.id + a, 4 * np, hipMemcpyDeviceToHost));
+        int64_t *idp = (int64_t *)p;
+        for (size_t i = 0; i < np; ++i) idp[i] = full_id(low[i], hd.next_id);
+    }
     p += 8 * np;
     HIPCHK(s, hipMemcpy(p, s->ctx.sigc + cs.cell0, 8 * nc, hipMemcpyDeviceToHost));
     p += 8 * nc;
@@ -1186,6 +1192,12 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
             s->err = "imported cells must be in range and non-decreasing";
             return HS_ERR_ARG;
         }
+        // the state keeps ids as their low 32 bits: every id must be one of the case's last
+        // 2^32 ids below its next id
+        if (ids[i] < 0 || ids[i] >= hd.next_id || hd.next_id - ids[i] >= (int64_t)1 << 32) {
+            s->err = "imported ids must lie in [next_id - 2^32 + 1, next_id)";
+            return HS_ERR_ARG;
+        }
         for (int d = 0; d < 3; ++d) {
             if (!std::isfinite(rd(vel + d * es * np, i))) { s->err = "non-finite imported velocity"; return HS_ERR_NUMERIC; }
             if (d < cs.dim) {
@@ -1208,7 +1220,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     const int dmax = s->plan.dim_max;
     std::vector<std::vector<char>> arrs(6);
     std::vector<int32_t> ncell;
-    std::vector<int64_t> nid;
+    std::vector<uint32_t> nid;                 // ids as stored: their low 32 bits
     for (int k = 0; k < ncase; ++k) {
         const CaseDev &ck = s->plan.cases[k];
         if (k == c) {
@@ -1224,7 +1236,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
             }
             for (size_t i = 0; i < np; ++i) {
                 ncell.push_back(cell[i] + ck.cell0);
-                nid.push_back(ids[i]);
+                nid.push_back((uint32_t)ids[i]);
             }
         } else {
             const int32_t a = cst[ck.cell0], b = cst[ck.cell0 + ck.ncells];
@@ -1244,7 +1256,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
             nid.resize(at + m);
             if (m) {
                 HIPCHK(s, hipMemcpy(ncell.data() + at, Bo.cell + a, 4 * m, hipMemcpyDeviceToHost));
-                HIPCHK(s, hipMemcpy(nid.data() + at, Bo.id + a, 8 * m, hipMemcpyDeviceToHost));
+                HIPCHK(s, hipMemcpy(nid.data() + at, Bo.id + a, 4 * m, hipMemcpyDeviceToHost));
             }
         }
     }
@@ -1256,7 +1268,7 @@ hs_status hs_import_state(hs_sim *s, int c, const void *host_buf, size_t bytes)
     }
     if (total) {
         HIPCHK(s, hipMemcpy(Bn.cell, ncell.data(), 4 * total, hipMemcpyHostToDevice));
-        HIPCHK(s, hipMemcpy(Bn.id, nid.data(), 8 * total, hipMemcpyHostToDevice));
+        HIPCHK(s, hipMemcpy(Bn.id, nid.data(), 4 * total, hipMemcpyHostToDevice));
     }
     std::vector<int32_t> cnt((size_t)s->plan.ncells + 1, 0);
     for (size_t i = 0; i < total; ++i) cnt[(size_t)ncell[i] + 1]++;

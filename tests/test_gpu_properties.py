@@ -497,3 +497,60 @@ def test_time_averages_within_three_standard_errors(gas, prec):
         assert (z ** 2).mean() < 2.0, (k, (z ** 2).mean())
         assert (abs(z) > 4).mean() < 0.01, (k, (abs(z) > 4).mean())
     print(prec, "; ".join(report))
+
+
+def test_ids_across_a_two_to_the_32_boundary(gas):
+    """The device keeps a particle id's low 32 bits and restores the full id from the case's
+    next id.  States whose ids straddle 2^40 (a multiple of 2^32: their low bits wrap): the
+    0-D batch, whose Shakhov draws are keyed by the ids, and the small cylinder, whose inflow
+    continues the ids across the boundary and whose wall reflections draw by id, both step for
+    step equal to the FP64 oracle (ids exact, cells exact, velocities 1e-12); an id outside
+    the last 2^32 below next_id is refused on import."""
+    from oracle.oracle import Oracle
+    from paper_2506_23917_amd.hs import HsError
+    from test_gpu_parity import _compare, _compare_trace
+    base = (1 << 40) - 700
+    # 0-D batch
+    case = W.relax_0d(ncells=32, ppc=400, n_steady=0)
+    case["dt_over_tau"] = np.linspace(0.2, 3.0, 32)
+    v, cell, ids = W.relax_0d_state(case, ppc=400)
+    ids = ids.astype(np.int64) + base
+    nxt = int(ids.max()) + 1
+    ora = Oracle(gas, case, trace=True)
+    ora.set_state(0, None, v, cell, ids, nxt, 0)
+    sim = _sim(gas, case, precision="fp64", trace=True, no_particles=True)
+    sim.import_state(0, dict(pos=np.zeros((len(ids), 3)), vel=v, cell=cell, id=ids, next_id=nxt, step=0,
+                             sigc_max=ora.get_cells(0)["sigc_max"]))
+    for _ in range(3):
+        sim.step(1)
+        ora.step(1)
+        _compare(gas, case, sim.export_state(0), ora.get_state(0), label="0-D ids past 2^40")
+        tr = sim.trace(0)
+        _compare_trace(tr, ora.trace(0), label="0-D ids past 2^40")
+    assert tr["nrelax"].sum() > 0
+    # cylinder with inflow: the state after a few steps, ids moved to straddle 2^40
+    case = _cyl()
+    s0 = _sim(gas, case, precision="fp64")
+    s0.step(4)
+    st = s0.export_state(0)
+    shift = base - int(st["id"].min()) + 300
+    st["id"] = st["id"] + shift
+    st["next_id"] = int(st["next_id"]) + shift
+    assert st["id"].min() < (1 << 40) <= st["next_id"]
+    sim = _sim(gas, case, precision="fp64", trace=True)
+    sim.import_state(0, st)
+    ora = Oracle(gas, case, trace=True)
+    ora.set_state(0, gpu_to_abs(case, st), st["vel"], st["cell"], st["id"], st["next_id"], st["step"])
+    ora.set_cells(0, st["sigc_max"], st["acc"], st["n_samples"])
+    for _ in range(3):
+        sim.step(1)
+        ora.step(1)
+        g = sim.export_state(0)
+        _compare(gas, case, g, ora.get_state(0), label="cylinder ids past 2^40")
+        _compare_trace(sim.trace(0), ora.trace(0), label="cylinder ids past 2^40")
+    assert g["id"].max() >= (1 << 40) and g["next_id"] > st["next_id"]
+    bad = dict(st)
+    bad["id"] = st["id"].copy()
+    bad["id"][0] = st["next_id"] - (1 << 32)
+    with pytest.raises(HsError):
+        _sim(gas, case, precision="fp64").import_state(0, bad)
